@@ -1,0 +1,181 @@
+/*
+ * fe_forms.h -- C ABI of the MI355X (gfx950) per-element weak-form library.
+ *
+ * The library evaluates multilinear finite element weak forms element by
+ * element and quadrature point by quadrature point, as in the paper's element
+ * loops (Algorithm "feloopv": residual/action; Algorithm "feloopm": element
+ * matrices) and its evaluation modes (section "Overview" of the weak form to
+ * einsum transpiler: 'residual', 'matrix', 'eval').  The forms are those of
+ * the table of example weak forms: vector dot product / mass ('i,i'), weak
+ * Laplacian ('0.i,0.i') and linear elasticity ('IK,s(i:j)->I,s(k:l)->K').
+ *
+ * Conventions (fixed by this library where the paper leaves them open):
+ *   - reference hexahedron [0,1]^3, tensor Gauss-Legendre rule with p+1
+ *     points per axis ((p+1)^3 points, as in the paper's cell/DOF table);
+ *     equispaced Lagrange basis of order p, isoparametric geometry;
+ *     local numbering a = i + (p+1)(j + (p+1)k), x fastest;
+ *   - reference tetrahedron {xi >= 0, xi_1+xi_2+xi_3 <= 1}, P1/P2 Lagrange
+ *     basis, vertices then edge nodes on edges (0,1),(1,2),(0,2),(0,3),(1,3),
+ *     (2,3); collapsed-coordinate Gauss-Jacobi rule, p+1 points per direction;
+ *   - the geometry step (Jacobian J, det J, J^-1, w_q det J, physical basis
+ *     gradients) is always computed in FP64 from FP64 node coordinates;
+ *   - vector unknowns are component-major inside an element: row/column index
+ *     r*n_basis + a (the reshape (j,k)->J below eq. fe1e); the global DOF
+ *     array is (n_nodes, n_comp) row-major;
+ *   - elasticity uses symmetric (Voigt) storage 11,22,33,12,13,23 with
+ *     engineering shear (the extractor of section "Linear Elasticity
+ *     Expression"), D is 6x6 in that order;
+ *   - det J <= 0 at any quadrature point is an error (reported by
+ *     fe_plan_check), never silently made positive.
+ *
+ * Ownership: every mesh, material, DOF, output and workspace buffer is a
+ * DEVICE pointer owned by the caller.  A plan owns only its device copy of the
+ * reference tables.  Nothing is allocated by fe_execute.  Calls enqueue work
+ * on the given HIP stream (a hipStream_t passed as void*, NULL = default
+ * stream) and return without synchronising, except fe_plan_check.
+ *
+ * Errors: every call returns an fe_status.  Host-side validation errors are
+ * returned synchronously and nothing is enqueued.  Faults found by the
+ * kernels (non-positive Jacobian, node index out of range) set sticky bits in
+ * the workspace that fe_plan_check reads and clears; an out-of-range node
+ * index is replaced by node 0 for the access so no kernel reads out of bounds.
+ * fe_last_error() gives a thread-local message for the last failure.
+ */
+#ifndef FE_FORMS_H
+#define FE_FORMS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FE_OK = 0,
+    FE_ERR_INVALID_ARG = 1,
+    FE_ERR_UNSUPPORTED = 2,
+    FE_ERR_NONPOSITIVE_JACOBIAN = 3,
+    FE_ERR_INDEX_OUT_OF_RANGE = 4,
+    FE_ERR_OUT_OF_MEMORY = 5,
+    FE_ERR_HIP = 6,
+    FE_ERR_NO_DEVICE = 7
+} fe_status;
+
+typedef enum { FE_CELL_HEX = 0, FE_CELL_TET = 1 } fe_cell;
+
+/* Forms of the table of example weak forms.  MASS: scalar 'i,i' with one
+ * component; VMASS: 'i,i' with three components (its matrix is D diagonal
+ * blocks of the scalar one, eq. fe3c); LAPLACE: '0.i,0.i';
+ * ELASTICITY: 'IK,s(i:j)->I,s(k:l)->K' with three components. */
+typedef enum {
+    FE_FORM_MASS = 0,
+    FE_FORM_VMASS = 1,
+    FE_FORM_LAPLACE = 2,
+    FE_FORM_ELASTICITY = 3
+} fe_form;
+
+/* MATRIX: element matrices (Algorithm "feloopm").  RESIDUAL: per-element
+ * action on DOFs gathered through the connectivity, unassembled (Algorithm
+ * "feloopv").  EVAL: per-element integral value u_e^T K_e u_e. */
+typedef enum { FE_MODE_MATRIX = 0, FE_MODE_RESIDUAL = 1, FE_MODE_EVAL = 2 } fe_mode;
+
+/* Arithmetic of the contraction.  The geometry step is FP64 in all three.
+ * FP64: everything FP64, outputs/material/DOFs FP64.
+ * FP32: contraction in FP32 (VALU or FP32 MFMA), FP32 outputs/material/DOFs.
+ * BF16X3: each FP32 operand split as hi = bf16(a), lo = bf16(a - hi); the
+ *         product is hi*hi + hi*lo + lo*hi on BF16 MFMA with FP32
+ *         accumulation; FP32 outputs/material/DOFs (matrix mode of the MFMA
+ *         kernels only). */
+typedef enum { FE_PREC_FP64 = 0, FE_PREC_FP32 = 1, FE_PREC_BF16X3 = 2 } fe_precision;
+
+/* Material data layout (elasticity only; NONE for mass and Laplace):
+ * ISO_CELL [n_cells][2] (lambda, mu); ISO_QP [n_cells][n_qp][2];
+ * VOIGT_QP [n_cells][n_qp][6][6] (the per-quadrature-point D of the paper's
+ * elasticity einsum, 'cqIK').  FP64 in FP64 mode, FP32 otherwise. */
+typedef enum {
+    FE_MAT_NONE = 0,
+    FE_MAT_ISO_CELL = 1,
+    FE_MAT_ISO_QP = 2,
+    FE_MAT_VOIGT_QP = 3
+} fe_material_kind;
+
+/* Kernel variant (0 = automatic choice). */
+typedef enum {
+    FE_VARIANT_AUTO = 0,
+    FE_VARIANT_GENERIC = 1,   /* reference-table VALU kernel, any cell/order */
+    FE_VARIANT_MFMA = 2,      /* matrix mode: per-element GEMM on matrix cores */
+    FE_VARIANT_SUMFACT = 3,   /* hex residual/eval: sum-factorized, gradient-first */
+    FE_VARIANT_MATRIX_FIRST = 4 /* residual: form K_e then K_e u_e */
+} fe_variant;
+
+typedef struct {
+    int variant;      /* fe_variant */
+    int block;        /* threads per workgroup hint, 0 = default */
+    int elems;        /* elements per workgroup hint, 0 = default */
+    int xcd_remap;    /* 1 = map contiguous element ranges to one XCD (default), 0 = off, -1 = default */
+} fe_options;
+
+typedef struct fe_plan_s *fe_plan;
+
+/* Status name, e.g. "FE_ERR_INVALID_ARG". Never NULL. */
+const char *fe_status_string(int status);
+/* Thread-local detail message of the last failing call on this thread. */
+const char *fe_last_error(void);
+/* Library version string. */
+const char *fe_version(void);
+
+/* Number of basis functions and quadrature points of a reference element
+ * (section "Notation": basis phi_k on the reference element, quadrature
+ * points xi).  Host only. */
+int fe_reference_sizes(int cell, int order, int *n_basis, int *n_qp);
+
+/* The library's reference tables, written to HOST arrays of the caller:
+ * weights[n_qp], points[n_qp][3], bf[n_qp][n_basis] (phi_a(xi_q)),
+ * bfg[n_qp][3][n_basis] (d phi_a / d xi_j at xi_q).  Any pointer may be NULL.
+ * Host only, no device needed. */
+int fe_reference_tables(int cell, int order, double *weights, double *points,
+                        double *bf, double *bfg);
+
+/* Create a plan for one (cell, order, form, mode, precision, material kind)
+ * on the current HIP device: builds the reference tables and copies them to
+ * the device.  opts may be NULL. */
+int fe_plan_create(int cell, int order, int form, int mode, int precision,
+                   int material_kind, const fe_options *opts, fe_plan *out);
+
+/* Plan facts: n_basis, n_qp, n_comp (1 or 3), the chosen variant and the
+ * element matrix/vector row count n_comp*n_basis.  Any pointer may be NULL. */
+int fe_plan_info(fe_plan plan, int *n_basis, int *n_qp, int *n_comp,
+                 int *variant, int *n_dof);
+
+/* Bytes of device workspace fe_execute needs for n_cells cells.  The
+ * workspace holds the sticky fault bits (first 256 bytes); it must be
+ * zero-filled once before first use and is cleared by fe_plan_check. */
+int fe_plan_workspace_size(fe_plan plan, int64_t n_cells, size_t *bytes);
+
+/* Evaluate the plan's form on n_cells cells.
+ *   coords [n_nodes][3] FP64        node coordinates
+ *   conn   [n_cells][n_basis] int32 local-to-global node numbers
+ *   material                        layout by the plan's material kind, or NULL
+ *   dofs   [n_nodes][n_comp]        RESIDUAL/EVAL only (NULL in MATRIX mode)
+ *   out    MATRIX   [n_cells][n_dof][n_dof]
+ *          RESIDUAL [n_cells][n_comp][n_basis]
+ *          EVAL     [n_cells]
+ * Element types follow the plan's precision (FP64 or FP32); coords are FP64
+ * always.  All pointers are device pointers.  Asynchronous on `stream`. */
+int fe_execute(fe_plan plan, int64_t n_cells, int64_t n_nodes,
+               const double *coords, const int32_t *conn, const void *material,
+               const void *dofs, void *out, void *workspace,
+               size_t workspace_bytes, void *stream);
+
+/* Synchronise `stream`, read and clear the workspace fault bits.  Returns
+ * FE_ERR_INDEX_OUT_OF_RANGE or FE_ERR_NONPOSITIVE_JACOBIAN if a kernel saw
+ * one since the last check, FE_OK otherwise. */
+int fe_plan_check(fe_plan plan, void *workspace, void *stream);
+
+int fe_plan_destroy(fe_plan plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FE_FORMS_H */

@@ -1,0 +1,169 @@
+"""MI355X (gfx950) per-element finite element weak-form evaluation.
+
+Python face of libfe_forms.so: plans for (cell, order, form, mode, precision,
+material kind) and their execution on device tensors.  PyTorch provides the
+device memory and the stream; the evaluation itself (gather, FP64 geometry,
+contraction, output) runs in the library's HIP kernels.
+
+    plan = Plan("hex", 2, "elasticity", "matrix", "fp64", material="iso_cell")
+    K = plan(coords, conn, material=lam_mu)     # (n_cells, 81, 81) on cuda
+    plan.check()                                # raises on det J <= 0 etc.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import FeError
+
+__all__ = ["Plan", "FeError", "reference_sizes", "reference_tables",
+           "n_comp"]
+
+_TORCH_DT = {"fp64": "float64", "fp32": "float32", "bf16x3": "float32"}
+
+
+def n_comp(form: str) -> int:
+    return 3 if form in ("vmass", "elasticity") else 1
+
+
+def reference_sizes(cell: str, order: int):
+    nb, nq = ctypes.c_int(), ctypes.c_int()
+    _lib.check(_lib.lib().fe_reference_sizes(_lib.CELLS[cell], order,
+                                             ctypes.byref(nb),
+                                             ctypes.byref(nq)),
+               "fe_reference_sizes")
+    return nb.value, nq.value
+
+
+def reference_tables(cell: str, order: int):
+    """The library's own (w[nq], pts[nq,3], bf[nq,nb], bfg[nq,3,nb])."""
+    nb, nq = reference_sizes(cell, order)
+    w, pts = np.zeros(nq), np.zeros((nq, 3))
+    bf, bfg = np.zeros((nq, nb)), np.zeros((nq, 3, nb))
+    dp = ctypes.POINTER(ctypes.c_double)
+    _lib.check(_lib.lib().fe_reference_tables(
+        _lib.CELLS[cell], order, w.ctypes.data_as(dp),
+        pts.ctypes.data_as(dp), bf.ctypes.data_as(dp),
+        bfg.ctypes.data_as(dp)), "fe_reference_tables")
+    return w, pts, bf, bfg
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """One compiled evaluation: cell kind/order, form, mode, precision and
+    material layout.  Calls are asynchronous on the current torch stream."""
+
+    def __init__(self, cell: str, order: int, form: str, mode: str = "matrix",
+                 precision: str = "fp64", material: str | None = None,
+                 variant: str = "auto", xcd_remap: bool = True):
+        self.cell, self.order, self.form = cell, int(order), form
+        self.mode, self.precision, self.material = mode, precision, material
+        opts = _lib.fe_options(_lib.VARIANTS[variant], 0, 0,
+                               1 if xcd_remap else 0)
+        h = ctypes.c_void_p()
+        L = _lib.lib()
+        _lib.check(L.fe_plan_create(_lib.CELLS[cell], self.order,
+                                    _lib.FORMS[form], _lib.MODES[mode],
+                                    _lib.PRECS[precision],
+                                    _lib.MATS[material], ctypes.byref(opts),
+                                    ctypes.byref(h)), "fe_plan_create")
+        self._h = h
+        ints = [ctypes.c_int() for _ in range(5)]
+        _lib.check(L.fe_plan_info(h, *[ctypes.byref(i) for i in ints]),
+                   "fe_plan_info")
+        self.n_basis, self.n_qp, self.n_comp, v, self.n_dof = (
+            i.value for i in ints)
+        self.variant = _lib.VARIANT_NAMES[v]
+        self._ws = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib._lib is not None:
+            _lib._lib.fe_plan_destroy(h)
+            self._h = None
+
+    @property
+    def dtype(self):
+        import torch
+        return getattr(torch, _TORCH_DT[self.precision])
+
+    def workspace_bytes(self, n_cells: int) -> int:
+        b = ctypes.c_size_t()
+        _lib.check(_lib.lib().fe_plan_workspace_size(self._h, n_cells,
+                                                     ctypes.byref(b)),
+                   "fe_plan_workspace_size")
+        return b.value
+
+    def workspace(self, n_cells: int, device=None):
+        """A zero-filled device workspace large enough for n_cells (reused
+        between calls of this plan)."""
+        import torch
+        need = self.workspace_bytes(n_cells)
+        if self._ws is None or self._ws.numel() < need or (
+                device is not None and self._ws.device != device):
+            self._ws = torch.zeros(need, dtype=torch.uint8,
+                                   device=device or "cuda")
+        return self._ws
+
+    def out_shape(self, n_cells: int):
+        if self.mode == "matrix":
+            return (n_cells, self.n_dof, self.n_dof)
+        if self.mode == "residual":
+            return (n_cells, self.n_comp, self.n_basis)
+        return (n_cells,)
+
+    def __call__(self, coords, conn, material=None, dofs=None, out=None,
+                 workspace=None, stream=None):
+        import torch
+        n_cells, nb = conn.shape
+        if nb != self.n_basis:
+            raise ValueError(f"conn has {nb} columns, plan needs "
+                             f"{self.n_basis}")
+        if coords.dtype != torch.float64 or coords.dim() != 2 or \
+                coords.shape[1] != 3:
+            raise ValueError("coords must be (n_nodes, 3) float64")
+        if conn.dtype != torch.int32:
+            raise ValueError("conn must be int32")
+        for name, t in (("coords", coords), ("conn", conn),
+                        ("material", material), ("dofs", dofs)):
+            if t is not None and (not t.is_cuda or not t.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous cuda tensor")
+        dt = self.dtype
+        if material is not None and material.dtype != dt:
+            raise ValueError(f"material must be {dt}")
+        if dofs is not None and dofs.dtype != dt:
+            raise ValueError(f"dofs must be {dt}")
+        if out is None:
+            out = torch.empty(self.out_shape(n_cells), dtype=dt,
+                              device=coords.device)
+        elif (tuple(out.shape) != self.out_shape(n_cells) or out.dtype != dt
+              or not out.is_contiguous()):
+            raise ValueError("out has the wrong shape/dtype/layout")
+        ws = workspace if workspace is not None else self.workspace(
+            n_cells, coords.device)
+        _lib.check(_lib.lib().fe_execute(
+            self._h, n_cells, coords.shape[0], _ptr(coords), _ptr(conn),
+            _ptr(material), _ptr(dofs), _ptr(out), _ptr(ws), ws.numel(),
+            _stream_handle(stream)), "fe_execute")
+        return out
+
+    def check(self, workspace=None, stream=None):
+        """Synchronise and raise FeError if a kernel saw det J <= 0 or an
+        out-of-range node number since the last check."""
+        ws = workspace if workspace is not None else self._ws
+        if ws is None:
+            return
+        _lib.check(_lib.lib().fe_plan_check(self._h, _ptr(ws),
+                                            _stream_handle(stream)),
+                   "fe_plan_check")

@@ -1,0 +1,262 @@
+// C ABI of the gfx950 weak-form library: plans, validation, dispatch.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "fe_internal.h"
+
+struct fe_plan_s : fe::Plan {};
+
+namespace fe {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+int n_comp_of(int form) { return (form == FE_FORM_VMASS || form == FE_FORM_ELASTICITY) ? 3 : 1; }
+
+LaunchFn select_generic_f64(const Plan &p);
+LaunchFn select_generic_f32(const Plan &p);
+
+LaunchFn select_generic(const Plan &p)
+{
+    if (p.prec == FE_PREC_FP64) return select_generic_f64(p);
+    if (p.prec == FE_PREC_FP32) return select_generic_f32(p);
+    return nullptr;
+}
+
+static int fail(int status, const std::string &msg)
+{
+    set_error(msg);
+    return status;
+}
+
+static constexpr size_t FLAG_BYTES = 256;
+
+}  // namespace fe
+
+using namespace fe;
+
+extern "C" {
+
+const char *fe_status_string(int s)
+{
+    switch (s) {
+    case FE_OK: return "FE_OK";
+    case FE_ERR_INVALID_ARG: return "FE_ERR_INVALID_ARG";
+    case FE_ERR_UNSUPPORTED: return "FE_ERR_UNSUPPORTED";
+    case FE_ERR_NONPOSITIVE_JACOBIAN: return "FE_ERR_NONPOSITIVE_JACOBIAN";
+    case FE_ERR_INDEX_OUT_OF_RANGE: return "FE_ERR_INDEX_OUT_OF_RANGE";
+    case FE_ERR_OUT_OF_MEMORY: return "FE_ERR_OUT_OF_MEMORY";
+    case FE_ERR_HIP: return "FE_ERR_HIP";
+    case FE_ERR_NO_DEVICE: return "FE_ERR_NO_DEVICE";
+    }
+    return "FE_ERR_UNKNOWN";
+}
+
+const char *fe_last_error(void) { return g_last_error.c_str(); }
+
+const char *fe_version(void) { return "fe_forms 0.1 (gfx950)"; }
+
+int fe_reference_sizes(int cell, int order, int *n_basis, int *n_qp)
+{
+    int nb, nq;
+    int st = reference_sizes(cell, order, &nb, &nq);
+    if (st) return fail(st, "unsupported cell/order");
+    if (n_basis) *n_basis = nb;
+    if (n_qp) *n_qp = nq;
+    return FE_OK;
+}
+
+int fe_reference_tables(int cell, int order, double *weights, double *points, double *bf, double *bfg)
+{
+    RefTables T;
+    int st = reference_tables(cell, order, T);
+    if (st) return fail(st, "unsupported cell/order");
+    if (weights) std::memcpy(weights, T.w.data(), T.w.size() * sizeof(double));
+    if (points) std::memcpy(points, T.pts.data(), T.pts.size() * sizeof(double));
+    if (bf) std::memcpy(bf, T.bf.data(), T.bf.size() * sizeof(double));
+    if (bfg) std::memcpy(bfg, T.bfg.data(), T.bfg.size() * sizeof(double));
+    return FE_OK;
+}
+
+int fe_plan_create(int cell, int order, int form, int mode, int precision, int material_kind,
+                   const fe_options *opts, fe_plan *out)
+{
+    if (!out) return fail(FE_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (cell != FE_CELL_HEX && cell != FE_CELL_TET) return fail(FE_ERR_INVALID_ARG, "bad cell");
+    if (form < FE_FORM_MASS || form > FE_FORM_ELASTICITY) return fail(FE_ERR_INVALID_ARG, "bad form");
+    if (mode < FE_MODE_MATRIX || mode > FE_MODE_EVAL) return fail(FE_ERR_INVALID_ARG, "bad mode");
+    if (precision < FE_PREC_FP64 || precision > FE_PREC_BF16X3) return fail(FE_ERR_INVALID_ARG, "bad precision");
+    if (form == FE_FORM_ELASTICITY) {
+        if (material_kind < FE_MAT_ISO_CELL || material_kind > FE_MAT_VOIGT_QP)
+            return fail(FE_ERR_INVALID_ARG, "elasticity needs a material kind");
+    } else if (material_kind != FE_MAT_NONE) {
+        return fail(FE_ERR_INVALID_ARG, "only elasticity takes a material");
+    }
+    int nb, nq;
+    if (reference_sizes(cell, order, &nb, &nq)) return fail(FE_ERR_UNSUPPORTED, "unsupported cell/order");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) {
+        (void)hipGetLastError();
+        return fail(FE_ERR_NO_DEVICE, "no HIP device");
+    }
+    fe_plan_s *p = new (std::nothrow) fe_plan_s();
+    if (!p) return fail(FE_ERR_OUT_OF_MEMORY, "host allocation failed");
+    p->cell = cell;
+    p->order = order;
+    p->form = form;
+    p->mode = mode;
+    p->prec = precision;
+    p->mat_kind = material_kind;
+    p->nb = nb;
+    p->nq = nq;
+    p->nc = n_comp_of(form);
+    p->device = dev;
+    if (opts) p->opts = *opts;
+    else {
+        p->opts.variant = FE_VARIANT_AUTO;
+        p->opts.xcd_remap = -1;
+    }
+    if (reference_tables(cell, order, p->ref)) {
+        delete p;
+        return fail(FE_ERR_UNSUPPORTED, "reference tables");
+    }
+    // kernel choice
+    const int want = p->opts.variant;
+    LaunchFn fn = nullptr;
+    int variant = FE_VARIANT_GENERIC;
+    if (want == FE_VARIANT_AUTO || want == FE_VARIANT_MFMA) {
+        if (mode == FE_MODE_MATRIX && (fn = select_mfma(*p))) variant = FE_VARIANT_MFMA;
+    }
+    if (!fn && (want == FE_VARIANT_AUTO || want == FE_VARIANT_SUMFACT)) {
+        if (mode != FE_MODE_MATRIX && (fn = select_sumfact(*p))) variant = FE_VARIANT_SUMFACT;
+    }
+    if (!fn && (want == FE_VARIANT_AUTO || want == FE_VARIANT_GENERIC)) {
+        if ((fn = select_generic(*p))) variant = FE_VARIANT_GENERIC;
+    }
+    if (!fn) {
+        delete p;
+        return fail(FE_ERR_UNSUPPORTED, "no kernel for this cell/order/form/mode/precision/variant");
+    }
+    p->launch = fn;
+    p->variant = variant;
+    // device tables: w | bf | bfgT | B1 | D1
+    const int n1 = (cell == FE_CELL_HEX) ? (order + 1) * (order + 1) : 0;
+    const size_t nwords = nq + (size_t)nq * nb + (size_t)nb * 3 * nq + 2 * n1;
+    std::vector<double> h(nwords, 0.0);
+    double *w = h.data(), *bf = w + nq, *bfgT = bf + (size_t)nq * nb, *B1 = bfgT + (size_t)nb * 3 * nq,
+           *D1 = B1 + n1;
+    for (int q = 0; q < nq; q++) {
+        w[q] = p->ref.w[q];
+        for (int a = 0; a < nb; a++) {
+            bf[(size_t)q * nb + a] = p->ref.bf[(size_t)q * nb + a];
+            for (int j = 0; j < 3; j++) bfgT[((size_t)a * 3 + j) * nq + q] = p->ref.bfg[((size_t)q * 3 + j) * nb + a];
+        }
+    }
+    for (int i = 0; i < n1; i++) {
+        B1[i] = p->ref.B1[i];
+        D1[i] = p->ref.D1[i];
+    }
+    if (hipMalloc(&p->d_tab, nwords * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        delete p;
+        return fail(FE_ERR_OUT_OF_MEMORY, "device table allocation failed");
+    }
+    if (hipMemcpy(p->d_tab, h.data(), nwords * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(p->d_tab);
+        delete p;
+        return fail(FE_ERR_HIP, "device table copy failed");
+    }
+    p->tab.w = p->d_tab;
+    p->tab.bf = p->d_tab + (bf - w);
+    p->tab.bfgT = p->d_tab + (bfgT - w);
+    p->tab.B1 = p->d_tab + (B1 - w);
+    p->tab.D1 = p->d_tab + (D1 - w);
+    *out = p;
+    return FE_OK;
+}
+
+int fe_plan_info(fe_plan p, int *n_basis, int *n_qp, int *n_comp, int *variant, int *n_dof)
+{
+    if (!p) return fail(FE_ERR_INVALID_ARG, "plan is NULL");
+    if (n_basis) *n_basis = p->nb;
+    if (n_qp) *n_qp = p->nq;
+    if (n_comp) *n_comp = p->nc;
+    if (variant) *variant = p->variant;
+    if (n_dof) *n_dof = p->nc * p->nb;
+    return FE_OK;
+}
+
+int fe_plan_workspace_size(fe_plan p, int64_t n_cells, size_t *bytes)
+{
+    if (!p || !bytes || n_cells < 0) return fail(FE_ERR_INVALID_ARG, "bad argument");
+    *bytes = FLAG_BYTES;
+    return FE_OK;
+}
+
+int fe_execute(fe_plan p, int64_t n_cells, int64_t n_nodes, const double *coords, const int32_t *conn,
+               const void *material, const void *dofs, void *out, void *workspace, size_t workspace_bytes,
+               void *stream)
+{
+    if (!p) return fail(FE_ERR_INVALID_ARG, "plan is NULL");
+    if (n_cells < 0 || n_nodes < 0) return fail(FE_ERR_INVALID_ARG, "negative size");
+    if (n_cells == 0) return FE_OK;
+    if (n_nodes == 0) return fail(FE_ERR_INVALID_ARG, "cells without nodes");
+    if (!coords || !conn || !out) return fail(FE_ERR_INVALID_ARG, "coords/conn/out is NULL");
+    if (p->form == FE_FORM_ELASTICITY && !material) return fail(FE_ERR_INVALID_ARG, "material is NULL");
+    if (p->mode != FE_MODE_MATRIX && !dofs) return fail(FE_ERR_INVALID_ARG, "dofs is NULL");
+    size_t need;
+    fe_plan_workspace_size(p, n_cells, &need);
+    if (!workspace || workspace_bytes < need) return fail(FE_ERR_INVALID_ARG, "workspace too small");
+    if (n_nodes > 0x7fffffffLL) return fail(FE_ERR_INVALID_ARG, "n_nodes exceeds int32 node numbers");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
+        return fail(FE_ERR_INVALID_ARG, "plan was created on another device");
+    ExecArgs A{};
+    A.n_cells = n_cells;
+    A.n_nodes = n_nodes;
+    A.coords = coords;
+    A.conn = conn;
+    A.mat = material;
+    A.mat_kind = p->mat_kind;
+    A.dofs = dofs;
+    A.out = out;
+    A.flags = static_cast<unsigned *>(workspace);
+    A.tab = p->tab;
+    A.xcd_remap = p->opts.xcd_remap == 0 ? 0 : 1;
+    A.eval = p->mode == FE_MODE_EVAL ? 1 : 0;
+    return p->launch(*p, A, static_cast<hipStream_t>(stream));
+}
+
+int fe_plan_check(fe_plan p, void *workspace, void *stream)
+{
+    if (!p || !workspace) return fail(FE_ERR_INVALID_ARG, "bad argument");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    unsigned flags = 0;
+    FE_HIP_CHECK(hipMemcpyAsync(&flags, workspace, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+    FE_HIP_CHECK(hipStreamSynchronize(st));
+    if (flags) {
+        const unsigned zero = 0;
+        FE_HIP_CHECK(hipMemcpyAsync(workspace, &zero, sizeof(unsigned), hipMemcpyHostToDevice, st));
+        FE_HIP_CHECK(hipStreamSynchronize(st));
+    }
+    if (flags & FAULT_INDEX) return fail(FE_ERR_INDEX_OUT_OF_RANGE, "a connectivity entry is out of range");
+    if (flags & FAULT_DET) return fail(FE_ERR_NONPOSITIVE_JACOBIAN, "det J <= 0 at a quadrature point");
+    return FE_OK;
+}
+
+int fe_plan_destroy(fe_plan p)
+{
+    if (!p) return FE_OK;
+    if (p->d_tab) (void)hipFree(p->d_tab);
+    delete p;
+    return FE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,81 @@
+// Internal declarations of the gfx950 weak-form library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fe_forms.h"
+
+namespace fe {
+
+struct RefTables {
+    int cell = 0, order = 0, nb = 0, nq = 0;
+    std::vector<double> w, pts, bf, bfg;  // bf [nq][nb], bfg [nq][3][nb]
+    std::vector<double> s1, w1, B1, D1;   // hex only: 1-D rule and basis [q][k]
+};
+
+int reference_sizes(int cell, int order, int *nb, int *nq);
+int reference_tables(int cell, int order, RefTables &T);
+
+// Device copy of the tables, laid out for the kernels:
+//   w[nq] | bf[nq][nb] | bfgT[nb][3][nq] | B1[n][n] | D1[n][n]   (FP64)
+struct DevTables {
+    const double *w, *bf, *bfgT, *B1, *D1;
+};
+
+// Fault bits written by kernels into the first word of the workspace.
+enum : unsigned { FAULT_DET = 1u, FAULT_INDEX = 2u };
+
+// Everything a launcher needs for one fe_execute call.
+struct ExecArgs {
+    int64_t n_cells, n_nodes;
+    const double *coords;
+    const int32_t *conn;
+    const void *mat;
+    int mat_kind;
+    const void *dofs;
+    void *out;
+    unsigned *flags;
+    DevTables tab;
+    int xcd_remap;
+    int eval;  // residual-family kernels: 1 = write per-element energy
+};
+
+struct Plan;
+using LaunchFn = int (*)(const Plan &, const ExecArgs &, hipStream_t);
+
+struct Plan {
+    int cell, order, form, mode, prec, mat_kind, variant;
+    int nb, nq, nc;
+    int device;
+    RefTables ref;
+    double *d_tab = nullptr;
+    DevTables tab{};
+    LaunchFn launch = nullptr;
+    fe_options opts{};
+};
+
+// thread-local error message
+void set_error(const std::string &msg);
+
+#define FE_HIP_CHECK(call)                                                     \
+    do {                                                                       \
+        hipError_t _e = (call);                                                \
+        if (_e != hipSuccess) {                                                \
+            ::fe::set_error(std::string(#call) + ": " + hipGetErrorString(_e)); \
+            return FE_ERR_HIP;                                                 \
+        }                                                                      \
+    } while (0)
+
+// Kernel family selectors; each returns nullptr when it has no kernel for the
+// plan (the caller then tries the next family).
+LaunchFn select_generic(const Plan &p);
+LaunchFn select_mfma(const Plan &p);
+LaunchFn select_sumfact(const Plan &p);
+
+int n_comp_of(int form);
+
+}  // namespace fe
