@@ -155,3 +155,26 @@ def test_repeatable_bitwise(orc):
     b = plan(_t(mesh.coords), _t(mesh.conn), material=_t(lm))
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("variant", ["auto", "generic"])
+def test_elasticity_q2_variants(orc, prec, variant):
+    """Q2 elasticity matrices with per-cell coefficients: the matrix-core
+    kernel (auto) and the generic kernel, every precision, on a curved mesh
+    whose cell count leaves a ragged tail across the 8 XCD ranges."""
+    import paper_2107_04121_amd as fe
+    if variant == "generic" and prec == "bf16x3":
+        pytest.skip("bf16x3 exists only on the matrix-core path")
+    mesh = meshgen.hex_mesh((7, 5, 3), 2, alpha=0.15, seed=11, curved=0.04)
+    lm = meshgen.lame_cell(mesh.n_cells, seed=12)
+    ref = orc.matrix(mesh, "elasticity", lm, "iso_cell")
+    plan = fe.Plan("hex", 2, "elasticity", "matrix", prec,
+                   material="iso_cell", variant=variant)
+    assert plan.variant == ("mfma" if variant == "auto" else "generic")
+    print(f"[parity] q2 elasticity {prec} {plan.variant}", flush=True)
+    out = plan(_t(mesh.coords), _t(mesh.conn), material=_t(lm, plan.dtype))
+    plan.check()
+    err = elem_rel_err(out.cpu().numpy(), ref)
+    print(f"[parity] max rel err {err:.3e}", flush=True)
+    assert err < TOL[prec], err
