@@ -41,6 +41,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true",
                     help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-calibration", type=float, default=0.0,
+                    help="GiB copied by one torch copy before the run (a "
+                    "plain copy kernel of known size, used to scale HBM "
+                    "byte counters)")
     return ap.parse_args()
 
 
@@ -135,6 +139,13 @@ def main():
     import paper_2107_04121_amd as fe
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration > 0:
+        nbytes = int(args.copy_calibration * 2**30)
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     n = args.n
     mesh = meshgen.hex_mesh(n, 2, alpha=0.15, seed=0)
     lm = meshgen.lame_cell(mesh.n_cells, seed=0)
