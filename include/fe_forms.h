@@ -175,6 +175,56 @@ int fe_plan_check(fe_plan plan, void *workspace, void *stream);
 
 int fe_plan_destroy(fe_plan plan);
 
+/* ---- node incidence, assembly and the adjoint of the eval mode ---------- */
+
+typedef struct fe_incidence_s *fe_incidence;
+
+/* Node-to-(cell, local node) incidence of a connectivity, in CSR form, built
+ * on the current device (the gather step behind assembly and the coordinate
+ * gradient).  Entries of each node are sorted by cell*n_basis + a, so every
+ * sum over them has a fixed order and the results are bitwise repeatable.
+ *   conn [n_cells][n_basis] int32, device; entries must lie in [0, n_nodes)
+ *   (FE_ERR_INDEX_OUT_OF_RANGE otherwise).  Synchronises `stream`.  The
+ *   handle owns its device arrays (allocated here, freed by
+ *   fe_incidence_destroy). */
+int fe_incidence_create(int64_t n_cells, int64_t n_nodes, int n_basis, const int32_t *conn,
+                        void *stream, fe_incidence *out);
+int fe_incidence_destroy(fe_incidence inc);
+
+/* Assembly of per-cell vectors into nodal ones (the global residual the
+ * paper leaves out of its timings, Algorithm "feloopv" returns the cell
+ * parts):  out[n][c] = scale * sum over (e,a) with conn[e][a] = n of
+ * cell_vec[e][c][a].
+ *   cell_vec [n_cells][n_comp][n_basis], out [n_nodes][n_comp], both device,
+ *   FP64 when precision == FE_PREC_FP64, FP32 otherwise; out is
+ *   overwritten.  Asynchronous. */
+int fe_assemble(fe_incidence inc, int n_comp, int precision, const void *cell_vec, double scale,
+                void *out, void *stream);
+
+/* Gradient of the eval-mode value of linear elasticity,
+ *   J(c, x) = sum_e u_e^T K_e(c, x) u_e
+ * (eval mode of the elasticity form; the derivative rules below follow from
+ * differentiating the quadrature sum, as the paper differentiates forms with
+ * respect to the DOFs), with respect to the material coefficients and the
+ * node coordinates, recomputing the geometry (nothing is stored between the
+ * forward and the backward pass):
+ *   dJ/dlambda_{e,q} = w det J (tr eps)^2,   dJ/dmu_{e,q} = 2 w det J eps:eps,
+ *   dJ/dx_n = sum_{(e,a): conn[e][a]=n} sum_q w det J
+ *             sum_l (W delta_kl - 2 (H^T sigma)_kl) dphi_a/dx_l
+ *   with H = grad u, sigma = lambda tr(eps) I + 2 mu eps, W = eps:sigma.
+ * The plan must be ELASTICITY / EVAL with material ISO_QP or ISO_CELL.
+ *   grad_material: [n_cells][n_qp][2] (ISO_QP) or [n_cells][2] (ISO_CELL),
+ *                  plan precision, overwritten, or NULL;
+ *   grad_coords:   [n_nodes][3] FP64, overwritten, or NULL (needs inc);
+ *   scale multiplies both (the incoming gradient of a scalar loss).
+ * The workspace must hold fe_energy_grad_workspace_size() bytes, the first
+ * 256 of which are the fault bits of fe_plan_check.  Asynchronous. */
+int fe_energy_grad_workspace_size(fe_plan plan, int64_t n_cells, size_t *bytes);
+int fe_energy_grad(fe_plan plan, fe_incidence inc, int64_t n_cells, int64_t n_nodes, const double *coords,
+                   const int32_t *conn, const void *material, const void *dofs, double scale,
+                   void *grad_material, double *grad_coords, void *workspace, size_t workspace_bytes,
+                   void *stream);
+
 #ifdef __cplusplus
 }
 #endif

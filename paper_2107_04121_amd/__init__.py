@@ -18,8 +18,8 @@ import numpy as np
 from . import _lib
 from ._lib import FeError
 
-__all__ = ["Plan", "FeError", "reference_sizes", "reference_tables",
-           "n_comp"]
+__all__ = ["Plan", "FeError", "Incidence", "assemble", "reference_sizes",
+           "reference_tables", "n_comp", "ElasticEnergy"]
 
 _TORCH_DT = {"fp64": "float64", "fp32": "float32", "bf16x3": "float32"}
 
@@ -167,3 +167,128 @@ class Plan:
         _lib.check(_lib.lib().fe_plan_check(self._h, _ptr(ws),
                                             _stream_handle(stream)),
                    "fe_plan_check")
+
+
+class Incidence:
+    """Node-to-(cell, local node) incidence of a connectivity (CSR, built on
+    the device, sorted so every gather over it has a fixed order)."""
+
+    def __init__(self, conn, n_nodes: int, stream=None):
+        if conn.dtype.__str__() != "torch.int32" or not conn.is_cuda or \
+                not conn.is_contiguous():
+            raise ValueError("conn must be a contiguous int32 cuda tensor")
+        self.n_cells, self.n_basis = conn.shape
+        self.n_nodes = int(n_nodes)
+        h = ctypes.c_void_p()
+        _lib.check(_lib.lib().fe_incidence_create(
+            self.n_cells, self.n_nodes, self.n_basis, _ptr(conn),
+            _stream_handle(stream), ctypes.byref(h)), "fe_incidence_create")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib._lib is not None:
+            _lib._lib.fe_incidence_destroy(h)
+            self._h = None
+
+
+def assemble(inc: Incidence, cell_vec, scale: float = 1.0, out=None,
+             stream=None):
+    """Sum per-cell vectors (n_cells, n_comp, n_basis) into nodal ones
+    (n_nodes, n_comp) through the incidence."""
+    import torch
+    n_cells, nc, nb = cell_vec.shape
+    if (n_cells, nb) != (inc.n_cells, inc.n_basis):
+        raise ValueError("cell_vec does not match the incidence")
+    if not cell_vec.is_contiguous():
+        raise ValueError("cell_vec must be contiguous")
+    prec = {torch.float64: 0, torch.float32: 1}[cell_vec.dtype]
+    if out is None:
+        out = torch.empty((inc.n_nodes, nc), dtype=cell_vec.dtype,
+                          device=cell_vec.device)
+    _lib.check(_lib.lib().fe_assemble(inc._h, nc, prec, _ptr(cell_vec),
+                                      float(scale), _ptr(out),
+                                      _stream_handle(stream)), "fe_assemble")
+    return out
+
+
+def _energy_grad(plan, inc, coords, conn, material, dofs, scale,
+                 want_mat=True, want_coords=True, stream=None):
+    """dJ/dc and dJ/dx of the elasticity eval value (see fe_energy_grad)."""
+    import torch
+    n_cells = conn.shape[0]
+    b = ctypes.c_size_t()
+    _lib.check(_lib.lib().fe_energy_grad_workspace_size(plan._h, n_cells,
+                                                        ctypes.byref(b)),
+               "fe_energy_grad_workspace_size")
+    ws = torch.zeros(b.value, dtype=torch.uint8, device=coords.device)
+    gm = torch.empty_like(material) if want_mat else None
+    gx = (torch.empty_like(coords) if want_coords else None)
+    _lib.check(_lib.lib().fe_energy_grad(
+        plan._h, inc._h if inc is not None else None, n_cells,
+        coords.shape[0], _ptr(coords), _ptr(conn), _ptr(material),
+        _ptr(dofs), float(scale), _ptr(gm), _ptr(gx), _ptr(ws), ws.numel(),
+        _stream_handle(stream)), "fe_energy_grad")
+    plan.check(ws, stream)
+    return gm, gx
+
+
+class ElasticEnergyPlan:
+    """Everything the elasticity energy J(c, x, u) = sum_e u_e^T K_e u_e
+    needs for one mesh topology: eval and residual plans and the incidence."""
+
+    def __init__(self, cell, order, conn, n_nodes, precision="fp64",
+                 material="iso_qp"):
+        self.conn = conn
+        self.n_nodes = int(n_nodes)
+        self.eval = Plan(cell, order, "elasticity", "eval", precision,
+                         material=material)
+        self.resid = Plan(cell, order, "elasticity", "residual", precision,
+                          material=material)
+        self.inc = Incidence(conn, n_nodes)
+
+
+def _make_energy_function():
+    import torch
+
+    class _ElasticEnergy(torch.autograd.Function):
+        """J = sum_e u_e^T K_e(c, x) u_e.  Backward: dJ/dc, dJ/dx from the
+        adjoint kernel (geometry recomputed), dJ/du = 2 * assembled
+        residual."""
+
+        @staticmethod
+        def forward(ctx, c, x, u, ep):
+            e = ep.eval(x, ep.conn, material=c, dofs=u)
+            ep.eval.check()
+            ctx.ep = ep
+            ctx.save_for_backward(c, x, u)
+            return e.sum()
+
+        @staticmethod
+        def backward(ctx, gJ):
+            c, x, u = ctx.saved_tensors
+            ep = ctx.ep
+            s = float(gJ)
+            gc = gx = gu = None
+            need_c, need_x, need_u = ctx.needs_input_grad[:3]
+            if need_c or need_x:
+                gc, gx = _energy_grad(ep.eval, ep.inc, x, ep.conn, c, u, s,
+                                      want_mat=need_c, want_coords=need_x)
+            if need_u:
+                r = ep.resid(x, ep.conn, material=c, dofs=u)
+                ep.resid.check()
+                gu = assemble(ep.inc, r, scale=2.0 * s)
+            return gc, gx, gu, None
+
+    return _ElasticEnergy
+
+
+_ELASTIC = None
+
+
+def ElasticEnergy(c, x, u, ep: ElasticEnergyPlan):
+    """Differentiable J(c, x, u) (a torch scalar) on the GPU."""
+    global _ELASTIC
+    if _ELASTIC is None:
+        _ELASTIC = _make_energy_function()
+    return _ELASTIC.apply(c, x, u, ep)

@@ -28,7 +28,9 @@ STATUS = {0: "FE_OK", 1: "FE_ERR_INVALID_ARG", 2: "FE_ERR_UNSUPPORTED",
 EXPORTS = ["fe_status_string", "fe_last_error", "fe_version",
            "fe_reference_sizes", "fe_reference_tables", "fe_plan_create",
            "fe_plan_info", "fe_plan_workspace_size", "fe_execute",
-           "fe_plan_check", "fe_plan_destroy"]
+           "fe_plan_check", "fe_plan_destroy", "fe_incidence_create",
+           "fe_incidence_destroy", "fe_assemble",
+           "fe_energy_grad_workspace_size", "fe_energy_grad"]
 
 
 class FeError(RuntimeError):
@@ -81,6 +83,14 @@ def lib():
     L.fe_execute.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, sz, vp]
     L.fe_plan_check.argtypes = [vp, vp, vp]
     L.fe_plan_destroy.argtypes = [vp]
+    dbl = ctypes.c_double
+    L.fe_incidence_create.argtypes = [i64, i64, i32, vp, vp,
+                                      ctypes.POINTER(vp)]
+    L.fe_incidence_destroy.argtypes = [vp]
+    L.fe_assemble.argtypes = [vp, i32, i32, vp, dbl, vp, vp]
+    L.fe_energy_grad_workspace_size.argtypes = [vp, i64, ctypes.POINTER(sz)]
+    L.fe_energy_grad.argtypes = [vp, vp, i64, i64, vp, vp, vp, vp, dbl, vp,
+                                 vp, vp, sz, vp]
     _lib = L
     return L
 

@@ -21,7 +21,8 @@ HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wall", "-Wno-unused-result", "-munsafe-fp-atomics"]
 SOURCES = ["api.hip", "reference.cpp", "k_generic_f64.hip",
-           "k_generic_f32.hip", "k_mfma.hip", "k_sumfact.hip"]
+           "k_generic_f32.hip", "k_mfma.hip", "k_sumfact.hip",
+           "k_adjoint.hip"]
 
 
 def _compile(src: str) -> str:

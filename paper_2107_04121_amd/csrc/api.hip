@@ -10,6 +10,7 @@
 
 struct fe_plan_s : fe::Plan {};
 
+
 namespace fe {
 
 static thread_local std::string g_last_error;
@@ -17,6 +18,13 @@ static thread_local std::string g_last_error;
 void set_error(const std::string &msg) { g_last_error = msg; }
 
 int n_comp_of(int form) { return (form == FE_FORM_VMASS || form == FE_FORM_ELASTICITY) ? 3 : 1; }
+
+size_t grad_part_bytes(const Plan &p, int64_t n_cells);
+int energy_grad_impl(const Plan &p, const fe_incidence_s *inc, const ExecArgs &A, double scale, void *gmat,
+                     double *gcoords, void *part, hipStream_t st);
+int assemble_impl(const fe_incidence_s *inc, int nc, int prec, const void *vec, double scale, void *out,
+                  hipStream_t st);
+int incidence_build(fe_incidence_s *inc, const int32_t *conn, hipStream_t st);
 
 LaunchFn select_generic_f64(const Plan &p);
 LaunchFn select_generic_f32(const Plan &p);
@@ -249,6 +257,91 @@ int fe_plan_check(fe_plan p, void *workspace, void *stream)
     if (flags & FAULT_INDEX) return fail(FE_ERR_INDEX_OUT_OF_RANGE, "a connectivity entry is out of range");
     if (flags & FAULT_DET) return fail(FE_ERR_NONPOSITIVE_JACOBIAN, "det J <= 0 at a quadrature point");
     return FE_OK;
+}
+
+int fe_incidence_create(int64_t n_cells, int64_t n_nodes, int n_basis, const int32_t *conn, void *stream,
+                        fe_incidence *out)
+{
+    if (!out) return fail(FE_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (n_cells < 0 || n_nodes < 0 || n_basis <= 0 || (n_cells > 0 && (!conn || n_nodes == 0)))
+        return fail(FE_ERR_INVALID_ARG, "bad incidence arguments");
+    if (n_cells * (int64_t)n_basis > 0x7fffffffLL || n_nodes > 0x7ffffffeLL)
+        return fail(FE_ERR_INVALID_ARG, "mesh too large for int32 incidence");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) {
+        (void)hipGetLastError();
+        return fail(FE_ERR_NO_DEVICE, "no HIP device");
+    }
+    fe_incidence_s *inc = new (std::nothrow) fe_incidence_s();
+    if (!inc) return fail(FE_ERR_OUT_OF_MEMORY, "host allocation failed");
+    inc->n_cells = n_cells;
+    inc->n_nodes = n_nodes;
+    inc->nb = n_basis;
+    inc->device = dev;
+    int rc = incidence_build(inc, conn, static_cast<hipStream_t>(stream));
+    if (rc) {
+        fe_incidence_destroy(inc);
+        return rc;
+    }
+    *out = inc;
+    return FE_OK;
+}
+
+int fe_incidence_destroy(fe_incidence inc)
+{
+    if (!inc) return FE_OK;
+    if (inc->offsets) (void)hipFree(inc->offsets);
+    if (inc->items) (void)hipFree(inc->items);
+    delete inc;
+    return FE_OK;
+}
+
+int fe_assemble(fe_incidence inc, int n_comp, int precision, const void *cell_vec, double scale, void *out,
+                void *stream)
+{
+    if (!inc || !cell_vec || !out || n_comp < 1 || n_comp > 3) return fail(FE_ERR_INVALID_ARG, "bad argument");
+    if (precision < FE_PREC_FP64 || precision > FE_PREC_BF16X3) return fail(FE_ERR_INVALID_ARG, "bad precision");
+    return assemble_impl(inc, n_comp, precision, cell_vec, scale, out, static_cast<hipStream_t>(stream));
+}
+
+int fe_energy_grad_workspace_size(fe_plan p, int64_t n_cells, size_t *bytes)
+{
+    if (!p || !bytes || n_cells < 0) return fail(FE_ERR_INVALID_ARG, "bad argument");
+    *bytes = FLAG_BYTES + grad_part_bytes(*p, n_cells);
+    return FE_OK;
+}
+
+int fe_energy_grad(fe_plan p, fe_incidence inc, int64_t n_cells, int64_t n_nodes, const double *coords,
+                   const int32_t *conn, const void *material, const void *dofs, double scale, void *grad_material,
+                   double *grad_coords, void *workspace, size_t workspace_bytes, void *stream)
+{
+    if (!p) return fail(FE_ERR_INVALID_ARG, "plan is NULL");
+    if (p->form != FE_FORM_ELASTICITY || p->mode != FE_MODE_EVAL ||
+        (p->mat_kind != FE_MAT_ISO_QP && p->mat_kind != FE_MAT_ISO_CELL) || p->prec == FE_PREC_BF16X3)
+        return fail(FE_ERR_UNSUPPORTED, "needs an ELASTICITY/EVAL plan with ISO_QP or ISO_CELL material, FP64/FP32");
+    if (n_cells < 0 || n_nodes < 0) return fail(FE_ERR_INVALID_ARG, "negative size");
+    if (n_cells == 0) return FE_OK;
+    if (!coords || !conn || !material || !dofs) return fail(FE_ERR_INVALID_ARG, "NULL input");
+    if (grad_coords && (!inc || inc->n_cells != n_cells || inc->n_nodes != n_nodes || inc->nb != p->nb))
+        return fail(FE_ERR_INVALID_ARG, "incidence does not match the mesh");
+    size_t need;
+    fe_energy_grad_workspace_size(p, n_cells, &need);
+    if (!workspace || workspace_bytes < need) return fail(FE_ERR_INVALID_ARG, "workspace too small");
+    ExecArgs A{};
+    A.n_cells = n_cells;
+    A.n_nodes = n_nodes;
+    A.coords = coords;
+    A.conn = conn;
+    A.mat = material;
+    A.mat_kind = p->mat_kind;
+    A.dofs = dofs;
+    A.out = nullptr;
+    A.flags = static_cast<unsigned *>(workspace);
+    A.tab = p->tab;
+    A.xcd_remap = p->opts.xcd_remap == 0 ? 0 : 1;
+    void *part = static_cast<char *>(workspace) + FLAG_BYTES;
+    return energy_grad_impl(*p, inc, A, scale, grad_material, grad_coords, part, static_cast<hipStream_t>(stream));
 }
 
 int fe_plan_destroy(fe_plan p)

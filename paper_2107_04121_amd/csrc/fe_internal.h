@@ -9,6 +9,14 @@
 
 #include "../../include/fe_forms.h"
 
+// Node-to-(cell, local node) incidence in CSR form (device arrays).
+struct fe_incidence_s {
+    int64_t n_cells = 0, n_nodes = 0;
+    int nb = 0, device = -1;
+    int32_t *offsets = nullptr;  // [n_nodes + 1]
+    int32_t *items = nullptr;    // [n_cells * nb], item = e * nb + a, sorted per node
+};
+
 namespace fe {
 
 struct RefTables {
