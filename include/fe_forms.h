@@ -225,6 +225,52 @@ int fe_energy_grad(fe_plan plan, fe_incidence inc, int64_t n_cells, int64_t n_no
                    void *grad_material, double *grad_coords, void *workspace, size_t workspace_bytes,
                    void *stream);
 
+/* ---- batched evaluation of uneven groups in one persistent launch ------- */
+
+/* One group of cells of a single kind and order with its own mesh arrays and
+ * outputs (device pointers, caller-owned).  The paper's single-einsum
+ * evaluation needs rectangular operands and so one call per cell kind and
+ * order (grouping of mixed meshes is left open in its introduction); a batch
+ * evaluates all groups and all their forms in one kernel launch.
+ *   forms: bit mask of (1 << FE_FORM_MASS), (1 << FE_FORM_LAPLACE),
+ *          (1 << FE_FORM_ELASTICITY); all of a group's forms share one
+ *          geometry evaluation per cell;
+ *   tile:  cells per work item, 0 = default (tuned when autotune is on);
+ *   material: [n_cells][2] (lambda, mu) when ELASTICITY is requested;
+ *   out_mass, out_laplace: [n_cells][n_basis][n_basis];
+ *   out_elasticity: [n_cells][3 n_basis][3 n_basis] (16-byte aligned). */
+typedef struct {
+    int cell, order;
+    int forms;
+    int tile;
+    int64_t n_cells, n_nodes;
+    const double *coords;
+    const int32_t *conn;
+    const void *material;
+    void *out_mass;
+    void *out_laplace;
+    void *out_elasticity;
+} fe_group;
+
+typedef struct fe_batch_s *fe_batch;
+
+/* Build a batch of 1..16 groups (Q1/Q2 hexahedra, P1/P2 tetrahedra) in FP64
+ * or FP32 on the current device: copies the group descriptions and the
+ * reference tables to the device and captures the launch (a counter reset
+ * and one persistent kernel that pulls (group, tile) work items) in a HIP
+ * graph.  With autotune != 0 it then times the graph over tile candidates of
+ * each group and keeps the fastest (this runs the batch, writing the
+ * outputs).  Synchronous.  Errors: FE_ERR_INVALID_ARG, FE_ERR_UNSUPPORTED. */
+int fe_batch_create(int n_groups, const fe_group *groups, int precision, int autotune, fe_batch *out);
+/* Launch the captured graph on `stream` (asynchronous, allocates nothing). */
+int fe_batch_execute(fe_batch b, void *stream);
+/* Synchronise and report det J <= 0 / out-of-range node faults (then clear). */
+int fe_batch_check(fe_batch b, void *stream);
+/* Chosen tile per group (caller's order), the best tuned time in ms and the
+ * persistent grid size.  Any pointer may be NULL. */
+int fe_batch_tiles(fe_batch b, int *tiles, float *tune_ms, int *grid);
+int fe_batch_destroy(fe_batch b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -19,7 +19,7 @@ from . import _lib
 from ._lib import FeError
 
 __all__ = ["Plan", "FeError", "Incidence", "assemble", "reference_sizes",
-           "reference_tables", "n_comp", "ElasticEnergy"]
+           "reference_tables", "n_comp", "ElasticEnergy", "Batch"]
 
 _TORCH_DT = {"fp64": "float64", "fp32": "float32", "bf16x3": "float32"}
 
@@ -292,3 +292,79 @@ def ElasticEnergy(c, x, u, ep: ElasticEnergyPlan):
     if _ELASTIC is None:
         _ELASTIC = _make_energy_function()
     return _ELASTIC.apply(c, x, u, ep)
+
+
+class Batch:
+    """Uneven groups of cells (Q1/Q2 hexahedra, P1/P2 tetrahedra), each with
+    its own mesh arrays and a set of forms (mass, Laplace, elasticity), run
+    as ONE persistent kernel captured in a HIP graph.
+
+    groups: list of dicts with keys cell, order, forms (iterable of
+    "mass"/"laplace"/"elasticity"), coords, conn, material (lambda, mu per
+    cell, for elasticity) and optionally tile.  Outputs are allocated here:
+    batch.outputs[i][form] -> (n_cells, nd, nd) tensor."""
+
+    def __init__(self, groups, precision: str = "fp32", autotune: bool = True):
+        import torch
+        dt = {"fp64": torch.float64, "fp32": torch.float32}[precision]
+        self.precision = precision
+        self.outputs = []
+        self._keep = []
+        arr = (_lib.fe_group * len(groups))()
+        for i, g in enumerate(groups):
+            cell, order = g["cell"], int(g["order"])
+            nb, _ = reference_sizes(cell, order)
+            X, C = g["coords"], g["conn"]
+            n = C.shape[0]
+            forms = set(g["forms"])
+            outs = {}
+            mask = 0
+            for f in forms:
+                mask |= 1 << _lib.FORMS[f]
+                nd = 3 * nb if f == "elasticity" else nb
+                outs[f] = torch.empty((n, nd, nd), dtype=dt, device=X.device)
+            mat = g.get("material")
+            if mat is not None and mat.dtype != dt:
+                raise ValueError(f"material must be {dt}")
+            arr[i] = _lib.fe_group(
+                _lib.CELLS[cell], order, mask, int(g.get("tile", 0)), n,
+                X.shape[0], X.data_ptr(), C.data_ptr(),
+                mat.data_ptr() if mat is not None else None,
+                outs["mass"].data_ptr() if "mass" in outs else None,
+                outs["laplace"].data_ptr() if "laplace" in outs else None,
+                outs["elasticity"].data_ptr() if "elasticity" in outs
+                else None)
+            self.outputs.append(outs)
+            self._keep += [X, C, mat]
+        torch.cuda.synchronize()
+        h = ctypes.c_void_p()
+        _lib.check(_lib.lib().fe_batch_create(len(groups), arr,
+                                              _lib.PRECS[precision],
+                                              1 if autotune else 0,
+                                              ctypes.byref(h)),
+                   "fe_batch_create")
+        self._h = h
+        tiles = (ctypes.c_int * len(groups))()
+        ms, grid = ctypes.c_float(), ctypes.c_int()
+        _lib.check(_lib.lib().fe_batch_tiles(h, tiles, ctypes.byref(ms),
+                                             ctypes.byref(grid)),
+                   "fe_batch_tiles")
+        self.tiles = list(tiles)
+        self.tuned_ms = ms.value
+        self.grid = grid.value
+
+    def run(self, stream=None):
+        _lib.check(_lib.lib().fe_batch_execute(self._h,
+                                               _stream_handle(stream)),
+                   "fe_batch_execute")
+        return self.outputs
+
+    def check(self, stream=None):
+        _lib.check(_lib.lib().fe_batch_check(self._h, _stream_handle(stream)),
+                   "fe_batch_check")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib._lib is not None:
+            _lib._lib.fe_batch_destroy(h)
+            self._h = None

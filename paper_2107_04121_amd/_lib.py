@@ -30,7 +30,9 @@ EXPORTS = ["fe_status_string", "fe_last_error", "fe_version",
            "fe_plan_info", "fe_plan_workspace_size", "fe_execute",
            "fe_plan_check", "fe_plan_destroy", "fe_incidence_create",
            "fe_incidence_destroy", "fe_assemble",
-           "fe_energy_grad_workspace_size", "fe_energy_grad"]
+           "fe_energy_grad_workspace_size", "fe_energy_grad",
+           "fe_batch_create", "fe_batch_execute", "fe_batch_check",
+           "fe_batch_tiles", "fe_batch_destroy"]
 
 
 class FeError(RuntimeError):
@@ -44,6 +46,16 @@ class FeError(RuntimeError):
 class fe_options(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int), ("block", ctypes.c_int),
                 ("elems", ctypes.c_int), ("xcd_remap", ctypes.c_int)]
+
+
+class fe_group(ctypes.Structure):
+    _fields_ = [("cell", ctypes.c_int), ("order", ctypes.c_int),
+                ("forms", ctypes.c_int), ("tile", ctypes.c_int),
+                ("n_cells", ctypes.c_int64), ("n_nodes", ctypes.c_int64),
+                ("coords", ctypes.c_void_p), ("conn", ctypes.c_void_p),
+                ("material", ctypes.c_void_p), ("out_mass", ctypes.c_void_p),
+                ("out_laplace", ctypes.c_void_p),
+                ("out_elasticity", ctypes.c_void_p)]
 
 
 _lib = None
@@ -91,6 +103,12 @@ def lib():
     L.fe_energy_grad_workspace_size.argtypes = [vp, i64, ctypes.POINTER(sz)]
     L.fe_energy_grad.argtypes = [vp, vp, i64, i64, vp, vp, vp, vp, dbl, vp,
                                  vp, vp, sz, vp]
+    L.fe_batch_create.argtypes = [i32, ctypes.POINTER(fe_group), i32, i32,
+                                  ctypes.POINTER(vp)]
+    L.fe_batch_execute.argtypes = [vp, vp]
+    L.fe_batch_check.argtypes = [vp, vp]
+    L.fe_batch_tiles.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_float), ip]
+    L.fe_batch_destroy.argtypes = [vp]
     _lib = L
     return L
 

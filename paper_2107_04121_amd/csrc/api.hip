@@ -26,6 +26,12 @@ int assemble_impl(const fe_incidence_s *inc, int nc, int prec, const void *vec, 
                   hipStream_t st);
 int incidence_build(fe_incidence_s *inc, const int32_t *conn, hipStream_t st);
 
+int batch_create(int n_groups, const fe_group *groups, int precision, int autotune, fe_batch_s **out);
+int batch_execute(fe_batch_s *b, hipStream_t st);
+int batch_check(fe_batch_s *b, hipStream_t st);
+int batch_info(fe_batch_s *b, int *tiles, float *tune_ms, int *grid);
+void batch_destroy(fe_batch_s *b);
+
 LaunchFn select_generic_f64(const Plan &p);
 LaunchFn select_generic_f32(const Plan &p);
 
@@ -342,6 +348,36 @@ int fe_energy_grad(fe_plan p, fe_incidence inc, int64_t n_cells, int64_t n_nodes
     A.xcd_remap = p->opts.xcd_remap == 0 ? 0 : 1;
     void *part = static_cast<char *>(workspace) + FLAG_BYTES;
     return energy_grad_impl(*p, inc, A, scale, grad_material, grad_coords, part, static_cast<hipStream_t>(stream));
+}
+
+int fe_batch_create(int n_groups, const fe_group *groups, int precision, int autotune, fe_batch *out)
+{
+    if (!out) return fail(FE_ERR_INVALID_ARG, "out is NULL");
+    return batch_create(n_groups, groups, precision, autotune, out);
+}
+
+int fe_batch_execute(fe_batch b, void *stream)
+{
+    if (!b) return fail(FE_ERR_INVALID_ARG, "batch is NULL");
+    return batch_execute(b, static_cast<hipStream_t>(stream));
+}
+
+int fe_batch_check(fe_batch b, void *stream)
+{
+    if (!b) return fail(FE_ERR_INVALID_ARG, "batch is NULL");
+    return batch_check(b, static_cast<hipStream_t>(stream));
+}
+
+int fe_batch_tiles(fe_batch b, int *tiles, float *tune_ms, int *grid)
+{
+    if (!b) return fail(FE_ERR_INVALID_ARG, "batch is NULL");
+    return batch_info(b, tiles, tune_ms, grid);
+}
+
+int fe_batch_destroy(fe_batch b)
+{
+    batch_destroy(b);
+    return FE_OK;
 }
 
 int fe_plan_destroy(fe_plan p)

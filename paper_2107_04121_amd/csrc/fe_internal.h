@@ -17,6 +17,8 @@ struct fe_incidence_s {
     int32_t *items = nullptr;    // [n_cells * nb], item = e * nb + a, sorted per node
 };
 
+struct fe_batch_s;
+
 namespace fe {
 
 struct RefTables {

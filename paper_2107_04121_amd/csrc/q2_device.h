@@ -1,0 +1,524 @@
+// Q2 hexahedron linear-elasticity cell routine on the matrix cores (shared
+// by the single-form kernel and the batched kernel).  See k_mfma.hip for the
+// method.
+#pragma once
+
+#include "fe_device.h"
+
+namespace fe {
+namespace q2 {
+
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+enum { MM_F64 = 0, MM_F32 = 1, MM_BF16X3 = 2 };
+
+template <int MM>
+struct MMT {
+    using T = float;
+    using acc = f4;
+};
+template <>
+struct MMT<MM_F64> {
+    using T = double;
+    using acc = d4;
+};
+
+constexpr int align16(int x) { return (x + 15) & ~15; }
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
+// Q2 hexahedron
+constexpr int NB = 27, NQ = 27, ND = 81, NK = ND * ND;
+
+template <int MM>
+struct Q2Layout {
+    using T = typename MMT<MM>::T;
+    static constexpr int VEC = 16 / (int)sizeof(T);       // entries per 16-byte store
+    static constexpr int KP = MM == MM_BF16X3 ? 32 : 28;  // padded K (quadrature points)
+    // kept for the whole launch: 1-D tables and weights
+    static constexpr int OFF_TB = 0;                      // double B1[9], D1[9], w[27]
+    static constexpr int OFF_U = align16(OFF_TB + (9 + 9 + NQ) * 8);
+    // phase A (per cell): geometry and GEMM operand
+    static constexpr int OFF_X = OFF_U;                   // double xc[3][28] (component-major)
+    static constexpr int OFF_J = OFF_X + 3 * 28 * 8;      // double J[27][9]
+    static constexpr int OFF_WD = OFF_J + NQ * 9 * 8;     // double wd[28]
+    // GEMM operand, transposed: row = i*33 + a (component i, basis a; rows
+    // a = 27..32 are zero padding), column = quadrature point k, odd row
+    // stride KS.  Lanes of one MFMA fragment read 16 consecutive rows at
+    // fixed k and the geometry threads write one row entry per quadrature
+    // point, so both spread over the LDS banks.
+    static constexpr int KS = KP + 1;
+    static constexpr int GROWS = 3 * 33;
+    static constexpr int OFF_G = align16(OFF_WD + 28 * 8);  // T Gs[GROWS][KS]
+    static constexpr int END_A = OFF_G + GROWS * KS * (int)sizeof(T);
+    // phase B (aliases A): the cell's matrix row-major, shifted to the output
+    // alignment; it first holds the blocks r <= s of P in their places
+    static constexpr int OFF_K = OFF_U;
+    static constexpr int END_B = OFF_K + (NK + VEC) * (int)sizeof(T);
+    static constexpr int BYTES = align16(cmax(END_A, END_B));
+    // 16-byte vectors of the staged matrix per thread in the flush
+    static constexpr int NV = ((NK + 2 * VEC - 1) / VEC + 255) / 256;
+};
+
+// Persistent schedule: every workgroup walks a strided list of cells.  With
+// XCD remapping, the 8 XCDs (hardware workgroup id modulo 8) own 8
+// contiguous ranges of cells, so cells that share nodes meet in one L2.
+__device__ __forceinline__ void cell_range(int remap, int64_t n, int64_t &first, int64_t &end, int64_t &stride)
+{
+    const int G = gridDim.x, b = blockIdx.x;
+    if (!remap || G < 8 || (G & 7)) {
+        first = b;
+        end = n;
+        stride = G;
+        return;
+    }
+    const int x = b & 7, j = b >> 3, per = G >> 3;
+    const int64_t chunk = (n + 7) / 8;
+    const int64_t lo = x * chunk;
+    first = lo + j;
+    end = lo + chunk < n ? lo + chunk : n;
+    stride = per;
+}
+
+// 6x6 grid of 16x16 output tiles; block (r,s) = tiles 2r..2r+1 x 2s..2s+1.
+// The 24 tiles of blocks r <= s are split in 2-D rectangles, 6 per wave, so
+// each wave loads few distinct operand fragments per k step:
+//   wave 0: rows {0,1} x cols {0,1,2}   wave 1: rows {0,1} x cols {3,4,5}
+//   wave 2: rows {2,3} x cols {2,3,4}   wave 3: rows {2,3} x {5}, {4,5} x {4,5}
+// Wave w < 3 uses A rows AR[w][0..1], B cols BC[w][0..2], tile t = (t/3, t%3).
+// Wave 3 uses A rows 2,3,4,5, B cols 4,5 with tiles (0,1),(1,1),(2,0),(2,1),
+// (3,0),(3,1) in (A index, B index).
+__device__ __forceinline__ void tile_of(int wave, int t, int &TM, int &TN)
+{
+    if (wave < 3) {
+        const int r0 = wave == 2 ? 2 : 0;
+        const int c0 = wave == 0 ? 0 : (wave == 1 ? 3 : 2);
+        TM = r0 + t / 3;
+        TN = c0 + t % 3;
+    } else {
+        const int ai[6] = {0, 1, 2, 2, 3, 3}, bi[6] = {1, 1, 0, 1, 0, 1};
+        TM = 2 + ai[t];
+        TN = 4 + bi[t];
+    }
+}
+
+__device__ __forceinline__ int blk_id(int r, int s)  // r <= s
+{
+    return r == 0 ? s : (r == 1 ? 2 + s : 5);
+}
+
+template <int MM, int NA, int NBF>
+__device__ __forceinline__ void mma_rect(const typename MMT<MM>::T *Gs, const double *wd, const int (&ar)[NA],
+                                         const int (&bc)[NBF], const int (&ta)[6], const int (&tb)[6], int lane,
+                                         typename MMT<MM>::acc (&acc)[6])
+{
+    using T = typename MMT<MM>::T;
+    const int col = lane & 15, grp = lane >> 4;
+#pragma unroll
+    for (int t = 0; t < 6; t++) acc[t] = typename MMT<MM>::acc{};
+    constexpr int KS = Q2Layout<MM>::KS;
+    // operand row of tile row TM for this lane: component TM/2, basis
+    // 16*(TM%2) + lane%16
+    int ra[NA], rb[NBF];
+#pragma unroll
+    for (int i = 0; i < NA; i++) ra[i] = ((ar[i] >> 1) * 33 + (ar[i] & 1) * 16 + col) * KS;
+#pragma unroll
+    for (int j = 0; j < NBF; j++) rb[j] = ((bc[j] >> 1) * 33 + (bc[j] & 1) * 16 + col) * KS;
+    if constexpr (MM == MM_F64 || MM == MM_F32) {
+#pragma unroll
+        for (int kk = 0; kk < Q2Layout<MM>::KP / 4; kk++) {
+            const int k = 4 * kk + grp;
+            const T w = static_cast<T>(wd[k]);  // wd[27] == 0 (padding)
+            T a[NA], b[NBF];
+#pragma unroll
+            for (int i = 0; i < NA; i++) a[i] = Gs[ra[i] + k] * w;
+#pragma unroll
+            for (int j = 0; j < NBF; j++) b[j] = Gs[rb[j] + k];
+#pragma unroll
+            for (int t = 0; t < 6; t++) {
+                if constexpr (MM == MM_F64)
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta[t]], b[tb[t]], acc[t], 0, 0, 0);
+                else
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ta[t]], b[tb[t]], acc[t], 0, 0, 0);
+            }
+        }
+    } else {
+        bf8 ahi[NA], alo[NA], bhi[NBF], blo[NBF];
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const int k = 8 * grp + u;
+            const float w = k < NQ ? static_cast<float>(wd[k]) : 0.0f;
+#pragma unroll
+            for (int i = 0; i < NA; i++) {
+                const float x = Gs[ra[i] + k] * w;
+                const __bf16 h = static_cast<__bf16>(x);
+                ahi[i][u] = h;
+                alo[i][u] = static_cast<__bf16>(x - static_cast<float>(h));
+            }
+#pragma unroll
+            for (int j = 0; j < NBF; j++) {
+                const float x = Gs[rb[j] + k];
+                const __bf16 h = static_cast<__bf16>(x);
+                bhi[j][u] = h;
+                blo[j][u] = static_cast<__bf16>(x - static_cast<float>(h));
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 6; t++)
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[ta[t]], bhi[tb[t]], acc[t], 0, 0, 0);
+#pragma unroll
+        for (int t = 0; t < 6; t++)
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[ta[t]], blo[tb[t]], acc[t], 0, 0, 0);
+#pragma unroll
+        for (int t = 0; t < 6; t++)
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[ta[t]], bhi[tb[t]], acc[t], 0, 0, 0);
+    }
+}
+
+template <int MM>
+__device__ __forceinline__ void mma_wave(const typename MMT<MM>::T *Gs, const double *wd, int wave, int lane,
+                                         typename MMT<MM>::acc (&acc)[6])
+{
+    if (wave < 3) {
+        const int r0 = wave == 2 ? 2 : 0;
+        const int c0 = wave == 0 ? 0 : (wave == 1 ? 3 : 2);
+        const int ar[2] = {r0, r0 + 1}, bc[3] = {c0, c0 + 1, c0 + 2};
+        const int ta[6] = {0, 0, 0, 1, 1, 1}, tb[6] = {0, 1, 2, 0, 1, 2};
+        mma_rect<MM, 2, 3>(Gs, wd, ar, bc, ta, tb, lane, acc);
+    } else {
+        const int ar[4] = {2, 3, 4, 5}, bc[2] = {4, 5};
+        const int ta[6] = {0, 1, 2, 2, 3, 3}, tb[6] = {1, 1, 0, 1, 0, 1};
+        mma_rect<MM, 4, 2>(Gs, wd, ar, bc, ta, tb, lane, acc);
+    }
+}
+
+// 16x16 tile (TM, TN) of the scalar mass matrix sum_q wd[q] phi_a(q) phi_b(q)
+// on the matrix cores, basis values built from the 1-D table B1 (FP32 MFMA
+// for the split precision as well).
+template <int MM>
+__device__ __forceinline__ typename MMT<MM>::acc mass_tile(const double *B1, const double *wd, int TM, int TN,
+                                                           int lane)
+{
+    using T = typename MMT<MM>::T;
+    typename MMT<MM>::acc acc{};
+    const int col = lane & 15, grp = lane >> 4;
+    const int a = TM * 16 + col, b = TN * 16 + col;
+    auto phi = [&](int q, int f) -> double {
+        if (f >= NB) return 0.0;
+        return B1[(q % 3) * 3 + f % 3] * B1[((q / 3) % 3) * 3 + (f / 3) % 3] * B1[(q / 9) * 3 + f / 9];
+    };
+#pragma unroll
+    for (int kk = 0; kk < 7; kk++) {
+        const int k = 4 * kk + grp;
+        const bool ok = k < NQ;
+        const T x = ok ? static_cast<T>(wd[k] * phi(k, a)) : T(0);
+        const T y = ok ? static_cast<T>(phi(k, b)) : T(0);
+        if constexpr (MM == MM_F64)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc, 0, 0, 0);
+        else
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+template <typename V>
+__device__ __forceinline__ void out_store(const V &v, V *p)
+{
+    __builtin_nontemporal_store(v, p);
+}
+
+// Everything one run of the Q2 cell routine reads and writes.
+struct Q2Job {
+    int64_t n_cells, n_nodes;
+    const double *coords;
+    const int32_t *conn;
+    const void *mat;   // [n_cells][2] lambda, mu
+    void *out;         // elasticity [n_cells][81][81]
+    void *out_mass;    // MULTI only: scalar mass [n_cells][27][27] (or NULL)
+    void *out_lap;     // MULTI only: Laplace [n_cells][27][27] (or NULL)
+    unsigned *flags;
+    DevTables tab;
+};
+
+// Q2 cells e, e + stride, ... < e_end with one workgroup of 256 threads.
+// MULTI also emits the Laplace matrix P_00 + P_11 + P_22 (a by-product of
+// the elasticity contraction) and the scalar mass matrix (one more small
+// product on the matrix cores), sharing the geometry.  smem must hold
+// Q2Layout<MM>::BYTES.  Ends with the workgroup synchronised.
+template <int MM, bool MULTI>
+__device__ __forceinline__ void q2_run(const Q2Job &A, int64_t e, int64_t e_end, int64_t stride, unsigned char *smem)
+{
+    using L = Q2Layout<MM>;
+    using T = typename L::T;
+    using ACC = typename MMT<MM>::acc;
+    typedef T TV __attribute__((ext_vector_type(L::VEC)));
+    double *B1 = reinterpret_cast<double *>(smem + L::OFF_TB);
+    double *D1 = B1 + 9;
+    double *wq = D1 + 9;
+    double *xc = reinterpret_cast<double *>(smem + L::OFF_X);
+    double *Jq = reinterpret_cast<double *>(smem + L::OFF_J);
+    double *wd = reinterpret_cast<double *>(smem + L::OFF_WD);
+    T *Gs = reinterpret_cast<T *>(smem + L::OFF_G);
+    T *Ks = reinterpret_cast<T *>(smem + L::OFF_K);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    if (e >= e_end) return;  // uniform over the workgroup
+
+    if (tid < 9) {
+        B1[tid] = A.tab.B1[tid];
+        D1[tid] = A.tab.D1[tid];
+    } else if (tid >= 32 && tid < 32 + NQ) {
+        wq[tid - 32] = A.tab.w[tid - 32];
+    }
+    const T *mat = static_cast<const T *>(A.mat);
+    // this thread's node coordinate (threads < 81: node a = tid/3, axis tid%3)
+    const int ga = tid / 3, gc = tid - 3 * (tid / 3);
+    double xval = 0.0;
+    if (tid < NB * 3) {
+        const int64_t n = checked_node(A.conn, e * NB + ga, A.n_nodes, A.flags);
+        xval = A.coords[3 * n + gc];
+    }
+    T lam = mat[2 * e], mu = mat[2 * e + 1];
+
+    for (;;) {
+        const int64_t en = e + stride;
+        const bool has_next = en < e_end;
+
+        // 1. this cell's coordinates to LDS (component-major); zero the
+        //    GEMM operand; prefetch the next cell's connectivity
+        if (tid < NB * 3) xc[gc * 28 + ga] = xval;
+        if (tid == 255) wd[NQ] = 0.0;
+        // zero the operand padding: rows a = 27..32 of each component, and
+        // columns k = 27..KP-1 of the real rows
+        for (int i = tid; i < 3 * 6 * L::KS + 3 * NB * (L::KP - NQ); i += 256) {
+            if (i < 3 * 6 * L::KS) {
+                const int c = i / (6 * L::KS), rem = i - c * 6 * L::KS;
+                Gs[(c * 33 + NB) * L::KS + rem] = T(0);
+            } else {
+                const int j = i - 3 * 6 * L::KS, row = j / (L::KP - NQ), k = NQ + j % (L::KP - NQ);
+                Gs[((row / NB) * 33 + row % NB) * L::KS + k] = T(0);
+            }
+        }
+        int32_t nn = 0;
+        if (has_next && tid < NB * 3) nn = A.conn[en * NB + ga];
+        __syncthreads();
+
+        // 2. J[i][j] at quadrature point q, one entry per thread (243
+        //    threads), by sum factorization over the tensor-product basis
+        if (tid < NQ * 9) {
+            const int q = tid % NQ, ij = tid / NQ, i = ij / 3, j = ij - 3 * (ij / 3);
+            const int q0 = q % 3, q1 = (q / 3) % 3, q2 = q / 9;
+            const double *T0 = (j == 0 ? D1 : B1) + q0 * 3;
+            const double *T1 = (j == 1 ? D1 : B1) + q1 * 3;
+            const double *T2 = (j == 2 ? D1 : B1) + q2 * 3;
+            const double f0[3] = {T0[0], T0[1], T0[2]}, f1[3] = {T1[0], T1[1], T1[2]},
+                         f2[3] = {T2[0], T2[1], T2[2]};
+            const double *x = xc + i * 28;
+            double s2 = 0.0;
+#pragma unroll
+            for (int a2 = 0; a2 < 3; a2++) {
+                double s1 = 0.0;
+#pragma unroll
+                for (int a1 = 0; a1 < 3; a1++) {
+                    const double *xr = x + 3 * (a1 + 3 * a2);
+                    s1 = fma(f1[a1], f0[0] * xr[0] + f0[1] * xr[1] + f0[2] * xr[2], s1);
+                }
+                s2 = fma(f2[a2], s1, s2);
+            }
+            Jq[q * 9 + i * 3 + j] = s2;
+        }
+        __syncthreads();
+
+        // 3. det J and J^-1 per quadrature point (FP64, recomputed by each
+        //    of the 9 threads of a point), w det J; then
+        //    G[q][i][a] = sum_j dphi_a/dxi_j Jinv[j][i] (stored as T), one
+        //    (q, i, a2) triple per thread, 9 basis functions each.  The next
+        //    cell's coordinates and coefficients are prefetched here.
+        double xnext = 0.0;
+        T lamn = T(0), mun = T(0);
+        if (has_next) {
+            if (tid < NB * 3) {
+                int64_t n = nn;
+                if (n < 0 || n >= A.n_nodes) {
+                    raise_fault(A.flags, FAULT_INDEX);
+                    n = 0;
+                }
+                xnext = A.coords[3 * n + gc];
+            }
+            lamn = mat[2 * en];
+            mun = mat[2 * en + 1];
+        }
+        if (tid < NQ * 9) {
+            const int q = tid % NQ, r9 = tid / NQ, ci = r9 / 3, a2 = r9 - 3 * (r9 / 3);
+            const int q0 = q % 3, q1 = (q / 3) % 3, q2 = q / 9;
+            double J[3][3], Ji[3][3];
+#pragma unroll
+            for (int r = 0; r < 3; r++)
+#pragma unroll
+                for (int c = 0; c < 3; c++) J[r][c] = Jq[q * 9 + r * 3 + c];
+            const double det = inverse3(J, Ji);
+            if (r9 == 0) {
+                if (!(det > 0.0)) raise_fault(A.flags, FAULT_DET);
+                wd[q] = wq[q] * det;
+            }
+            const double c0 = Ji[0][ci], c1 = Ji[1][ci], c2 = Ji[2][ci];
+            const double bz = B1[q2 * 3 + a2], dz = D1[q2 * 3 + a2];
+            T *dst = Gs + ci * 33 * L::KS + q;
+#pragma unroll
+            for (int a1 = 0; a1 < 3; a1++) {
+                const double by = B1[q1 * 3 + a1], dy = D1[q1 * 3 + a1];
+#pragma unroll
+                for (int a0 = 0; a0 < 3; a0++) {
+                    const double bx = B1[q0 * 3 + a0], dx = D1[q0 * 3 + a0];
+                    const double v = c0 * (dx * by * bz) + c1 * (bx * dy * bz) + c2 * (bx * by * dz);
+                    dst[(a0 + 3 * (a1 + 3 * a2)) * L::KS] = static_cast<T>(v);
+                }
+            }
+        }
+        __syncthreads();
+
+        // 4. the per-cell GEMM on matrix cores
+        ACC acc[6];
+        mma_wave<MM>(Gs, wd, wave, lane, acc);
+        if constexpr (MULTI) {
+            // scalar mass M[a][b] = sum_q w_q det J_q phi_a(q) phi_b(q):
+            // wave w takes tile (w/2, w%2) of the 2x2 tiles over 27x27
+            if (A.out_mass) {
+                ACC am = mass_tile<MM>(B1, wd, wave >> 1, wave & 1, lane);
+                T *om = static_cast<T *>(A.out_mass) + e * (NB * NB);
+                const int b = (wave & 1) * 16 + (lane & 15);
+#pragma unroll
+                for (int v = 0; v < 4; v++) {
+                    const int a = (wave >> 1) * 16 + (MM == MM_F64 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v);
+                    if (a < NB && b < NB) om[a * NB + b] = static_cast<T>(am[v]);
+                }
+            }
+        }
+        __syncthreads();  // every wave is done reading the operands
+
+        // 5. the blocks r <= s of P go straight to their places in the
+        //    staging area that holds the cell's matrix row-major, shifted by
+        //    h entries so that LDS vectors line up with 16-byte aligned output
+        const int64_t base = e * NK;
+        const int h = static_cast<int>(base & (L::VEC - 1));
+#pragma unroll
+        for (int t = 0; t < 6; t++) {
+            int TM, TN;
+            tile_of(wave, t, TM, TN);
+            const int r = TM >> 1, s = TN >> 1;
+            // 16x16 accumulator layout: column = lane % 16; the f32 MFMAs
+            // hold rows 4*(lane/16) + v, the f64 MFMA rows lane/16 + 4*v.
+            const int b = (TN & 1) * 16 + (lane & 15);
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int a = (TM & 1) * 16 + (MM == MM_F64 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v);
+                if (a < NB && b < NB) Ks[h + (r * NB + a) * ND + s * NB + b] = static_cast<T>(acc[t][v]);
+            }
+        }
+        __syncthreads();
+
+        // 6. K from P in place.  A thread owns an unordered pair {a,b}
+        //    (a <= b) of block positions and touches only positions (a,b),
+        //    (b,a) of the nine blocks, so no other thread reads its entries:
+        //      K_rr = (lambda + mu) P_rr + mu (P_00 + P_11 + P_22)  (P_rr symmetric)
+        //      K_rs[x][y] = lambda P_rs[x][y] + mu P_rs[y][x],  K_sr = K_rs^T.
+        {
+            T *K = Ks + h;
+            const T lm = lam + mu;
+#pragma unroll
+            for (int it = 0; it < 2; it++) {
+                const int p = tid + 256 * it;
+                if (p >= NB * (NB + 1) / 2) break;
+                // row a of the upper triangle starts at a*27 - a(a-1)/2
+                int a = static_cast<int>((55.0f - sqrtf(3025.0f - 8.0f * p)) * 0.5f);
+                a = a < 0 ? 0 : (a > NB - 1 ? NB - 1 : a);
+                if (a > 0 && a * NB - a * (a - 1) / 2 > p) a--;
+                if (a < NB - 1 && (a + 1) * NB - (a + 1) * a / 2 <= p) a++;
+                const int b = a + (p - (a * NB - a * (a - 1) / 2));
+                const int ab = a * ND + b, ba = b * ND + a;  // offsets inside a block
+                const T d0 = K[ab], d1 = K[NB * ND + NB + ab], d2 = K[2 * NB * ND + 2 * NB + ab];
+                T pab[3], pba[3];
+#pragma unroll
+                for (int o = 0; o < 3; o++) {
+                    const int r = o == 2 ? 1 : 0, s = o == 0 ? 1 : 2;
+                    const T *U = K + r * NB * ND + s * NB;
+                    pab[o] = U[ab];
+                    pba[o] = U[ba];
+                }
+                const T tr = mu * (d0 + d1 + d2);
+                const T k0 = lm * d0 + tr, k1 = lm * d1 + tr, k2 = lm * d2 + tr;
+                if constexpr (MULTI) {
+                    if (A.out_lap) {
+                        T *ol = static_cast<T *>(A.out_lap) + e * (NB * NB);
+                        const T lv = d0 + d1 + d2;
+                        ol[a * NB + b] = lv;
+                        ol[b * NB + a] = lv;
+                    }
+                }
+                K[ab] = k0;
+                K[NB * ND + NB + ab] = k1;
+                K[2 * NB * ND + 2 * NB + ab] = k2;
+                K[ba] = k0;
+                K[NB * ND + NB + ba] = k1;
+                K[2 * NB * ND + 2 * NB + ba] = k2;
+#pragma unroll
+                for (int o = 0; o < 3; o++) {
+                    const int r = o == 2 ? 1 : 0, s = o == 0 ? 1 : 2;
+                    T *U = K + r * NB * ND + s * NB;  // block (r,s), holds P_rs
+                    T *W = K + s * NB * ND + r * NB;  // block (s,r)
+                    const T kab = lam * pab[o] + mu * pba[o], kba = lam * pba[o] + mu * pab[o];
+                    U[ab] = kab;
+                    W[ab] = kba;
+                    U[ba] = kba;
+                    W[ba] = kab;
+                }
+            }
+        }
+        __syncthreads();
+
+        // 7. linear flush: consecutive lanes store consecutive 16-byte vectors
+        //    of the cell's contiguous output (all LDS reads first); partial
+        //    head/tail vectors go entry by entry
+        {
+            T *out = static_cast<T *>(A.out);
+            TV *aligned = reinterpret_cast<TV *>(out + (base - h));
+            const int nvec = (NK + h + L::VEC - 1) / L::VEC;
+            const TV *k16 = reinterpret_cast<const TV *>(Ks);
+            constexpr int BATCH = 4;
+#pragma unroll
+            for (int j0 = 0; j0 < L::NV; j0 += BATCH) {
+                TV buf[BATCH];
+#pragma unroll
+                for (int j = 0; j < BATCH; j++) {
+                    const int v = tid + 256 * (j0 + j);
+                    if (j0 + j < L::NV && v < nvec) buf[j] = k16[v];
+                }
+#pragma unroll
+                for (int j = 0; j < BATCH; j++) {
+                    const int v = tid + 256 * (j0 + j);
+                    if (j0 + j >= L::NV || v >= nvec) break;
+                    const int lo = v * L::VEC - h;
+                    if (lo >= 0 && lo + L::VEC <= NK) {
+                        out_store(buf[j], aligned + v);
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < L::VEC; u++) {
+                            const int f = lo + u;
+                            if (f >= 0 && f < NK) out[base + f] = buf[j][u];
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();  // the staging area is reused by the next cell
+        if (!has_next) break;
+        e = en;
+        xval = xnext;
+        lam = lamn;
+        mu = mun;
+    }
+}
+
+}  // namespace q2
+}  // namespace fe
