@@ -109,11 +109,19 @@ typedef enum {
     FE_VARIANT_MATRIX_FIRST = 4 /* residual: form K_e then K_e u_e */
 } fe_variant;
 
+/* Residual output layout: CELL_MAJOR [n_cells][n_comp][n_basis] (the
+ * paper's default 'crd' order) or CELL_MINOR [n_comp][n_basis][n_cells]
+ * (the cell axis last, as in the paper's layout study; sum-factorized
+ * kernels only). */
+typedef enum { FE_LAYOUT_CELL_MAJOR = 0, FE_LAYOUT_CELL_MINOR = 1 } fe_layout;
+
 typedef struct {
     int variant;      /* fe_variant */
     int block;        /* threads per workgroup hint, 0 = default */
     int elems;        /* elements per workgroup hint, 0 = default */
     int xcd_remap;    /* 1 = map contiguous element ranges to one XCD (default), 0 = off, -1 = default */
+    int layout;       /* fe_layout of residual outputs */
+    int chunk;        /* MATRIX_FIRST: cells per element-matrix chunk, 0 = default (16384) */
 } fe_options;
 
 typedef struct fe_plan_s *fe_plan;
@@ -150,7 +158,9 @@ int fe_plan_info(fe_plan plan, int *n_basis, int *n_qp, int *n_comp,
 
 /* Bytes of device workspace fe_execute needs for n_cells cells.  The
  * workspace holds the sticky fault bits (first 256 bytes); it must be
- * zero-filled once before first use and is cleared by fe_plan_check. */
+ * zero-filled once before first use and is cleared by fe_plan_check.  The
+ * MATRIX_FIRST residual variant also keeps one chunk of element matrices
+ * there (chunk * n_dof^2 entries). */
 int fe_plan_workspace_size(fe_plan plan, int64_t n_cells, size_t *bytes);
 
 /* Evaluate the plan's form on n_cells cells.

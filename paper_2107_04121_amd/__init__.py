@@ -66,11 +66,14 @@ class Plan:
 
     def __init__(self, cell: str, order: int, form: str, mode: str = "matrix",
                  precision: str = "fp64", material: str | None = None,
-                 variant: str = "auto", xcd_remap: bool = True):
+                 variant: str = "auto", xcd_remap: bool = True,
+                 layout: str = "cell_major", chunk: int = 0):
         self.cell, self.order, self.form = cell, int(order), form
         self.mode, self.precision, self.material = mode, precision, material
+        self.layout = layout
         opts = _lib.fe_options(_lib.VARIANTS[variant], 0, 0,
-                               1 if xcd_remap else 0)
+                               1 if xcd_remap else 0, _lib.LAYOUTS[layout],
+                               int(chunk))
         h = ctypes.c_void_p()
         L = _lib.lib()
         _lib.check(L.fe_plan_create(_lib.CELLS[cell], self.order,
@@ -120,6 +123,8 @@ class Plan:
         if self.mode == "matrix":
             return (n_cells, self.n_dof, self.n_dof)
         if self.mode == "residual":
+            if self.layout == "cell_minor":
+                return (self.n_comp, self.n_basis, n_cells)
             return (n_cells, self.n_comp, self.n_basis)
         return (n_cells,)
 

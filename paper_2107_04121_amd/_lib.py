@@ -45,7 +45,11 @@ class FeError(RuntimeError):
 
 class fe_options(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int), ("block", ctypes.c_int),
-                ("elems", ctypes.c_int), ("xcd_remap", ctypes.c_int)]
+                ("elems", ctypes.c_int), ("xcd_remap", ctypes.c_int),
+                ("layout", ctypes.c_int), ("chunk", ctypes.c_int)]
+
+
+LAYOUTS = {"cell_major": 0, "cell_minor": 1}
 
 
 class fe_group(ctypes.Structure):

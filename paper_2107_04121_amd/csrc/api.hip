@@ -136,6 +136,10 @@ int fe_plan_create(int cell, int order, int form, int mode, int precision, int m
         p->opts.variant = FE_VARIANT_AUTO;
         p->opts.xcd_remap = -1;
     }
+    if (p->opts.layout != FE_LAYOUT_CELL_MAJOR && p->opts.layout != FE_LAYOUT_CELL_MINOR) {
+        delete p;
+        return fail(FE_ERR_INVALID_ARG, "bad layout");
+    }
     if (reference_tables(cell, order, p->ref)) {
         delete p;
         return fail(FE_ERR_UNSUPPORTED, "reference tables");
@@ -144,6 +148,23 @@ int fe_plan_create(int cell, int order, int form, int mode, int precision, int m
     const int want = p->opts.variant;
     LaunchFn fn = nullptr;
     int variant = FE_VARIANT_GENERIC;
+    if (want == FE_VARIANT_MATRIX_FIRST) {
+        if (mode != FE_MODE_RESIDUAL || p->opts.layout != FE_LAYOUT_CELL_MAJOR) {
+            delete p;
+            return fail(FE_ERR_UNSUPPORTED, "matrix-first is a cell-major residual variant");
+        }
+        Plan pm = *p;
+        pm.mode = FE_MODE_MATRIX;
+        LaunchFn fm = select_mfma(pm);
+        if (!fm) fm = select_generic(pm);
+        if (!fm) {
+            delete p;
+            return fail(FE_ERR_UNSUPPORTED, "no matrix kernel for matrix-first");
+        }
+        p->launch_mat = fm;
+        fn = launch_matrix_first;
+        variant = FE_VARIANT_MATRIX_FIRST;
+    }
     if (want == FE_VARIANT_AUTO || want == FE_VARIANT_MFMA) {
         if (mode == FE_MODE_MATRIX && (fn = select_mfma(*p))) variant = FE_VARIANT_MFMA;
     }
@@ -156,6 +177,10 @@ int fe_plan_create(int cell, int order, int form, int mode, int precision, int m
     if (!fn) {
         delete p;
         return fail(FE_ERR_UNSUPPORTED, "no kernel for this cell/order/form/mode/precision/variant");
+    }
+    if (p->opts.layout == FE_LAYOUT_CELL_MINOR && (variant != FE_VARIANT_SUMFACT || mode != FE_MODE_RESIDUAL)) {
+        delete p;
+        return fail(FE_ERR_UNSUPPORTED, "cell-minor output exists for sum-factorized residuals only");
     }
     p->launch = fn;
     p->variant = variant;
@@ -210,7 +235,7 @@ int fe_plan_info(fe_plan p, int *n_basis, int *n_qp, int *n_comp, int *variant, 
 int fe_plan_workspace_size(fe_plan p, int64_t n_cells, size_t *bytes)
 {
     if (!p || !bytes || n_cells < 0) return fail(FE_ERR_INVALID_ARG, "bad argument");
-    *bytes = FLAG_BYTES;
+    *bytes = FLAG_BYTES + (p->variant == FE_VARIANT_MATRIX_FIRST ? matrix_first_bytes(*p, n_cells) : 0);
     return FE_OK;
 }
 

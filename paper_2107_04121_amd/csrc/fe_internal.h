@@ -65,6 +65,7 @@ struct Plan {
     double *d_tab = nullptr;
     DevTables tab{};
     LaunchFn launch = nullptr;
+    LaunchFn launch_mat = nullptr;  // MATRIX_FIRST: the matrix-mode kernel it uses
     fe_options opts{};
 };
 
@@ -87,5 +88,7 @@ LaunchFn select_mfma(const Plan &p);
 LaunchFn select_sumfact(const Plan &p);
 
 int n_comp_of(int form);
+size_t matrix_first_bytes(const Plan &p, int64_t n_cells);
+int launch_matrix_first(const Plan &p, const ExecArgs &A, hipStream_t st);
 
 }  // namespace fe
