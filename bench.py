@@ -1,13 +1,26 @@
-"""Throughput benchmark: linear-elasticity element matrices, Q2 hexahedra
-(27 nodes, 81 DOFs), 3x3x3 Gauss, 48^3 = 110,592 cells on the unit cube with
-vertices perturbed by +-0.15h (seed 0), per-cell Lame lambda, mu ~
-lognormal(0, 0.5).  Output 110592 x 81 x 81.
+"""Throughput benchmark of the per-element weak-form evaluation on one GPU.
 
-One step = one full evaluation of the hot path on the whole mesh (connectivity
-gather, FP64 geometry, contraction, element-matrix store), inputs resident in
-HBM.  Prints one JSON line.  The primary value is FP64; FP32 and BF16X3 (FP64
-geometry, mixed contraction) are timed the same way and reported with their
-measured error against the FP64 oracle on sampled cells.
+Default workload (--config c2): linear-elasticity element matrices, Q2
+hexahedra (27 nodes, 81 DOFs), 3x3x3 Gauss, 48^3 = 110,592 cells on the unit
+cube with vertices perturbed by +-0.15h (seed 0), per-cell Lame lambda, mu ~
+lognormal(0, 0.5).  Output 110592 x 81 x 81.  One step = one full
+evaluation of the hot path on the whole mesh (connectivity gather, FP64
+geometry, contraction, element-matrix store), inputs resident in HBM.  The
+primary value is FP64; FP32 and BF16X3 are timed the same way and reported
+with their measured error against the FP64 oracle on sampled cells.
+
+Other configurations of the same hot path (--config):
+  c1  Q1 Laplace, 16^3 cells (+-0.2h): element matrices and residual, FP64,
+      plus a size sweep up to 128^3 for the HBM roof;
+  c3  Q3 residuals (Laplace, elasticity), 96^3 cells, FP32 with FP64
+      geometry: sum-factorized gradient-first (cell-major and cell-minor
+      output), generic gradient-first, matrix-first;
+  c4  one batched graph launch: 300k P1 tets, 120k P2 tets, 200k Q1 hex,
+      40k Q2 hex, mass + Laplace + elasticity each, FP32; vs separate
+      launches and vs untuned tiles;
+  c5  energy J = sum u_e^T K_e u_e of Q2 elasticity on 32^3 cells with
+      per-point coefficients: forward + adjoint (dJ/dc, dJ/dx, dJ/du).
+Every configuration prints one JSON line.
 """
 from __future__ import annotations
 
@@ -21,10 +34,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-WORKLOAD = dict(workload="linear elasticity element matrices, Q2 hex, "
-                "48^3 cells, 3x3x3 Gauss", cells=110592, order=2,
-                n_basis=27, n_qp=27, alpha=0.15, seed=0,
-                material="per-cell lambda,mu lognormal(0,0.5)")
+FP64_PEAK_TFLOPS = 78.6
+METRIC = ("element matrices/s (GElem/s) + HBM GB/s; FP64 vs mixed precision "
+          "at stated error")
 
 
 def parse():
@@ -32,12 +44,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=48, help="cells per axis")
+    ap.add_argument("--config", default="c2",
+                    choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--n", type=int, default=0, help="cells per axis")
     ap.add_argument("--precision", default="fp64",
                     choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--variant", default="auto")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the other precisions")
+                    help="skip the other precisions/variants")
     ap.add_argument("--no-cpu", action="store_true",
                     help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -48,19 +62,14 @@ def parse():
     return ap.parse_args()
 
 
-def alg_bytes_per_cell(mesh, out_itemsize, mat_itemsize):
-    """Algorithmic HBM bytes per cell: output written once, connectivity and
-    material read once, each unique node's coordinates read once."""
-    nd = 3 * mesh.n_basis
-    return (nd * nd * out_itemsize + mesh.n_basis * 4 + 2 * mat_itemsize
-            + mesh.n_nodes * 24.0 / mesh.n_cells)
+# --------------------------------------------------------------- helpers ---
 
-
-def time_plan(plan, X, C, M, out, steps, warmup):
+def time_calls(fn, steps, warmup):
+    """Wall time of `steps` calls (synchronised on both sides) and the HIP
+    event time of each call on the current stream."""
     import torch
     for _ in range(warmup):
-        plan(X, C, material=M, out=out)
-    plan.check()
+        fn()
     torch.cuda.synchronize()
     st = torch.cuda.current_stream()
     evs = [(torch.cuda.Event(enable_timing=True),
@@ -69,92 +78,100 @@ def time_plan(plan, X, C, M, out, steps, warmup):
     t0 = time.perf_counter()
     for a, b in evs:
         a.record(st)
-        plan(X, C, material=M, out=out)
+        fn()
         b.record(st)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    plan.check()
-    per = [a.elapsed_time(b) for a, b in evs]  # ms, each bracketing 1 launch
-    return wall, per
+    return wall, [a.elapsed_time(b) for a, b in evs]
 
 
-def sampled_error(orc, mesh, lm, out, n=48, seed=0):
+def mean(v):
+    return float(sum(v) / len(v))
+
+
+def tww_mean(v):
+    """Mean without the worst repetition (the paper's statistic)."""
+    v = sorted(v)
+    return mean(v[:-1]) if len(v) > 1 else float(v[0])
+
+
+def rel_err(got, ref):
     import numpy as np
-    import meshgen
+    n = ref.shape[0]
+    g = np.asarray(got, dtype=np.float64).reshape(n, -1)
+    r = ref.reshape(n, -1)
+    return float((np.abs(g - r).max(1) / np.abs(r).max(1)).max())
+
+
+def sample_cells(n_cells, k=48, seed=0):
+    import numpy as np
     rng = np.random.default_rng(seed)
-    idx = np.sort(rng.choice(mesh.n_cells, size=min(n, mesh.n_cells),
-                             replace=False))
-    idx = np.concatenate([idx, [0, mesh.n_cells - 1]])
-    sub = meshgen.Mesh(coords=mesh.coords, conn=mesh.conn[idx], cell="hex",
-                       order=mesh.order, h=mesh.h)
-    ref = orc.matrix(sub, "elasticity", lm[idx], "iso_cell")
-    import torch
-    got = out[torch.as_tensor(idx, device=out.device)].double().cpu().numpy()
-    scale = np.abs(ref).reshape(len(idx), -1).max(1)
-    err = np.abs(got - ref).reshape(len(idx), -1).max(1) / scale
-    return float(err.max())
+    idx = np.sort(rng.choice(n_cells, size=min(k, n_cells), replace=False))
+    return np.unique(np.concatenate([idx, [0, n_cells - 1]]))
 
 
-def cpu_baseline(orc, mesh, lm, budget_s):
-    """The oracle (as it stands) on a bounded sample of the same workload."""
-    import numpy as np
+def submesh(mesh, idx):
     import meshgen
+    return meshgen.Mesh(coords=mesh.coords, conn=mesh.conn[idx],
+                        cell=mesh.cell, order=mesh.order, h=mesh.h)
 
-    def run(k):
-        sub = meshgen.Mesh(coords=mesh.coords, conn=mesh.conn[:k],
-                           cell="hex", order=mesh.order, h=mesh.h)
-        t = time.perf_counter()
-        orc.matrix(sub, "elasticity", lm[:k], "iso_cell")
-        return time.perf_counter() - t
 
-    k = 256
-    t = run(k)
-    while t < 1.0 and k < mesh.n_cells:
-        k = min(mesh.n_cells, k * 4)
-        t = run(k)
-    # sample: the first k2 cells (at most the whole mesh), repeated until the
-    # budget is spent; the output of one pass is 52 KB per cell
-    k2 = int(min(mesh.n_cells, max(k, k * budget_s / max(t, 1e-3))))
-    reps, total_t = 0, 0.0
-    while total_t < budget_s and reps < 50:
-        total_t += run(k2)
+def oracle_rate(orc_call, n_cells, budget_s):
+    """Time the oracle (as it stands) on the first k cells, k grown until the
+    run takes about 1 s, then repeated until budget_s; cells/s."""
+    k = 64
+    t = orc_call(k)
+    while t < 1.0 and k < n_cells:
+        k = min(n_cells, k * 4)
+        t = orc_call(k)
+    k2 = int(min(n_cells, max(k, k * budget_s / max(t, 1e-3))))
+    reps, total = 0, 0.0
+    while total < budget_s and reps < 100000:
+        total += orc_call(k2)
         reps += 1
-    return dict(value=k2 * reps / total_t / 1e9, unit="GElem/s",
-                cores=orc.num_threads(), kind="oracle",
-                sample=f"first {k2} cells of the 48^3 Q2 mesh x {reps} "
-                       f"passes, FP64 element matrices, {total_t:.1f} s",
-                seconds=total_t, cells=k2 * reps)
+    return k2 * reps / total, k2, reps, total
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; "
-                          "--gpus must be 1", "n_gpus": args.gpus}))
-        sys.exit(2)
-    import numpy as np
+def copy_calibration(gib):
     import torch
+    if gib <= 0:
+        return
+    nbytes = int(gib * 2**30)
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
 
+
+def base_line(args, value, ms, dtype, config):
+    return {"metric": METRIC, "value": value, "unit": "GElem/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": dtype, "data": "synthetic",
+            "config": dict(config, parallelism="none")}
+
+
+# ------------------------------------------------------------------- c2 ---
+
+def alg_bytes_per_cell(mesh, nd, out_itemsize, mat_itemsize):
+    """Algorithmic HBM bytes per cell: output written once, connectivity and
+    material read once, each unique node's coordinates read once."""
+    return (nd * nd * out_itemsize + mesh.n_basis * 4 + 2 * mat_itemsize
+            + mesh.n_nodes * 24.0 / mesh.n_cells)
+
+
+def run_c2(args, orc):
+    import torch
     import meshgen
     import paper_2107_04121_amd as fe
-
     dev = torch.device("cuda:0")
-    if args.copy_calibration > 0:
-        nbytes = int(args.copy_calibration * 2**30)
-        src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    n = args.n
+    n = args.n or 48
     mesh = meshgen.hex_mesh(n, 2, alpha=0.15, seed=0)
     lm = meshgen.lame_cell(mesh.n_cells, seed=0)
     X = torch.from_numpy(mesh.coords).to(dev)
     C = torch.from_numpy(mesh.conn).to(dev)
-
-    import oracle  # test infrastructure: error vs FP64 oracle, CPU baseline
-    oracle.build()
-
+    idx = sample_cells(mesh.n_cells)
+    ref = orc.matrix(submesh(mesh, idx), "elasticity", lm[idx], "iso_cell")
     results = {}
     precs = [args.precision] + ([] if args.no_extra else
                                 [p for p in ("fp64", "fp32", "bf16x3")
@@ -166,60 +183,420 @@ def main():
         except fe.FeError as e:
             results[prec] = {"error": str(e)}
             continue
-        dt = plan.dtype
-        M = torch.from_numpy(lm).to(dev).to(dt)
-        out = torch.empty(plan.out_shape(mesh.n_cells), dtype=dt, device=dev)
-        wall, per = time_plan(plan, X, C, M, out, args.steps, args.warmup)
+        M = torch.from_numpy(lm).to(dev).to(plan.dtype)
+        out = torch.empty(plan.out_shape(mesh.n_cells), dtype=plan.dtype,
+                          device=dev)
+        wall, per = time_calls(lambda: plan(X, C, material=M, out=out),
+                               args.steps, args.warmup)
+        plan.check()
         ms = wall * 1e3 / args.steps
-        kern_ms = float(np.mean(per))
-        bpc = alg_bytes_per_cell(mesh, out.element_size(), M.element_size())
-        gbs = bpc * mesh.n_cells / (kern_ms * 1e-3) / 1e9
-        err = sampled_error(oracle, mesh, lm, out)
+        kern_ms = mean(per)
+        bpc = alg_bytes_per_cell(mesh, 81, out.element_size(),
+                                 M.element_size())
+        err = rel_err(out[torch.as_tensor(idx, device=dev)].cpu().numpy(),
+                      ref)
         results[prec] = dict(ms_per_step=ms, kernel_ms=kern_ms,
-                             kernel_ms_min=float(np.min(per)),
+                             kernel_ms_tww=tww_mean(per),
+                             kernel_ms_min=float(min(per)),
                              gelem_s=mesh.n_cells / (ms * 1e-3) / 1e9,
-                             alg_bytes_per_cell=bpc, hbm_gbs=gbs,
+                             alg_bytes_per_cell=bpc,
+                             hbm_gbs=bpc * mesh.n_cells / (kern_ms * 1e-3)
+                             / 1e9,
                              variant=plan.variant, max_rel_err=err)
         del out
         torch.cuda.empty_cache()
     prim = results[args.precision]
     if "error" in prim:
-        print(json.dumps({"error": prim["error"]}))
-        sys.exit(1)
-    line = {
-        "metric": "element matrices/s (GElem/s) + HBM GB/s; FP64 vs mixed "
-                  "precision at stated error",
-        "value": prim["gelem_s"],
-        "unit": "GElem/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": prim["ms_per_step"],
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[
-            args.precision],
-        "data": "synthetic",
-        "config": dict(WORKLOAD, cells=mesh.n_cells, parallelism="none"),
-        "hbm_gbs": prim["hbm_gbs"],
-        "max_rel_err_vs_fp64_oracle": prim["max_rel_err"],
-        "roofline": {
-            "bound": "hbm",
-            "achieved": prim["hbm_gbs"],
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": prim["hbm_gbs"] / HBM_PEAK_GBS,
-            "traffic": None,
-            "kernel": "element-matrix kernel (" + prim["variant"] + ")",
-            "kernel_ms": prim["kernel_ms"],
-        },
-        "precisions": results,
-    }
+        return {"error": prim["error"]}
+    line = base_line(args, prim["gelem_s"], prim["ms_per_step"],
+                     {"fp64": "f64", "fp32": "f32",
+                      "bf16x3": "bf16x3"}[args.precision],
+                     dict(workload="linear elasticity element matrices, Q2 "
+                          "hex, 48^3 cells, 3x3x3 Gauss", cells=mesh.n_cells,
+                          order=2, n_basis=27, n_qp=27, alpha=0.15, seed=0,
+                          material="per-cell lambda,mu lognormal(0,0.5)"))
+    line["hbm_gbs"] = prim["hbm_gbs"]
+    line["max_rel_err_vs_fp64_oracle"] = prim["max_rel_err"]
+    line["roofline"] = {"bound": "hbm", "achieved": prim["hbm_gbs"],
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": prim["hbm_gbs"] / HBM_PEAK_GBS,
+                        "traffic": None,
+                        "kernel": "k_elast_q2 (" + prim["variant"] + ")",
+                        "kernel_ms": prim["kernel_ms"]}
+    line["precisions"] = results
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(oracle, mesh, lm,
-                                            args.cpu_seconds)
+        def call(k):
+            t = time.perf_counter()
+            orc.matrix(submesh(mesh, slice(0, k)), "elasticity", lm[:k],
+                       "iso_cell")
+            return time.perf_counter() - t
+        rate, k2, reps, tot = oracle_rate(call, mesh.n_cells,
+                                          args.cpu_seconds)
+        line["cpu_baseline"] = {
+            "value": rate / 1e9, "unit": "GElem/s",
+            "cores": orc.num_threads(), "kind": "oracle",
+            "sample": f"first {k2} cells of the 48^3 Q2 mesh x {reps} "
+                      f"passes, FP64 element matrices, {tot:.1f} s"}
+    return line
+
+
+# ------------------------------------------------------------------- c1 ---
+
+def run_c1(args, orc):
+    import torch
+    import meshgen
+    import paper_2107_04121_amd as fe
+    dev = torch.device("cuda:0")
+    n = args.n or 16
+    mesh = meshgen.hex_mesh(n, 1, alpha=0.2, seed=0)
+    U = meshgen.dofs(mesh.n_nodes, 1, seed=0)
+    X = torch.from_numpy(mesh.coords).to(dev)
+    C = torch.from_numpy(mesh.conn).to(dev)
+    Ut = torch.from_numpy(U).to(dev)
+    pm = fe.Plan("hex", 1, "laplace", "matrix", "fp64")
+    pr = fe.Plan("hex", 1, "laplace", "residual", "fp64")
+    K = torch.empty(pm.out_shape(mesh.n_cells), dtype=torch.float64,
+                    device=dev)
+    r = torch.empty(pr.out_shape(mesh.n_cells), dtype=torch.float64,
+                    device=dev)
+
+    def step():
+        pm(X, C, out=K)
+        pr(X, C, dofs=Ut, out=r)
+
+    wall, per = time_calls(step, args.steps, args.warmup)
+    pm.check()
+    pr.check()
+    _, per_m = time_calls(lambda: pm(X, C, out=K), args.steps, 1)
+    _, per_r = time_calls(lambda: pr(X, C, dofs=Ut, out=r), args.steps, 1)
+    err_m = rel_err(K.cpu().numpy(), orc.matrix(mesh, "laplace"))
+    err_r = rel_err(r.cpu().numpy(), orc.residual(mesh, "laplace", U))
+    ms = wall * 1e3 / args.steps
+    # size sweep of the matrix kernel for the HBM roof
+    sweep = {}
+    for m in ([16, 32, 64, 96, 128] if not args.no_extra else []):
+        msh = meshgen.hex_mesh(m, 1, alpha=0.2, seed=0)
+        Xs = torch.from_numpy(msh.coords).to(dev)
+        Cs = torch.from_numpy(msh.conn).to(dev)
+        Ks = torch.empty(pm.out_shape(msh.n_cells), dtype=torch.float64,
+                         device=dev)
+        _, p2 = time_calls(lambda: pm(Xs, Cs, out=Ks), 10, 2)
+        bpc = 512 + 32 + msh.n_nodes * 24.0 / msh.n_cells
+        kms = mean(p2)
+        sweep[f"{m}^3"] = dict(cells=msh.n_cells, kernel_ms=kms,
+                               gelem_s=msh.n_cells / (kms * 1e-3) / 1e9,
+                               hbm_gbs=bpc * msh.n_cells / (kms * 1e-3) / 1e9)
+        del Ks, Xs, Cs
+    torch.cuda.empty_cache()
+    bpc = 512 + 32 + mesh.n_nodes * 24.0 / mesh.n_cells
+    kms = mean(per_m)
+    line = base_line(args, mesh.n_cells / (ms * 1e-3) / 1e9, ms, "f64",
+                     dict(workload="Q1 Laplace element matrices + residual, "
+                          f"{n}^3 cells, 2x2x2 Gauss", cells=mesh.n_cells,
+                          order=1, alpha=0.2, seed=0))
+    line["matrix"] = dict(kernel_ms=kms, variant=pm.variant,
+                          gelem_s=mesh.n_cells / (kms * 1e-3) / 1e9,
+                          hbm_gbs=bpc * mesh.n_cells / (kms * 1e-3) / 1e9,
+                          max_rel_err=err_m)
+    line["residual"] = dict(kernel_ms=mean(per_r), variant=pr.variant,
+                            gelem_s=mesh.n_cells / (mean(per_r) * 1e-3)
+                            / 1e9, max_rel_err=err_r)
+    big = sweep.get("128^3")
+    if big:
+        line["roofline"] = {"bound": "hbm", "achieved": big["hbm_gbs"],
+                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": big["hbm_gbs"] / HBM_PEAK_GBS,
+                            "traffic": None,
+                            "kernel": "k_matrix<hex,1,laplace> at 128^3",
+                            "kernel_ms": big["kernel_ms"]}
+    line["sweep"] = sweep
+    if not args.no_cpu:
+        def call(k):
+            t = time.perf_counter()
+            sub = submesh(mesh, slice(0, k))
+            orc.matrix(sub, "laplace")
+            orc.residual(sub, "laplace", U)
+            return time.perf_counter() - t
+        rate, k2, reps, tot = oracle_rate(call, mesh.n_cells,
+                                          args.cpu_seconds)
+        line["cpu_baseline"] = {
+            "value": rate / 1e9, "unit": "GElem/s",
+            "cores": orc.num_threads(), "kind": "oracle",
+            "sample": f"{k2} cells x {reps} passes of matrix + residual, "
+                      f"{tot:.1f} s"}
+    return line
+
+
+# ------------------------------------------------------------------- c3 ---
+
+def run_c3(args, orc):
+    import numpy as np
+    import torch
+    import meshgen
+    import paper_2107_04121_amd as fe
+    dev = torch.device("cuda:0")
+    n = args.n or 96
+    mesh = meshgen.hex_mesh(n, 3, alpha=0.15, seed=0)
+    lm = meshgen.lame_cell(mesh.n_cells, seed=0)
+    X = torch.from_numpy(mesh.coords).to(dev)
+    C = torch.from_numpy(mesh.conn).to(dev)
+    M = torch.from_numpy(lm).to(dev).float()
+    idx = sample_cells(mesh.n_cells, 24)
+    sub = submesh(mesh, idx)
+    res = {}
+    for form, nc in (("laplace", 1), ("elasticity", 3)):
+        U = meshgen.dofs(mesh.n_nodes, nc, seed=0)
+        Ut = torch.from_numpy(U).to(dev).float()
+        mat, kind = (M, "iso_cell") if form == "elasticity" else (None, None)
+        ref = orc.residual(sub, form, U, lm[idx] if mat is not None else None,
+                           kind)
+        variants = [("sumfact", "cell_major"), ("sumfact", "cell_minor")]
+        if not args.no_extra:
+            variants += [("generic", "cell_major"),
+                         ("matrix_first", "cell_major")]
+        for variant, layout in variants:
+            plan = fe.Plan("hex", 3, form, "residual", "fp32", material=kind,
+                           variant=variant, layout=layout)
+            out = torch.empty(plan.out_shape(mesh.n_cells),
+                              dtype=torch.float32, device=dev)
+            ws = plan.workspace(mesh.n_cells, dev)
+            steps = args.steps if variant == "sumfact" else 1
+            warm = args.warmup if variant == "sumfact" else 0
+            wall, per = time_calls(
+                lambda: plan(X, C, material=mat, dofs=Ut, out=out,
+                             workspace=ws), steps, warm)
+            plan.check()
+            got = out.cpu().numpy()
+            if layout == "cell_minor":
+                got = np.moveaxis(got, -1, 0)
+            err = rel_err(got[idx], ref)
+            bpc = (mesh.n_nodes * (24 + 4 * nc) / mesh.n_cells + 64 * 4
+                   + 64 * nc * 4 + (8 if kind else 0))
+            kms = mean(per)
+            res[f"{form}/{variant}/{layout}"] = dict(
+                kernel_ms=kms, gelem_s=mesh.n_cells / (kms * 1e-3) / 1e9,
+                hbm_gbs=bpc * mesh.n_cells / (kms * 1e-3) / 1e9,
+                max_rel_err=err, steps=steps)
+            del out, ws
+            plan._ws = None
+            torch.cuda.empty_cache()
+    prim = res["elasticity/sumfact/cell_major"]
+    tot_ms = prim["kernel_ms"] + res["laplace/sumfact/cell_major"][
+        "kernel_ms"]
+    line = base_line(args, mesh.n_cells / (prim["kernel_ms"] * 1e-3) / 1e9,
+                     tot_ms, "f32",
+                     dict(workload="Q3 hex residuals (Laplace + elasticity),"
+                          f" {n}^3 cells, 4x4x4 Gauss, FP32 with FP64 "
+                          "geometry", cells=mesh.n_cells, order=3,
+                          alpha=0.15, seed=0))
+    # sum-factorized elasticity per cell: FP64 geometry (3 fields x 2048
+    # FMA + inverse) and FP32 gradients, flux, test contraction
+    flops = 2 * (3 * 2048 + 64 * 60) + 2 * (6 * 2048 + 64 * 120)
+    achieved = flops * mesh.n_cells / (prim["kernel_ms"] * 1e-3) / 1e12
+    line["roofline"] = {"bound": "alu", "achieved": achieved,
+                        "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": achieved / FP64_PEAK_TFLOPS,
+                        "traffic": None,
+                        "kernel": "k_sf<3,elasticity,float>",
+                        "kernel_ms": prim["kernel_ms"],
+                        "hbm_frac": prim["hbm_gbs"] / HBM_PEAK_GBS}
+    line["paths"] = res
+    if not args.no_cpu:
+        U3 = meshgen.dofs(mesh.n_nodes, 3, seed=0)
+
+        def call(k):
+            t = time.perf_counter()
+            orc.residual(submesh(mesh, slice(0, k)), "elasticity", U3,
+                         lm[:k], "iso_cell")
+            return time.perf_counter() - t
+        rate, k2, reps, tot = oracle_rate(call, mesh.n_cells,
+                                          args.cpu_seconds)
+        line["cpu_baseline"] = {
+            "value": rate / 1e9, "unit": "GElem/s",
+            "cores": orc.num_threads(), "kind": "oracle",
+            "sample": f"{k2} Q3 cells x {reps} passes, elasticity residual "
+                      f"FP64, {tot:.1f} s"}
+    return line
+
+
+# ------------------------------------------------------------------- c4 ---
+
+C4_GROUPS = [("tet", 1, (50, 40, 25)), ("tet", 2, (40, 25, 20)),
+             ("hex", 1, (100, 50, 40)), ("hex", 2, (40, 40, 25))]
+
+
+def run_c4(args, orc):
+    import numpy as np
+    import torch
+    import meshgen
+    import paper_2107_04121_amd as fe
+    dev = torch.device("cuda:0")
+    ss = np.random.SeedSequence(0).spawn(4)
+    groups, meshes = [], []
+    for (cell, p, dims), s in zip(C4_GROUPS, ss):
+        seed = int(s.generate_state(1)[0])
+        m = (meshgen.tet_mesh(dims, p, alpha=0.15, seed=seed) if cell == "tet"
+             else meshgen.hex_mesh(dims, p, alpha=0.15, seed=seed))
+        lm = meshgen.lame_cell(m.n_cells, seed=seed)
+        meshes.append((m, lm))
+        groups.append(dict(cell=cell, order=p,
+                           coords=torch.from_numpy(m.coords).to(dev),
+                           conn=torch.from_numpy(m.conn).to(dev),
+                           material=torch.from_numpy(lm).to(dev).float(),
+                           forms=("mass", "laplace", "elasticity")))
+    n_cells = sum(m.n_cells for m, _ in meshes)
+    out_bytes = sum(m.n_cells * 4 * (2 * m.n_basis ** 2 + 9 * m.n_basis ** 2)
+                    for m, _ in meshes)
+    tuned = fe.Batch(groups, precision="fp32", autotune=True)
+    wall, per = time_calls(tuned.run, args.steps, args.warmup)
+    tuned.check()
+    errs = {}
+    for (m, lm), o in zip(meshes, tuned.outputs):
+        idx = sample_cells(m.n_cells, 16)
+        sub = submesh(m, idx)
+        ti = torch.as_tensor(idx, device=dev)
+        errs[f"{m.cell}{m.order}"] = max(
+            rel_err(o["mass"][ti].cpu().numpy(), orc.matrix(sub, "mass")),
+            rel_err(o["laplace"][ti].cpu().numpy(),
+                    orc.matrix(sub, "laplace")),
+            rel_err(o["elasticity"][ti].cpu().numpy(),
+                    orc.matrix(sub, "elasticity", lm[idx], "iso_cell")))
+    tiles = tuned.tiles
+    del tuned
+    torch.cuda.empty_cache()
+    extra = {}
+    if not args.no_extra:
+        default = fe.Batch(groups, precision="fp32", autotune=False)
+        _, pd = time_calls(default.run, args.steps, args.warmup)
+        extra["untuned_batch_ms"] = mean(pd)
+        extra["untuned_tiles"] = default.tiles
+        del default
+        torch.cuda.empty_cache()
+        # the same work as 12 separate single-form launches
+        plans = []
+        for g, (m, lm) in zip(groups, meshes):
+            for form in ("mass", "laplace", "elasticity"):
+                kind = "iso_cell" if form == "elasticity" else None
+                pl = fe.Plan(g["cell"], g["order"], form, "matrix", "fp32",
+                             material=kind)
+                o = torch.empty(pl.out_shape(m.n_cells), dtype=torch.float32,
+                                device=dev)
+                plans.append((pl, g, o, kind))
+
+        def separate():
+            for pl, g, o, kind in plans:
+                pl(g["coords"], g["conn"],
+                   material=g["material"] if kind else None, out=o)
+
+        _, ps = time_calls(separate, args.steps, args.warmup)
+        extra["separate_launches_ms"] = mean(ps)
+        extra["separate_variants"] = [pl.variant for pl, *_ in plans]
+        del plans
+        torch.cuda.empty_cache()
+    ms = wall * 1e3 / args.steps
+    kms = mean(per)
+    gbs = out_bytes / (kms * 1e-3) / 1e9
+    line = base_line(args, n_cells / (ms * 1e-3) / 1e9, ms, "f32",
+                     dict(workload="batched uneven mesh in one graph launch:"
+                          " 300k P1 tet, 120k P2 tet, 200k Q1 hex, 40k Q2 "
+                          "hex; mass + Laplace + elasticity each",
+                          cells=n_cells, alpha=0.15, seed=0))
+    line["batch_ms"] = kms
+    line["tiles"] = tiles
+    line["out_gb"] = out_bytes / 1e9
+    line["max_rel_err_vs_fp64_oracle"] = errs
+    line["roofline"] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                        "traffic": None, "kernel": "k_batch<float>",
+                        "kernel_ms": kms}
+    line.update(extra)
+    return line
+
+
+# ------------------------------------------------------------------- c5 ---
+
+def run_c5(args, orc):
+    import numpy as np
+    import torch
+    import meshgen
+    import paper_2107_04121_amd as fe
+    dev = torch.device("cuda:0")
+    n = args.n or 32
+    mesh = meshgen.hex_mesh(n, 2, alpha=0.15, seed=0)
+    c = meshgen.lame_qp(mesh.n_cells, 27, seed=0)
+    U = meshgen.dofs(mesh.n_nodes, 3, seed=0)
+    C = torch.from_numpy(mesh.conn).to(dev)
+    gm_ref, gx_ref = orc.energy_grad(mesh, c, U)
+    J_ref = orc.energy(mesh, "elasticity", U, c, "iso_qp").sum()
+    out = {}
+    for prec in ("fp64", "fp32"):
+        ep = fe.ElasticEnergyPlan("hex", 2, C, mesh.n_nodes, prec)
+        dt = ep.eval.dtype
+        ct = torch.from_numpy(c).to(dev).to(dt).requires_grad_(True)
+        xt = torch.from_numpy(mesh.coords).to(dev).requires_grad_(True)
+        ut = torch.from_numpy(U).to(dev).to(dt).requires_grad_(True)
+
+        def step():
+            ct.grad = xt.grad = ut.grad = None
+            J = fe.ElasticEnergy(ct, xt, ut, ep)
+            J.backward()
+            return J
+
+        wall, per = time_calls(step, args.steps, args.warmup)
+        J = step()
+        torch.cuda.synchronize()
+
+        def rel(a, b):
+            return float(np.abs(a - b).max() / np.abs(b).max())
+
+        out[prec] = dict(ms_per_step=wall * 1e3 / args.steps,
+                         event_ms=mean(per),
+                         err_J=abs(float(J) - J_ref) / abs(J_ref),
+                         err_dJdc=rel(ct.grad.cpu().numpy(), gm_ref),
+                         err_dJdx=rel(xt.grad.cpu().numpy(), gx_ref))
+        del ep
+        torch.cuda.empty_cache()
+    p = out["fp64"]
+    line = base_line(args, mesh.n_cells / (p["ms_per_step"] * 1e-3) / 1e9,
+                     p["ms_per_step"], "f64",
+                     dict(workload="adjoint of J = sum u^T K u, Q2 "
+                          f"elasticity, {n}^3 cells, per-point lambda,mu: "
+                          "forward + dJ/dc, dJ/dx, dJ/du", cells=mesh.n_cells,
+                          order=2, alpha=0.15, seed=0))
+    line["precisions"] = out
+    if not args.no_cpu:
+        def call(k):
+            t = time.perf_counter()
+            sub = submesh(mesh, slice(0, k))
+            orc.energy(sub, "elasticity", U, c[:k], "iso_qp")
+            orc.energy_grad(sub, c[:k], U)
+            return time.perf_counter() - t
+        rate, k2, reps, tot = oracle_rate(call, mesh.n_cells,
+                                          args.cpu_seconds)
+        line["cpu_baseline"] = {
+            "value": rate / 1e9, "unit": "GElem/s",
+            "cores": orc.num_threads(), "kind": "oracle",
+            "sample": f"{k2} cells x {reps} passes of energy + gradient, "
+                      f"{tot:.1f} s"}
+    return line
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; "
+                          "--gpus must be 1", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch  # noqa: F401
+    import oracle  # test infrastructure: error vs FP64 oracle, CPU baseline
+    oracle.build()
+    copy_calibration(args.copy_calibration)
+    fn = {"c1": run_c1, "c2": run_c2, "c3": run_c3, "c4": run_c4,
+          "c5": run_c5}[args.config]
+    line = fn(args, oracle)
     print(json.dumps(line))
+    if "error" in line:
+        sys.exit(1)
 
 
 if __name__ == "__main__":
