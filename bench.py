@@ -35,6 +35,30 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+# HBM bytes per launch of a kernel, from two rocprofv3 --pmc passes
+# (FETCH_SIZE, WRITE_SIZE) scaled by what the same counters read for a 1 GiB
+# copy (fetch x2.0, write x1.0).  A figure holds only for the sources it was
+# measured on: when their hash differs the field is reported as null.
+MEASURED_TRAFFIC = {
+    "k_elast_q2<0>": dict(bytes=5997870916, sha256="9bc9db275becd16f",
+                          sources=["k_mfma.hip", "q2_device.h",
+                                   "fe_device.h"]),
+}
+
+
+def traffic(kernel):
+    import hashlib
+    m = MEASURED_TRAFFIC.get(kernel)
+    if m is None:
+        return None
+    h = hashlib.sha256()
+    for f in m["sources"]:
+        with open(os.path.join(ROOT, "paper_2107_04121_amd", "csrc", f),
+                  "rb") as fh:
+            h.update(fh.read())
+    return m["bytes"] if h.hexdigest()[:16] == m["sha256"] else None
+
+
 METRIC = ("element matrices/s (GElem/s) + HBM GB/s; FP64 vs mixed precision "
           "at stated error")
 
@@ -220,7 +244,9 @@ def run_c2(args, orc):
     line["roofline"] = {"bound": "hbm", "achieved": prim["hbm_gbs"],
                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": prim["hbm_gbs"] / HBM_PEAK_GBS,
-                        "traffic": None,
+                        "traffic": (traffic("k_elast_q2<0>")
+                                    if args.precision == "fp64"
+                                    and prim["variant"] == "mfma" else None),
                         "kernel": "k_elast_q2 (" + prim["variant"] + ")",
                         "kernel_ms": prim["kernel_ms"]}
     line["precisions"] = results
