@@ -106,7 +106,8 @@ typedef enum {
     FE_VARIANT_GENERIC = 1,   /* reference-table VALU kernel, any cell/order */
     FE_VARIANT_MFMA = 2,      /* matrix mode: per-element GEMM on matrix cores */
     FE_VARIANT_SUMFACT = 3,   /* hex residual/eval: sum-factorized, gradient-first */
-    FE_VARIANT_MATRIX_FIRST = 4 /* residual: form K_e then K_e u_e */
+    FE_VARIANT_MATRIX_FIRST = 4, /* residual: form K_e then K_e u_e */
+    FE_VARIANT_CELLWISE = 5      /* matrix mode, Q1/P1/P2: one cell per lane, registers */
 } fe_variant;
 
 /* Residual output layout: CELL_MAJOR [n_cells][n_comp][n_basis] (the

@@ -16,7 +16,7 @@ MODES = {"matrix": 0, "residual": 1, "eval": 2}
 PRECS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 MATS = {None: 0, "none": 0, "iso_cell": 1, "iso_qp": 2, "voigt_qp": 3}
 VARIANTS = {"auto": 0, "generic": 1, "mfma": 2, "sumfact": 3,
-            "matrix_first": 4}
+            "matrix_first": 4, "cellwise": 5}
 VARIANT_NAMES = {v: k for k, v in VARIANTS.items()}
 
 FE_OK = 0

@@ -156,6 +156,7 @@ int fe_plan_create(int cell, int order, int form, int mode, int precision, int m
         Plan pm = *p;
         pm.mode = FE_MODE_MATRIX;
         LaunchFn fm = select_mfma(pm);
+        if (!fm) fm = select_cellwise(pm);
         if (!fm) fm = select_generic(pm);
         if (!fm) {
             delete p;
@@ -167,6 +168,9 @@ int fe_plan_create(int cell, int order, int form, int mode, int precision, int m
     }
     if (want == FE_VARIANT_AUTO || want == FE_VARIANT_MFMA) {
         if (mode == FE_MODE_MATRIX && (fn = select_mfma(*p))) variant = FE_VARIANT_MFMA;
+    }
+    if (!fn && (want == FE_VARIANT_AUTO || want == FE_VARIANT_CELLWISE)) {
+        if (mode == FE_MODE_MATRIX && (fn = select_cellwise(*p))) variant = FE_VARIANT_CELLWISE;
     }
     if (!fn && (want == FE_VARIANT_AUTO || want == FE_VARIANT_SUMFACT)) {
         if (mode != FE_MODE_MATRIX && (fn = select_sumfact(*p))) variant = FE_VARIANT_SUMFACT;

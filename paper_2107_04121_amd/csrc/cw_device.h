@@ -1,0 +1,183 @@
+// Cell-per-lane device routines for low-order cells (P1/P2 tetrahedra, Q1
+// hexahedra): every lane owns one cell, gathers its node coordinates into
+// registers or LDS, evaluates the FP64 geometry at each quadrature point
+// itself and accumulates its element-matrix entries in registers.  Table
+// offsets depend only on the quadrature point and basis index, which are the
+// same for every lane of a wave, so table reads go through the scalar unit.
+//
+// Geometry: J_ij = sum_a x_a,i dphi_a/dxi_j (section "Notation"), adj J by
+// cofactors, det J = J_0. . adj_.0.  Instead of G = dphi/dxi J^-1 the routines
+// keep H = dphi/dxi adj J = det J * G, and fold the determinant into the
+// per-point weight: w det J G_a.G_b = (w / det J) H_a.H_b.  The results equal
+// the definitions up to rounding.
+#pragma once
+
+#include "fe_device.h"
+
+namespace fe {
+namespace cw {
+
+// The reference tables are never written while a kernel runs.  Reading them
+// through the constant address space lets the compiler use scalar loads for
+// the wave-uniform offsets even in kernels that also write global memory.
+typedef __attribute__((address_space(4))) const double ctab_t;
+__device__ __forceinline__ const ctab_t *ctab(const double *p) { return (const ctab_t *)p; }
+
+template <int CELL, int P>
+struct Shape {
+    static constexpr int NB = cell_nb(CELL, P), NQ = cell_nq(CELL, P);
+    // P1 basis gradients are constant: the Jacobian is the same at every point
+    static constexpr bool AFFINE = CELL == FE_CELL_TET && P == 1;
+};
+
+// Coordinates of a lane's cell held in registers.
+template <int NB>
+struct XReg {
+    double v[NB][3];
+    __device__ __forceinline__ double operator()(int a, int i) const { return v[a][i]; }
+};
+
+// Coordinates of a lane's cell in LDS: row of NB*3 doubles plus one pad
+// word, so lanes reading the same entry of their own rows spread over banks.
+template <int NB>
+struct XLds {
+    static constexpr int STRIDE = NB * 3 + 1;
+    const double *row;
+    __device__ __forceinline__ double operator()(int a, int i) const { return row[a * 3 + i]; }
+};
+
+// Node coordinates of cell e (a lane's own cell) into registers.  Invalid
+// lanes read node 0.  An out-of-range node number reads node 0 and sets
+// FAULT_INDEX in the returned bits.  Faults are collected in registers and
+// raised once at the end of a kernel: a global atomic before the quadrature
+// loop would keep the compiler from reading the reference tables through the
+// scalar unit (it could not prove them unmodified).
+template <int NB>
+__device__ __forceinline__ unsigned gather(const int32_t *__restrict__ conn, const double *__restrict__ coords,
+                                           int64_t e, int64_t n_nodes, bool valid, XReg<NB> &xr)
+{
+    unsigned fault = 0;
+    int32_t nd[NB];
+    if constexpr (NB % 4 == 0) {
+        const int4 *c4 = reinterpret_cast<const int4 *>(conn + (valid ? e : 0) * NB);
+#pragma unroll
+        for (int k = 0; k < NB / 4; k++) {
+            const int4 v = c4[k];
+            nd[4 * k] = v.x;
+            nd[4 * k + 1] = v.y;
+            nd[4 * k + 2] = v.z;
+            nd[4 * k + 3] = v.w;
+        }
+    } else if constexpr (NB % 2 == 0) {
+        const int2 *c2 = reinterpret_cast<const int2 *>(conn + (valid ? e : 0) * NB);
+#pragma unroll
+        for (int k = 0; k < NB / 2; k++) {
+            const int2 v = c2[k];
+            nd[2 * k] = v.x;
+            nd[2 * k + 1] = v.y;
+        }
+    } else {
+#pragma unroll
+        for (int a = 0; a < NB; a++) nd[a] = conn[(valid ? e : 0) * NB + a];
+    }
+#pragma unroll
+    for (int a = 0; a < NB; a++) {
+        int64_t n = nd[a];
+        if (n < 0 || n >= n_nodes) {
+            if (valid) fault |= FAULT_INDEX;
+            n = 0;
+        }
+        xr.v[a][0] = coords[3 * n];
+        xr.v[a][1] = coords[3 * n + 1];
+        xr.v[a][2] = coords[3 * n + 2];
+    }
+    return fault;
+}
+
+// Jacobian at point q from coordinates x(a, i) (registers or LDS), its
+// adjugate (adj[j][i] = det J * (J^-1)_ji) and det J.
+template <int NB, int NQ, typename X>
+__device__ __forceinline__ double jac_adj(const X &x, const ctab_t *bfgT, int q, double (&adj)[3][3])
+{
+    double J[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) J[i][j] = 0.0;
+#pragma unroll
+    for (int a = 0; a < NB; a++) {
+        const double x0 = x(a, 0), x1 = x(a, 1), x2 = x(a, 2);
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            const double g = bfgT[(a * 3 + j) * NQ + q];
+            J[0][j] = fma(x0, g, J[0][j]);
+            J[1][j] = fma(x1, g, J[1][j]);
+            J[2][j] = fma(x2, g, J[2][j]);
+        }
+    }
+    adj[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    adj[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    adj[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    adj[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+    adj[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+    adj[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+    adj[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+    adj[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+    adj[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    return J[0][0] * adj[0][0] + J[0][1] * adj[1][0] + J[0][2] * adj[2][0];
+}
+
+// Cooperative gather of the node coordinates of cells e0 .. e0+63 into LDS
+// rows xs[c * XLds<NB>::STRIDE + a * 3 + i] (threads 0 .. nthreads-1);
+// returns this thread's fault bits like gather().
+template <int NB>
+__device__ __forceinline__ unsigned gather_lds(const int32_t *__restrict__ conn, const double *__restrict__ coords,
+                                               int64_t e0, int64_t n_cells, int64_t n_nodes, double *xs, int tid,
+                                               int nthreads)
+{
+    unsigned fault = 0;
+    for (int t = tid; t < 64 * NB; t += nthreads) {
+        const int c = t / NB, a = t - c * NB;
+        const int64_t e = e0 + c;
+        double x0 = 0.0, x1 = 0.0, x2 = 0.0;
+        if (e < n_cells) {
+            int64_t n = conn[e * NB + a];
+            if (n < 0 || n >= n_nodes) {
+                fault |= FAULT_INDEX;
+                n = 0;
+            }
+            x0 = coords[3 * n];
+            x1 = coords[3 * n + 1];
+            x2 = coords[3 * n + 2];
+        }
+        double *r = xs + c * XLds<NB>::STRIDE + a * 3;
+        r[0] = x0;
+        r[1] = x1;
+        r[2] = x2;
+    }
+    return fault;
+}
+
+// H_a[i] = sum_j dphi_a/dxi_j(q) adj[j][i] (FP64), for component i.
+template <int NB, int NQ>
+__device__ __forceinline__ double h_comp(const ctab_t *bfgT, const double (&adj)[3][3], int q, int a,
+                                         int i)
+{
+    return bfgT[(a * 3 + 0) * NQ + q] * adj[0][i] + bfgT[(a * 3 + 1) * NQ + q] * adj[1][i] +
+           bfgT[(a * 3 + 2) * NQ + q] * adj[2][i];
+}
+
+// Index of (a, b), a <= b, in packed upper-triangle storage.
+__host__ __device__ constexpr int tri(int a, int b, int n) { return a * n - a * (a - 1) / 2 + (b - a); }
+
+// Largest divisor of n whose chunk of 64 cells x rc rows x nd columns (plus
+// one pad entry per cell) fits in cap bytes.
+constexpr int pick_rows(int n, int nd, int esize, int cap)
+{
+    for (int rc = n; rc >= 1; rc--)
+        if (n % rc == 0 && 64 * (rc * nd + 1) * esize <= cap) return rc;
+    return 1;
+}
+
+}  // namespace cw
+}  // namespace fe

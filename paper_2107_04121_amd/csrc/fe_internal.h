@@ -86,6 +86,7 @@ void set_error(const std::string &msg);
 LaunchFn select_generic(const Plan &p);
 LaunchFn select_mfma(const Plan &p);
 LaunchFn select_sumfact(const Plan &p);
+LaunchFn select_cellwise(const Plan &p);
 
 int n_comp_of(int form);
 size_t matrix_first_bytes(const Plan &p, int64_t n_cells);

@@ -1,0 +1,398 @@
+// Cell-per-lane element-matrix kernels for low-order cells (Q1 hexahedra,
+// P1/P2 tetrahedra): Algorithm "feloopm" with the cell loop spread over the
+// lanes of a wave and the quadrature loop kept in each lane's registers.
+//
+//   k_cw_scalar  mass ('i,i', scalar and vector) and Laplace ('0.i,0.i'):
+//                one wave of 64 lanes = 64 cells; each lane accumulates the
+//                upper triangle of its cell's symmetric matrix.
+//   k_cw_elast   isotropic linear elasticity: six waves per workgroup, wave w
+//                computes block (r,s), r <= s, of the same 64 cells.  With
+//                H = dphi/dxi adj J and s_q = w_q / det J (see cw_device.h):
+//                  K_rs[a][b] = sum_q s_q (lambda H_r[a] H_s[b] + mu H_s[a] H_r[b])
+//                  K_rr[a][b] = sum_q s_q ((lambda + mu) H_r[a] H_r[b] + mu H_a . H_b)
+//                which is w det J B^T D B of section "Linear Elasticity
+//                Expression" for the isotropic D, block by block; K_sr = K_rs^T.
+//
+// Output: every kernel stages a chunk of rows of its 64 cells in LDS (one
+// padded row set per cell, so the lane-per-cell writes spread over the LDS
+// banks) and then stores the chunk with consecutive threads on consecutive
+// entries, so global stores are contiguous runs instead of one stream per
+// lane.
+#include "cw_device.h"
+
+namespace fe {
+namespace {
+
+using namespace cw;
+
+constexpr int SCALAR_STAGE = 12 * 1024;
+constexpr int ELAST_STAGE = 28 * 1024;
+constexpr int ELAST_THREADS = 384;
+
+template <typename T>
+__device__ __forceinline__ void st_nt(T *p, T v)
+{
+    __builtin_nontemporal_store(v, p);
+}
+
+template <int CELL, int P, int FORM, typename T>
+struct CwScalar {
+    using S = Shape<CELL, P>;
+    static constexpr int NB = S::NB, NQ = S::NQ, NP = NB * (NB + 1) / 2;
+    static constexpr int ND = FORM == FE_FORM_VMASS ? 3 * NB : NB;
+    static constexpr int RC = pick_rows(ND, ND, (int)sizeof(T), SCALAR_STAGE);
+    static constexpr int SS = RC * ND + 1;
+    // coordinates in registers up to 8 nodes, in LDS beyond
+    static constexpr bool X_LDS = NB > 8;
+    using XT = typename std::conditional<X_LDS, XLds<NB>, XReg<NB>>::type;
+};
+
+template <int CELL, int P, int FORM, typename T>
+__global__ __launch_bounds__(64) void k_cw_scalar(ExecArgs A)
+{
+    using C = CwScalar<CELL, P, FORM, T>;
+    constexpr int NB = C::NB, NQ = C::NQ, NP = C::NP, ND = C::ND, RC = C::RC, SS = C::SS;
+    constexpr bool AFFINE = C::S::AFFINE, X_LDS = C::X_LDS;
+    __shared__ T stage[64 * SS];
+    __shared__ double xs[X_LDS ? 64 * XLds<NB>::STRIDE : 1];
+    const int lane = threadIdx.x;
+    const int64_t e0 = logical_block(A.xcd_remap) * 64;
+    const int64_t e = e0 + lane;
+    const bool valid = e < A.n_cells;
+    const ctab_t *bfgT = ctab(A.tab.bfgT);
+    const ctab_t *bf = ctab(A.tab.bf);
+    const ctab_t *w = ctab(A.tab.w);
+
+    using XT = typename C::XT;
+    XT x;
+    unsigned fault;
+    if constexpr (X_LDS) {
+        fault = gather_lds<NB>(A.conn, A.coords, e0, A.n_cells, A.n_nodes, xs, lane, 64);
+        __syncthreads();
+        x.row = xs + lane * XLds<NB>::STRIDE;
+    } else {
+        fault = gather<NB>(A.conn, A.coords, e, A.n_nodes, valid, x);
+    }
+
+    T acc[NP];
+#pragma unroll
+    for (int p = 0; p < NP; p++) acc[p] = T(0);
+
+    double adj[3][3];
+    double det = 0.0;
+    if constexpr (AFFINE) {
+        det = jac_adj<NB, NQ>(x, bfgT, 0, adj);
+        if (valid && !(det > 0.0)) fault |= FAULT_DET;
+    }
+    if constexpr (FORM == FE_FORM_LAPLACE && AFFINE) {
+        // constant gradients: K = (sum_q w_q / det J) H H^T
+        double wsum = 0.0;
+        for (int q = 0; q < NQ; q++) wsum += w[q];
+        const double s = wsum / det;
+        T H[NB][3], sH[NB][3];
+#pragma unroll
+        for (int a = 0; a < NB; a++)
+#pragma unroll
+            for (int i = 0; i < 3; i++) {
+                const double h = h_comp<NB, NQ>(bfgT, adj, 0, a, i);
+                H[a][i] = static_cast<T>(h);
+                sH[a][i] = static_cast<T>(s * h);
+            }
+#pragma unroll
+        for (int a = 0; a < NB; a++)
+#pragma unroll
+            for (int b = a; b < NB; b++)
+                acc[tri(a, b, NB)] = sH[a][0] * H[b][0] + sH[a][1] * H[b][1] + sH[a][2] * H[b][2];
+    } else {
+#pragma unroll 1
+        for (int q = 0; q < NQ; q++) {
+            if constexpr (!AFFINE) {
+                det = jac_adj<NB, NQ>(x, bfgT, q, adj);
+                if (valid && !(det > 0.0)) fault |= FAULT_DET;
+            }
+            if constexpr (FORM == FE_FORM_LAPLACE) {
+                const double s = w[q] / det;
+                T H[NB][3];
+#pragma unroll
+                for (int a = 0; a < NB; a++)
+#pragma unroll
+                    for (int i = 0; i < 3; i++) H[a][i] = static_cast<T>(h_comp<NB, NQ>(bfgT, adj, q, a, i));
+                if constexpr (sizeof(T) == 8) {
+                    // acc += s (H_a . H_b): no scaled copy of H, fewer registers
+#pragma unroll
+                    for (int a = 0; a < NB; a++)
+#pragma unroll
+                        for (int b = a; b < NB; b++) {
+                            const T d = H[a][0] * H[b][0] + H[a][1] * H[b][1] + H[a][2] * H[b][2];
+                            acc[tri(a, b, NB)] = fma(static_cast<T>(s), d, acc[tri(a, b, NB)]);
+                        }
+                } else {
+                    const T sf = static_cast<T>(s);
+#pragma unroll
+                    for (int a = 0; a < NB; a++) {
+                        const T h0 = sf * H[a][0], h1 = sf * H[a][1], h2 = sf * H[a][2];
+#pragma unroll
+                        for (int b = a; b < NB; b++) {
+                            T v = acc[tri(a, b, NB)];
+                            v = fma(h0, H[b][0], v);
+                            v = fma(h1, H[b][1], v);
+                            v = fma(h2, H[b][2], v);
+                            acc[tri(a, b, NB)] = v;
+                        }
+                    }
+                }
+            } else {
+                const T wd = static_cast<T>(w[q] * det);
+                T phi[NB];
+#pragma unroll
+                for (int a = 0; a < NB; a++) phi[a] = static_cast<T>(bf[q * NB + a]);
+#pragma unroll
+                for (int a = 0; a < NB; a++) {
+                    const T wa = wd * phi[a];
+#pragma unroll
+                    for (int b = a; b < NB; b++) acc[tri(a, b, NB)] = fma(wa, phi[b], acc[tri(a, b, NB)]);
+                }
+            }
+        }
+    }
+
+    if (fault) raise_fault(A.flags, fault);
+
+    // staged, coalesced output of RC rows at a time
+    T *out = static_cast<T *>(A.out);
+    const int ncell = A.n_cells - e0 < 64 ? static_cast<int>(A.n_cells - e0) : 64;
+#pragma unroll
+    for (int c0 = 0; c0 < ND; c0 += RC) {
+#pragma unroll
+        for (int rr = 0; rr < RC; rr++) {
+            const int row = c0 + rr, ra = row % NB, rc = row / NB;
+#pragma unroll
+            for (int col = 0; col < ND; col++) {
+                const int cb = col % NB, cc = col / NB;
+                const T v = (rc != cc) ? T(0) : (ra <= cb ? acc[tri(ra, cb, NB)] : acc[tri(cb, ra, NB)]);
+                stage[lane * SS + rr * ND + col] = v;
+            }
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int k = lane; k < 64 * RC * ND; k += 64) {
+            const int cc = k / (RC * ND), off = k - cc * (RC * ND);
+            if (cc < ncell) st_nt(out + (e0 + cc) * (ND * ND) + c0 * ND + off, stage[cc * SS + off]);
+        }
+        __syncthreads();
+    }
+}
+
+template <int CELL, int P, typename T>
+struct CwElast {
+    using S = Shape<CELL, P>;
+    static constexpr int NB = S::NB, NQ = S::NQ, ND = 3 * NB;
+    static constexpr int RH = pick_rows(NB, ND, (int)sizeof(T), ELAST_STAGE);
+    static constexpr int SS = RH * ND + 1;
+};
+
+// Block (R,S) of the isotropic elasticity matrix of the workgroup's 64 cells,
+// computed by one wave (lane = cell) from the coordinates the workgroup
+// gathered into LDS, then the staged row chunks written by the whole
+// workgroup.  Every instantiation executes the same barriers.
+template <int CELL, int P, typename T, int R, int S>
+__device__ __forceinline__ void elast_block(const ExecArgs &A, int64_t e0, const double *xs, T *stage,
+                                            unsigned fault)
+{
+    using C = CwElast<CELL, P, T>;
+    constexpr int NB = C::NB, NQ = C::NQ, ND = C::ND, RH = C::RH, SS = C::SS;
+    constexpr bool AFFINE = C::S::AFFINE, DIAG = R == S;
+    constexpr int NACC = DIAG ? NB * (NB + 1) / 2 : NB * NB;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int64_t e = e0 + lane;
+    const bool valid = e < A.n_cells;
+    const ctab_t *bfgT = ctab(A.tab.bfgT);
+    const ctab_t *w = ctab(A.tab.w);
+    const T *mat = static_cast<const T *>(A.mat);
+    const bool per_qp = A.mat_kind == FE_MAT_ISO_QP;
+    const XLds<NB> x{xs + lane * XLds<NB>::STRIDE};
+
+    T lam = T(0), mu = T(0);
+    if (valid && !per_qp) {
+        lam = mat[2 * e];
+        mu = mat[2 * e + 1];
+    }
+    T acc[NACC];
+#pragma unroll
+    for (int p = 0; p < NACC; p++) acc[p] = T(0);
+    double adj[3][3];
+    double det = 0.0;
+    if constexpr (AFFINE) {
+        det = jac_adj<NB, NQ>(x, bfgT, 0, adj);
+        if (valid && !(det > 0.0)) fault |= FAULT_DET;
+    }
+#pragma unroll 1
+    for (int q = 0; q < NQ; q++) {
+        if constexpr (!AFFINE) {
+            det = jac_adj<NB, NQ>(x, bfgT, q, adj);
+            if (valid && !(det > 0.0)) fault |= FAULT_DET;
+        }
+        if (valid && per_qp) {
+            lam = mat[2 * (e * NQ + q)];
+            mu = mat[2 * (e * NQ + q) + 1];
+        }
+        const T sd = static_cast<T>(w[q] / det);
+        const int qg = AFFINE ? 0 : q;  // table column of the gradients
+        if constexpr (DIAG) {
+            T H[NB][3];
+#pragma unroll
+            for (int a = 0; a < NB; a++)
+#pragma unroll
+                for (int i = 0; i < 3; i++) H[a][i] = static_cast<T>(h_comp<NB, NQ>(bfgT, adj, qg, a, i));
+            const T c1 = sd * (lam + mu), c2 = sd * mu;
+#pragma unroll
+            for (int a = 0; a < NB; a++) {
+                const T y = c1 * H[a][R], z0 = c2 * H[a][0], z1 = c2 * H[a][1], z2 = c2 * H[a][2];
+#pragma unroll
+                for (int b = a; b < NB; b++) {
+                    T v = acc[tri(a, b, NB)];
+                    v = fma(y, H[b][R], v);
+                    v = fma(z0, H[b][0], v);
+                    v = fma(z1, H[b][1], v);
+                    v = fma(z2, H[b][2], v);
+                    acc[tri(a, b, NB)] = v;
+                }
+            }
+        } else {
+            T Hr[NB], Hs[NB];
+#pragma unroll
+            for (int a = 0; a < NB; a++) {
+                Hr[a] = static_cast<T>(h_comp<NB, NQ>(bfgT, adj, qg, a, R));
+                Hs[a] = static_cast<T>(h_comp<NB, NQ>(bfgT, adj, qg, a, S));
+            }
+            const T sl = sd * lam, sm = sd * mu;
+#pragma unroll
+            for (int a = 0; a < NB; a++) {
+                const T u = sl * Hr[a], v = sm * Hs[a];
+#pragma unroll
+                for (int b = 0; b < NB; b++) acc[a * NB + b] = fma(u, Hs[b], fma(v, Hr[b], acc[a * NB + b]));
+            }
+        }
+    }
+
+    if (fault) raise_fault(A.flags, fault);
+
+    T *out = static_cast<T *>(A.out);
+    const int ncell = A.n_cells - e0 < 64 ? static_cast<int>(A.n_cells - e0) : 64;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+#pragma unroll
+        for (int h = 0; h < NB / RH; h++) {
+            if (c == R) {  // rows of block (R, S)
+#pragma unroll
+                for (int rr = 0; rr < RH; rr++) {
+                    const int a = h * RH + rr;
+#pragma unroll
+                    for (int b = 0; b < NB; b++) {
+                        T v;
+                        if constexpr (DIAG) v = a <= b ? acc[tri(a, b, NB)] : acc[tri(b, a, NB)];
+                        else v = acc[a * NB + b];
+                        stage[lane * SS + rr * ND + S * NB + b] = v;
+                    }
+                }
+            }
+            if (!DIAG && c == S) {  // rows of block (S, R) = (R, S)^T
+#pragma unroll
+                for (int rr = 0; rr < RH; rr++) {
+                    const int b = h * RH + rr;
+#pragma unroll
+                    for (int a = 0; a < NB; a++) stage[lane * SS + rr * ND + R * NB + a] = acc[a * NB + b];
+                }
+            }
+            __syncthreads();
+            const int64_t row0 = c * NB + h * RH;
+            for (int k = tid; k < 64 * RH * ND; k += ELAST_THREADS) {
+                const int cc = k / (RH * ND), off = k - cc * (RH * ND);
+                if (cc < ncell) st_nt(out + (e0 + cc) * (ND * ND) + row0 * ND + off, stage[cc * SS + off]);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <int CELL, int P, typename T>
+__global__ __launch_bounds__(ELAST_THREADS) void k_cw_elast(ExecArgs A)
+{
+    constexpr int NB = CwElast<CELL, P, T>::NB;
+    __shared__ T stage[64 * CwElast<CELL, P, T>::SS];
+    __shared__ double xs[64 * XLds<NB>::STRIDE];
+    const int64_t e0 = logical_block(A.xcd_remap) * 64;
+    const unsigned fault = gather_lds<NB>(A.conn, A.coords, e0, A.n_cells, A.n_nodes, xs, threadIdx.x, ELAST_THREADS);
+    __syncthreads();
+    // the wave index, made visibly uniform so the six paths are separate
+    // branches rather than one masked sequence
+    switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
+    case 0: elast_block<CELL, P, T, 0, 0>(A, e0, xs, stage, fault); break;
+    case 1: elast_block<CELL, P, T, 0, 1>(A, e0, xs, stage, fault); break;
+    case 2: elast_block<CELL, P, T, 0, 2>(A, e0, xs, stage, fault); break;
+    case 3: elast_block<CELL, P, T, 1, 1>(A, e0, xs, stage, fault); break;
+    case 4: elast_block<CELL, P, T, 1, 2>(A, e0, xs, stage, fault); break;
+    default: elast_block<CELL, P, T, 2, 2>(A, e0, xs, stage, fault); break;
+    }
+}
+
+template <typename K>
+int launch_cw(K kernel, int threads, const ExecArgs &A, hipStream_t st)
+{
+    if (A.n_cells <= 0) return FE_OK;
+    const int64_t blocks = (A.n_cells + 63) / 64;
+    if (blocks > 0x7fffffff) {
+        set_error("too many cells for one launch");
+        return FE_ERR_INVALID_ARG;
+    }
+    hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(threads), 0, st, A);
+    FE_HIP_CHECK(hipGetLastError());
+    return FE_OK;
+}
+
+template <int CELL, int P, int FORM, typename T>
+int launch_scalar(const Plan &, const ExecArgs &A, hipStream_t st)
+{
+    return launch_cw(k_cw_scalar<CELL, P, FORM, T>, 64, A, st);
+}
+
+template <int CELL, int P, typename T>
+int launch_elast(const Plan &, const ExecArgs &A, hipStream_t st)
+{
+    return launch_cw(k_cw_elast<CELL, P, T>, ELAST_THREADS, A, st);
+}
+
+template <int CELL, int P, typename T>
+LaunchFn pick(const Plan &p)
+{
+    switch (p.form) {
+    case FE_FORM_MASS: return launch_scalar<CELL, P, FE_FORM_MASS, T>;
+    case FE_FORM_VMASS: return launch_scalar<CELL, P, FE_FORM_VMASS, T>;
+    case FE_FORM_LAPLACE: return launch_scalar<CELL, P, FE_FORM_LAPLACE, T>;
+    case FE_FORM_ELASTICITY:
+        if (p.mat_kind == FE_MAT_ISO_CELL || p.mat_kind == FE_MAT_ISO_QP) return launch_elast<CELL, P, T>;
+        return nullptr;
+    }
+    return nullptr;
+}
+
+template <typename T>
+LaunchFn pick_cell(const Plan &p)
+{
+    if (p.cell == FE_CELL_HEX && p.order == 1) return pick<FE_CELL_HEX, 1, T>(p);
+    if (p.cell == FE_CELL_TET && p.order == 1) return pick<FE_CELL_TET, 1, T>(p);
+    if (p.cell == FE_CELL_TET && p.order == 2) return pick<FE_CELL_TET, 2, T>(p);
+    return nullptr;
+}
+
+}  // namespace
+
+LaunchFn select_cellwise(const Plan &p)
+{
+    if (p.mode != FE_MODE_MATRIX) return nullptr;
+    if (p.prec == FE_PREC_FP64) return pick_cell<double>(p);
+    if (p.prec == FE_PREC_FP32) return pick_cell<float>(p);
+    return nullptr;
+}
+
+}  // namespace fe
