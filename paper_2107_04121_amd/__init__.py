@@ -91,9 +91,12 @@ class Plan:
         self._ws = None
 
     def __del__(self):
+        # the library handle is looked up defensively: at interpreter exit
+        # module globals may already be gone
         h = getattr(self, "_h", None)
-        if h is not None and h.value and _lib._lib is not None:
-            _lib._lib.fe_plan_destroy(h)
+        lib = getattr(_lib, "_lib", None) if _lib is not None else None
+        if h is not None and h.value and lib is not None:
+            lib.fe_plan_destroy(h)
             self._h = None
 
     @property
@@ -191,9 +194,12 @@ class Incidence:
         self._h = h
 
     def __del__(self):
+        # the library handle is looked up defensively: at interpreter exit
+        # module globals may already be gone
         h = getattr(self, "_h", None)
-        if h is not None and h.value and _lib._lib is not None:
-            _lib._lib.fe_incidence_destroy(h)
+        lib = getattr(_lib, "_lib", None) if _lib is not None else None
+        if h is not None and h.value and lib is not None:
+            lib.fe_incidence_destroy(h)
             self._h = None
 
 
@@ -369,7 +375,10 @@ class Batch:
                    "fe_batch_check")
 
     def __del__(self):
+        # the library handle is looked up defensively: at interpreter exit
+        # module globals may already be gone
         h = getattr(self, "_h", None)
-        if h is not None and h.value and _lib._lib is not None:
-            _lib._lib.fe_batch_destroy(h)
+        lib = getattr(_lib, "_lib", None) if _lib is not None else None
+        if h is not None and h.value and lib is not None:
+            lib.fe_batch_destroy(h)
             self._h = None

@@ -179,5 +179,205 @@ constexpr int pick_rows(int n, int nd, int esize, int cap)
     return 1;
 }
 
+
+// Upper-triangle accumulators of the scalar mass (MASS, VMASS) or Laplace
+// matrix of a lane's cell: acc[tri(a, b)] = sum_q w_q det J phi_a phi_b, or
+// sum_q (w_q / det J) H_a . H_b.  FP64 geometry; products in T.
+template <int CELL, int P, int FORM, typename T, typename X>
+__device__ __forceinline__ void acc_scalar(const X &x, const ctab_t *w, const ctab_t *bf, const ctab_t *bfgT,
+                                           bool valid, unsigned &fault, T (&acc)[Shape<CELL, P>::NB *(Shape<CELL, P>::NB + 1) / 2])
+{
+    constexpr int NB = Shape<CELL, P>::NB, NQ = Shape<CELL, P>::NQ, NP = NB * (NB + 1) / 2;
+    constexpr bool AFFINE = Shape<CELL, P>::AFFINE;
+#pragma unroll
+    for (int p = 0; p < NP; p++) acc[p] = T(0);
+    double adj[3][3];
+    double det = 0.0;
+    if constexpr (AFFINE) {
+        det = jac_adj<NB, NQ>(x, bfgT, 0, adj);
+        if (valid && !(det > 0.0)) fault |= FAULT_DET;
+    }
+    if constexpr (FORM == FE_FORM_LAPLACE && AFFINE) {
+        // constant gradients: K = (sum_q w_q / det J) H H^T
+        double wsum = 0.0;
+        for (int q = 0; q < NQ; q++) wsum += w[q];
+        const double s = wsum / det;
+        T H[NB][3], sH[NB][3];
+#pragma unroll
+        for (int a = 0; a < NB; a++)
+#pragma unroll
+            for (int i = 0; i < 3; i++) {
+                const double h = h_comp<NB, NQ>(bfgT, adj, 0, a, i);
+                H[a][i] = static_cast<T>(h);
+                sH[a][i] = static_cast<T>(s * h);
+            }
+#pragma unroll
+        for (int a = 0; a < NB; a++)
+#pragma unroll
+            for (int b = a; b < NB; b++)
+                acc[tri(a, b, NB)] = sH[a][0] * H[b][0] + sH[a][1] * H[b][1] + sH[a][2] * H[b][2];
+    } else {
+#pragma unroll 1
+        for (int q = 0; q < NQ; q++) {
+            if constexpr (!AFFINE) {
+                det = jac_adj<NB, NQ>(x, bfgT, q, adj);
+                if (valid && !(det > 0.0)) fault |= FAULT_DET;
+            }
+            if constexpr (FORM == FE_FORM_LAPLACE) {
+                const double s = w[q] / det;
+                T H[NB][3];
+#pragma unroll
+                for (int a = 0; a < NB; a++)
+#pragma unroll
+                    for (int i = 0; i < 3; i++) H[a][i] = static_cast<T>(h_comp<NB, NQ>(bfgT, adj, q, a, i));
+                if constexpr (sizeof(T) == 8) {
+                    // acc += s (H_a . H_b): no scaled copy of H, fewer registers
+#pragma unroll
+                    for (int a = 0; a < NB; a++)
+#pragma unroll
+                        for (int b = a; b < NB; b++) {
+                            const T d = H[a][0] * H[b][0] + H[a][1] * H[b][1] + H[a][2] * H[b][2];
+                            acc[tri(a, b, NB)] = fma(static_cast<T>(s), d, acc[tri(a, b, NB)]);
+                        }
+                } else {
+                    const T sf = static_cast<T>(s);
+#pragma unroll
+                    for (int a = 0; a < NB; a++) {
+                        const T h0 = sf * H[a][0], h1 = sf * H[a][1], h2 = sf * H[a][2];
+#pragma unroll
+                        for (int b = a; b < NB; b++) {
+                            T v = acc[tri(a, b, NB)];
+                            v = fma(h0, H[b][0], v);
+                            v = fma(h1, H[b][1], v);
+                            v = fma(h2, H[b][2], v);
+                            acc[tri(a, b, NB)] = v;
+                        }
+                    }
+                }
+            } else {
+                const T wd = static_cast<T>(w[q] * det);
+                T phi[NB];
+#pragma unroll
+                for (int a = 0; a < NB; a++) phi[a] = static_cast<T>(bf[q * NB + a]);
+#pragma unroll
+                for (int a = 0; a < NB; a++) {
+                    const T wa = wd * phi[a];
+#pragma unroll
+                    for (int b = a; b < NB; b++) acc[tri(a, b, NB)] = fma(wa, phi[b], acc[tri(a, b, NB)]);
+                }
+            }
+        }
+    }
+}
+
+// Accumulators of block (R,S), R <= S, of the isotropic elasticity matrix:
+// packed upper triangle for R == S, row-major NB x NB otherwise.
+template <int NB, int R, int S>
+struct ElastAcc {
+    static constexpr int N = R == S ? NB * (NB + 1) / 2 : NB * NB;
+};
+
+// Block (R,S) of the isotropic elasticity matrix of a lane's cell (coefficients
+// per cell, or per point when per_qp):
+//   K_RS[a][b] = sum_q s_q (lambda H_R[a] H_S[b] + mu H_S[a] H_R[b]),  R < S,
+//   K_RR[a][b] = sum_q s_q ((lambda + mu) H_R[a] H_R[b] + mu H_a . H_b),
+// s_q = w_q / det J, H = dphi/dxi adj J; this is w det J B^T D B for the
+// isotropic D, block by block.
+template <int CELL, int P, typename T, int R, int S, typename X>
+__device__ __forceinline__ void acc_elast(const X &x, const ctab_t *w, const ctab_t *bfgT, const T *mat, bool per_qp,
+                                          int64_t e, bool valid, unsigned &fault,
+                                          T (&acc)[ElastAcc<Shape<CELL, P>::NB, R, S>::N])
+{
+    constexpr int NB = Shape<CELL, P>::NB, NQ = Shape<CELL, P>::NQ, NACC = ElastAcc<NB, R, S>::N;
+    constexpr bool AFFINE = Shape<CELL, P>::AFFINE, DIAG = R == S;
+    T lam = T(0), mu = T(0);
+    if (valid && !per_qp) {
+        lam = mat[2 * e];
+        mu = mat[2 * e + 1];
+    }
+#pragma unroll
+    for (int p = 0; p < NACC; p++) acc[p] = T(0);
+    double adj[3][3];
+    double det = 0.0;
+    if constexpr (AFFINE) {
+        det = jac_adj<NB, NQ>(x, bfgT, 0, adj);
+        if (valid && !(det > 0.0)) fault |= FAULT_DET;
+    }
+#pragma unroll 1
+    for (int q = 0; q < NQ; q++) {
+        if constexpr (!AFFINE) {
+            det = jac_adj<NB, NQ>(x, bfgT, q, adj);
+            if (valid && !(det > 0.0)) fault |= FAULT_DET;
+        }
+        if (valid && per_qp) {
+            lam = mat[2 * (e * NQ + q)];
+            mu = mat[2 * (e * NQ + q) + 1];
+        }
+        const T sd = static_cast<T>(w[q] / det);
+        const int qg = AFFINE ? 0 : q;  // table column of the gradients
+        if constexpr (DIAG) {
+            T H[NB][3];
+#pragma unroll
+            for (int a = 0; a < NB; a++)
+#pragma unroll
+                for (int i = 0; i < 3; i++) H[a][i] = static_cast<T>(h_comp<NB, NQ>(bfgT, adj, qg, a, i));
+            const T c1 = sd * (lam + mu), c2 = sd * mu;
+#pragma unroll
+            for (int a = 0; a < NB; a++) {
+                const T y = c1 * H[a][R], z0 = c2 * H[a][0], z1 = c2 * H[a][1], z2 = c2 * H[a][2];
+#pragma unroll
+                for (int b = a; b < NB; b++) {
+                    T v = acc[tri(a, b, NB)];
+                    v = fma(y, H[b][R], v);
+                    v = fma(z0, H[b][0], v);
+                    v = fma(z1, H[b][1], v);
+                    v = fma(z2, H[b][2], v);
+                    acc[tri(a, b, NB)] = v;
+                }
+            }
+        } else {
+            T Hr[NB], Hs[NB];
+#pragma unroll
+            for (int a = 0; a < NB; a++) {
+                Hr[a] = static_cast<T>(h_comp<NB, NQ>(bfgT, adj, qg, a, R));
+                Hs[a] = static_cast<T>(h_comp<NB, NQ>(bfgT, adj, qg, a, S));
+            }
+            const T sl = sd * lam, sm = sd * mu;
+#pragma unroll
+            for (int a = 0; a < NB; a++) {
+                const T u = sl * Hr[a], v = sm * Hs[a];
+#pragma unroll
+                for (int b = 0; b < NB; b++) acc[a * NB + b] = fma(u, Hs[b], fma(v, Hr[b], acc[a * NB + b]));
+            }
+        }
+    }
+}
+
+// Entry (a, b) of a symmetric matrix kept as a packed upper triangle.
+template <int NB, typename T, int N>
+__device__ __forceinline__ T sym_at(const T (&acc)[N], int a, int b)
+{
+    return a <= b ? acc[tri(a, b, NB)] : acc[tri(b, a, NB)];
+}
+
+// Rows a0 .. a0+RH-1 of elasticity block (R,S) (TRANS: of block (S,R) =
+// (R,S)^T) into a lane's staging rows of width ND, at column col0.
+template <int NB, int ND, int RH, int R, int S, bool TRANS, typename T, int N>
+__device__ __forceinline__ void stage_block(const T (&acc)[N], T *row, int a0, int col0)
+{
+#pragma unroll
+    for (int rr = 0; rr < RH; rr++) {
+#pragma unroll
+        for (int c = 0; c < NB; c++) {
+            // TRANS: row index of the transposed block is the column of (R,S)
+            const int a = TRANS ? c : a0 + rr, b = TRANS ? a0 + rr : c;
+            T v;
+            if constexpr (R == S) v = sym_at<NB>(acc, a, b);
+            else v = acc[a * NB + b];
+            row[rr * ND + col0 + c] = v;
+        }
+    }
+}
+
 }  // namespace cw
 }  // namespace fe

@@ -9,8 +9,8 @@
 // evaluation per cell:
 //   - Q2 hexahedra: the matrix-core cell routine (elasticity GEMM P = G^T W G,
 //     Laplace = P_00 + P_11 + P_22, mass on the matrix cores);
-//   - P1/P2 tetrahedra and Q1 hexahedra: a fused VALU tile routine computing
-//     the six blocks r <= s of P, the mass matrix, then all outputs.
+//   - P1/P2 tetrahedra and Q1 hexahedra: the same product on the matrix
+//     cores for several cells per pass (see SmallMM).
 // The counter reset and the kernel are captured once in a HIP graph; running
 // the batch is one graph launch.  Tiles per group are tuned by timing the
 // graph over a small candidate set.
@@ -43,121 +43,288 @@ namespace {
 
 using namespace q2;
 
-// Fused tile for small cells (any cell kind/order with NB <= 27): E cells per
-// pass; mass, Laplace and isotropic elasticity element matrices from one
-// geometry evaluation (FP64) and the six blocks P_rs = G_r^T W G_s, r <= s.
+// Low-order cells (P1/P2 tetrahedra, Q1 hexahedra) on the matrix cores, CPP
+// cells per pass: every (cell, quadrature point) pair's FP64 geometry is
+// evaluated once by one thread, G = dphi/dxi J^-1 goes to LDS in the
+// contraction type, and each wave forms, for CPW cells,
+//   P = G_s^T diag(w det J) G_s   (3nb x 3nb, G_s = [G_x G_y G_z])
+//   M = Phi^T diag(w det J) Phi   (nb x nb, the scalar mass matrix)
+// on 16x16 MFMA tiles.  All outputs are then read off P and M in LDS:
+//   K[(r,a),(s,b)] = lambda P[(r,a),(s,b)] + mu P[(s,a),(r,b)]
+//                    + delta_rs mu sum_j P[(j,a),(j,b)]   (isotropic elasticity)
+//   L[a][b] = sum_j P[(j,a),(j,b)]                        (Laplace)
+// and stored with consecutive threads on consecutive entries of the pass's
+// contiguous cells.
 template <int CELL, int P, typename T>
-struct Fused {
+struct SmallMM {
     static constexpr int NB = cell_nb(CELL, P), NQ = cell_nq(CELL, P), ND = 3 * NB;
-    static constexpr int PER = NB * 3 * 8 + NQ * 3 * NB * (int)sizeof(T) + NQ * (int)sizeof(T) +
-                               7 * NB * NB * (int)sizeof(T) + 2 * (int)sizeof(T);
-    static constexpr int choose(int cap)
-    {
-        int e = 256 / (NQ > NB ? NQ : NB);
-        if (e < 1) e = 1;
-        while (e > 1 && e * PER > cap) e--;
-        return e;
-    }
-    static constexpr int E = choose(48 * 1024);
-    static constexpr int BYTES = E * PER;
+    static constexpr int NQP = (NQ + 3) / 4 * 4;  // quadrature axis padded to the MFMA depth
+    static constexpr int KS = NQP + 1;            // odd row stride of the operand
+    static constexpr int NT = ND > 16 ? 2 : 1;    // 16x16 tiles per side of P
+    static constexpr int RP = 16 * NT;            // operand rows, padded
+    static constexpr int CPW = NQ > 8 ? 1 : (NB > 4 ? 2 : 4);  // cells per wave
+    static constexpr int CPP = 4 * CPW;                       // cells per pass
+    static constexpr int PS = ND + 1, MS = NB + 1;            // LDS row strides of P, M
+    static constexpr int XB = CPP * NB * 3;                                    // doubles per x buffer
+    static constexpr int OFF_X = 0;                                            // double x[2][CPP][NB*3]
+    static constexpr int OFF_LM = align16(OFF_X + 2 * XB * 8);                 // T lm[2][CPP][2]
+    static constexpr int OFF_WD = align16(OFF_LM + 2 * CPP * 2 * (int)sizeof(T));  // double wd[CPP][NQP]
+    static constexpr int OFF_G = align16(OFF_WD + CPP * NQP * 8);              // T G[CPP][RP][KS]
+    static constexpr int OFF_P = align16(OFF_G + CPP * RP * KS * (int)sizeof(T));  // T P[CPP][ND][PS]
+    static constexpr int OFF_M = align16(OFF_P + CPP * ND * PS * (int)sizeof(T));  // T M[CPP][NB][MS]
+    static constexpr int BYTES = align16(OFF_M + CPP * NB * MS * (int)sizeof(T));
 };
 
-template <int CELL, int P, typename T>
-__device__ void fused_tile(const GroupDev &g, int64_t c0, int64_t c1, unsigned *flags, unsigned char *smem)
+template <typename T>
+__device__ __forceinline__ void mma4(T a, T b, typename MMT<sizeof(T) == 8 ? MM_F64 : MM_F32>::acc &c)
 {
-    using F = Fused<CELL, P, T>;
-    constexpr int NB = F::NB, NQ = F::NQ, ND = F::ND, E = F::E, NN = NB * NB;
-    double *xs = reinterpret_cast<double *>(smem);  // [E][NB][3]
-    T *Gs = reinterpret_cast<T *>(xs + E * NB * 3);   // [E][NQ][3][NB]
-    T *wd = Gs + E * NQ * 3 * NB;                     // [E][NQ]
-    T *Ps = wd + E * NQ;                              // [E][7][NB][NB]: 6 blocks r <= s, then mass
-    T *lm = Ps + E * 7 * NN;                          // [E][2]
-    const int tid = threadIdx.x;
-    const T *mat = static_cast<const T *>(g.mat);
-    const bool want_el = g.forms & FORM_BIT_ELAST;
+    if constexpr (sizeof(T) == 8) c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    else c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
 
-    for (int64_t e0 = c0; e0 < c1; e0 += E) {
-        const int ne = static_cast<int>(c1 - e0 < E ? c1 - e0 : E);
-        for (int i = tid; i < ne * NB; i += 256) {
-            const int el = i / NB, a = i - el * NB;
-            const int64_t n = checked_node(g.conn, (e0 + el) * NB + a, g.n_nodes, flags);
-            xs[i * 3 + 0] = g.coords[3 * n];
-            xs[i * 3 + 1] = g.coords[3 * n + 1];
-            xs[i * 3 + 2] = g.coords[3 * n + 2];
+// Node coordinates (and coefficients) of cells e0 .. e0+n-1 into x buffer xb.
+template <int CELL, int P, typename T>
+__device__ __forceinline__ unsigned small_gather(const GroupDev &g, int64_t e0, int n, double *xb, T *lmb, int tid)
+{
+    using L = SmallMM<CELL, P, T>;
+    constexpr int NB = L::NB, CPP = L::CPP;
+    unsigned fault = 0;
+    for (int t = tid; t < CPP * NB; t += 256) {
+        const int c = t / NB, a = t - c * NB;
+        double x0 = 0.0, x1 = 0.0, x2 = 0.0;
+        if (c < n) {
+            int64_t nd = g.conn[(e0 + c) * NB + a];
+            if (nd < 0 || nd >= g.n_nodes) {
+                fault |= FAULT_INDEX;
+                nd = 0;
+            }
+            x0 = g.coords[3 * nd];
+            x1 = g.coords[3 * nd + 1];
+            x2 = g.coords[3 * nd + 2];
         }
-        if (want_el)
-            for (int i = tid; i < ne * 2; i += 256) lm[i] = mat[2 * e0 + i];
-        __syncthreads();
-        for (int i = tid; i < ne * NQ; i += 256) {
-            const int el = i / NQ, q = i - el * NQ;
-            double J[3][3], Ji[3][3];
-            jacobian_qp<NB, NQ>(xs + el * NB * 3, g.tab.bfgT, q, J);
-            const double det = inverse3(J, Ji);
-            if (!(det > 0.0)) raise_fault(flags, FAULT_DET);
-            wd[i] = static_cast<T>(g.tab.w[q] * det);
-            T *gq = Gs + i * 3 * NB;
-            for (int a = 0; a < NB; a++) {
-                const double r0 = g.tab.bfgT[(a * 3 + 0) * NQ + q];
-                const double r1 = g.tab.bfgT[(a * 3 + 1) * NQ + q];
-                const double r2 = g.tab.bfgT[(a * 3 + 2) * NQ + q];
+        xb[t * 3] = x0;
+        xb[t * 3 + 1] = x1;
+        xb[t * 3 + 2] = x2;
+    }
+    if ((g.forms & FORM_BIT_ELAST) && tid < 2 * CPP)
+        lmb[tid] = tid < 2 * n ? static_cast<const T *>(g.mat)[2 * e0 + tid] : T(0);
+    return fault;
+}
+
+// Cells e0 .. e0+n-1 (n <= CPP) of a low-order group, their coordinates
+// already in x buffer `buf`.  When nn_next > 0 the next pass (cells en ..
+// en+nn_next-1) is prefetched into the other buffer in two hops: its
+// connectivity during the geometry, its coordinates during the products,
+// both parked in LDS before this pass's stores, so no load waits for those
+// stores to drain (vector memory counters complete in order).
+template <int CELL, int P, typename T>
+__device__ void small_pass(const GroupDev &g, int64_t e0, int n, int buf, int64_t en, int nn_next, unsigned *flags,
+                           unsigned char *smem, int tid)
+{
+    using L = SmallMM<CELL, P, T>;
+    using ACC = typename MMT<sizeof(T) == 8 ? MM_F64 : MM_F32>::acc;
+    constexpr int NB = L::NB, NQ = L::NQ, ND = L::ND, NQP = L::NQP, KS = L::KS, NT = L::NT, RP = L::RP;
+    constexpr int CPP = L::CPP, CPW = L::CPW, PS = L::PS, MS = L::MS;
+    double *xs = reinterpret_cast<double *>(smem + L::OFF_X) + buf * L::XB;
+    double *xn = reinterpret_cast<double *>(smem + L::OFF_X) + (buf ^ 1) * L::XB;
+    T *lm = reinterpret_cast<T *>(smem + L::OFF_LM) + buf * 2 * CPP;
+    T *lmn = reinterpret_cast<T *>(smem + L::OFF_LM) + (buf ^ 1) * 2 * CPP;
+    double *wd = reinterpret_cast<double *>(smem + L::OFF_WD);
+    T *Gs = reinterpret_cast<T *>(smem + L::OFF_G);
+    T *Ps = reinterpret_cast<T *>(smem + L::OFF_P);
+    T *Ms = reinterpret_cast<T *>(smem + L::OFF_M);
+    const bool want_el = g.forms & FORM_BIT_ELAST;
+    unsigned fault = 0;
+
+    // 1. operand padding: rows nd..RP-1 and columns NQ..NQP-1 of every
+    //    cell's operand, weights of the padding points
+    constexpr int ZR = (RP - ND) * KS, ZC = ND * (NQP - NQ);
+    if constexpr (ZR + ZC > 0)
+        for (int t = tid; t < CPP * (ZR + ZC); t += 256) {
+            const int c = t / (ZR + ZC), u = t - c * (ZR + ZC);
+            T *G = Gs + c * RP * KS;
+            if (u < ZR) G[ND * KS + u] = T(0);
+            else if constexpr (ZC > 0) G[((u - ZR) / (NQP - NQ)) * KS + NQ + (u - ZR) % (NQP - NQ)] = T(0);
+        }
+    if constexpr (NQP > NQ)
+        if (tid < CPP * (NQP - NQ)) wd[(tid / (NQP - NQ)) * NQP + NQ + tid % (NQP - NQ)] = 0.0;
+
+    // first prefetch hop: the next pass's connectivity and coefficients
+    constexpr int PF = (CPP * NB + 255) / 256;  // prefetch slots per thread
+    int32_t pn[PF];
+    T plm = T(0);
 #pragma unroll
-                for (int d = 0; d < 3; d++) gq[d * NB + a] = static_cast<T>(r0 * Ji[0][d] + r1 * Ji[1][d] + r2 * Ji[2][d]);
+    for (int k = 0; k < PF; k++) {
+        const int t = tid + 256 * k, c = t / NB;
+        pn[k] = (t < CPP * NB && c < nn_next) ? g.conn[en * NB + t] : 0;
+    }
+    if (want_el && tid < 2 * nn_next) plm = static_cast<const T *>(g.mat)[2 * en + tid];
+
+    // 2. FP64 geometry, one (cell, point) pair per thread
+    for (int t = tid; t < CPP * NQ; t += 256) {
+        const int c = t / NQ, q = t - c * NQ;
+        const double *x = xs + c * NB * 3;
+        double J[3][3] = {};
+#pragma unroll
+        for (int a = 0; a < NB; a++) {
+            const double x0 = x[a * 3], x1 = x[a * 3 + 1], x2 = x[a * 3 + 2];
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+                const double gr = g.tab.bfgT[(a * 3 + j) * NQ + q];
+                J[0][j] = fma(x0, gr, J[0][j]);
+                J[1][j] = fma(x1, gr, J[1][j]);
+                J[2][j] = fma(x2, gr, J[2][j]);
             }
         }
-        __syncthreads();
-        // P_rs[a][b] = sum_q wd G_r[a] G_s[b] (6 blocks r <= s), block 6 = mass
-        for (int i = tid; i < ne * 7 * NN; i += 256) {
-            const int el = i / (7 * NN), rem = i - el * 7 * NN, blk = rem / NN, ab = rem - blk * NN;
-            const int a = ab / NB, b = ab - a * NB;
-            T s = T(0);
-            if (blk == 6) {
-                for (int q = 0; q < NQ; q++)
-                    s += wd[el * NQ + q] * static_cast<T>(g.tab.bf[q * NB + a]) * static_cast<T>(g.tab.bf[q * NB + b]);
-            } else {
-                const int r = blk < 3 ? 0 : (blk < 5 ? 1 : 2);
-                const int sc = blk < 3 ? blk : (blk < 5 ? blk - 2 : 2);
-                for (int q = 0; q < NQ; q++) {
-                    const T *gq = Gs + (el * NQ + q) * 3 * NB;
-                    s += wd[el * NQ + q] * gq[r * NB + a] * gq[sc * NB + b];
+        double Ji[3][3];
+        const double det = inverse3(J, Ji);
+        const bool live = c < n;
+        if (live && !(det > 0.0)) fault |= FAULT_DET;
+        wd[c * NQP + q] = live ? g.tab.w[q] * det : 0.0;
+        T *G = Gs + c * RP * KS + q;
+#pragma unroll
+        for (int a = 0; a < NB; a++) {
+            const double r0 = g.tab.bfgT[(a * 3 + 0) * NQ + q], r1 = g.tab.bfgT[(a * 3 + 1) * NQ + q],
+                         r2 = g.tab.bfgT[(a * 3 + 2) * NQ + q];
+#pragma unroll
+            for (int i = 0; i < 3; i++)
+                G[(i * NB + a) * KS] = live ? static_cast<T>(r0 * Ji[0][i] + r1 * Ji[1][i] + r2 * Ji[2][i]) : T(0);
+        }
+    }
+    __syncthreads();
+
+    // second prefetch hop: the next pass's coordinates (the empty asm keeps
+    // the wait for the connectivity loads here, not next to the loads)
+    double px[PF][3];
+#pragma unroll
+    for (int k = 0; k < PF; k++) {
+        const int t = tid + 256 * k, c = t / NB;
+        px[k][0] = px[k][1] = px[k][2] = 0.0;
+        if (t < CPP * NB && c < nn_next) {
+            asm volatile("" : "+v"(pn[k]));
+            int64_t nd = pn[k];
+            if (nd < 0 || nd >= g.n_nodes) {
+                fault |= FAULT_INDEX;
+                nd = 0;
+            }
+            px[k][0] = g.coords[3 * nd];
+            px[k][1] = g.coords[3 * nd + 1];
+            px[k][2] = g.coords[3 * nd + 2];
+        }
+    }
+
+    // 3. P and M on the matrix cores, wave w: cells w*CPW .. w*CPW+CPW-1
+    {
+        const int wave = tid >> 6, lane = tid & 63, col = lane & 15, grp = lane >> 4;
+#pragma unroll
+        for (int k = 0; k < CPW; k++) {
+            const int c = wave * CPW + k;
+            const T *G = Gs + c * RP * KS;
+            ACC acc[NT][NT], am{};
+#pragma unroll
+            for (int i = 0; i < NT; i++)
+#pragma unroll
+                for (int j = 0; j < NT; j++) acc[i][j] = ACC{};
+#pragma unroll
+            for (int kk = 0; kk < NQP / 4; kk++) {
+                const int q = 4 * kk + grp;
+                const T w = static_cast<T>(wd[c * NQP + q]);
+                T a[NT], b[NT];
+#pragma unroll
+                for (int i = 0; i < NT; i++) {
+                    b[i] = G[(i * 16 + col) * KS + q];
+                    a[i] = b[i] * w;
                 }
+#pragma unroll
+                for (int i = 0; i < NT; i++)
+#pragma unroll
+                    for (int j = 0; j < NT; j++) mma4<T>(a[i], b[j], acc[i][j]);
+                const T phi = (col < NB && q < NQ) ? static_cast<T>(g.tab.bf[q * NB + col]) : T(0);
+                mma4<T>(phi * w, phi, am);
             }
-            Ps[i] = s;
+            // accumulator layout: column = lane % 16; FP32 rows 4*(lane/16)+v,
+            // FP64 rows lane/16 + 4v
+            T *Pc = Ps + c * ND * PS;
+#pragma unroll
+            for (int i = 0; i < NT; i++)
+#pragma unroll
+                for (int j = 0; j < NT; j++)
+#pragma unroll
+                    for (int v = 0; v < 4; v++) {
+                        const int r = i * 16 + (sizeof(T) == 8 ? grp + 4 * v : 4 * grp + v), cc = j * 16 + col;
+                        if (r < ND && cc < ND) Pc[r * PS + cc] = static_cast<T>(acc[i][j][v]);
+                    }
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int r = sizeof(T) == 8 ? grp + 4 * v : 4 * grp + v;
+                if (r < NB && col < NB) Ms[(c * NB + r) * MS + col] = static_cast<T>(am[v]);
+            }
         }
+    }
+    // park the prefetched pass in the other buffer (not read by this pass)
+#pragma unroll
+    for (int k = 0; k < PF; k++) {
+        const int t = tid + 256 * k;
+        if (t < CPP * NB) {
+            xn[t * 3] = px[k][0];
+            xn[t * 3 + 1] = px[k][1];
+            xn[t * 3 + 2] = px[k][2];
+        }
+    }
+    if (want_el && tid < 2 * CPP) lmn[tid] = plm;
+    __syncthreads();
+
+    // 4. outputs of the pass's n contiguous cells
+    if (want_el) {
+        T *out = static_cast<T *>(g.out_el) + e0 * (ND * ND);
+        for (int f = tid; f < n * ND * ND; f += 256) {
+            const int c = f / (ND * ND), rem = f - c * (ND * ND), row = rem / ND, cl = rem - row * ND;
+            const int r = row / NB, a = row - r * NB, s = cl / NB, b = cl - s * NB;
+            const T *Pc = Ps + c * ND * PS;
+            const T lam = lm[2 * c], mu = lm[2 * c + 1];
+            T v = lam * Pc[row * PS + cl] + mu * Pc[(s * NB + a) * PS + r * NB + b];
+            if (r == s) v += mu * (Pc[a * PS + b] + Pc[(NB + a) * PS + NB + b] + Pc[(2 * NB + a) * PS + 2 * NB + b]);
+            q2::out_store(v, out + f);
+        }
+    }
+    if (g.forms & FORM_BIT_LAPLACE) {
+        T *out = static_cast<T *>(g.out_lap) + e0 * (NB * NB);
+        for (int f = tid; f < n * NB * NB; f += 256) {
+            const int c = f / (NB * NB), rem = f - c * (NB * NB), a = rem / NB, b = rem - a * NB;
+            const T *Pc = Ps + c * ND * PS;
+            q2::out_store(Pc[a * PS + b] + Pc[(NB + a) * PS + NB + b] + Pc[(2 * NB + a) * PS + 2 * NB + b], out + f);
+        }
+    }
+    if (g.forms & FORM_BIT_MASS) {
+        T *out = static_cast<T *>(g.out_mass) + e0 * (NB * NB);
+        for (int f = tid; f < n * NB * NB; f += 256) {
+            const int c = f / (NB * NB), rem = f - c * (NB * NB), a = rem / NB, b = rem - a * NB;
+            q2::out_store(Ms[(c * NB + a) * MS + b], out + f);
+        }
+    }
+    if (fault) raise_fault(flags, fault);
+    __syncthreads();  // LDS is reused by the next pass
+}
+
+template <int CELL, int P, typename T>
+__device__ void small_tile(const GroupDev &g, int64_t c0, int64_t c1, unsigned *flags, unsigned char *smem, int tid)
+{
+    using L = SmallMM<CELL, P, T>;
+    constexpr int CPP = L::CPP;
+    if (c0 >= c1) return;
+    {
+        const int n0 = c1 - c0 < CPP ? int(c1 - c0) : CPP;
+        const unsigned f = small_gather<CELL, P, T>(g, c0, n0, reinterpret_cast<double *>(smem + L::OFF_X),
+                                                    reinterpret_cast<T *>(smem + L::OFF_LM), tid);
+        if (f) raise_fault(flags, f);
         __syncthreads();
-        // outputs, consecutive threads on consecutive entries of each cell
-        if (g.forms & FORM_BIT_MASS) {
-            T *om = static_cast<T *>(g.out_mass) + e0 * NN;
-            for (int i = tid; i < ne * NN; i += 256) {
-                const int el = i / NN, ab = i - el * NN;
-                om[i] = Ps[(el * 7 + 6) * NN + ab];
-            }
-        }
-        if (g.forms & FORM_BIT_LAPLACE) {
-            T *ol = static_cast<T *>(g.out_lap) + e0 * NN;
-            for (int i = tid; i < ne * NN; i += 256) {
-                const int el = i / NN, ab = i - el * NN;
-                const T *pe = Ps + el * 7 * NN;
-                ol[i] = pe[0 * NN + ab] + pe[3 * NN + ab] + pe[5 * NN + ab];
-            }
-        }
-        if (want_el) {
-            T *oe = static_cast<T *>(g.out_el) + e0 * ND * ND;
-            for (int i = tid; i < ne * ND * ND; i += 256) {
-                const int el = i / (ND * ND), rem = i - el * ND * ND, row = rem / ND, col = rem - row * ND;
-                const int r = row / NB, a = row - r * NB, s = col / NB, b = col - s * NB;
-                const T *pe = Ps + el * 7 * NN;
-                const int lo = r < s ? r : s, hi = r < s ? s : r;
-                const int blk = lo == 0 ? hi : (lo == 1 ? 2 + hi : 5);
-                // P(r,s)[a][b] is stored for r <= s; P(s,r) = P(r,s)^T
-                const T pab = r <= s ? pe[blk * NN + a * NB + b] : pe[blk * NN + b * NB + a];
-                const T pba = r <= s ? pe[blk * NN + b * NB + a] : pe[blk * NN + a * NB + b];
-                const T lam = lm[el * 2], mu = lm[el * 2 + 1];
-                T v = lam * pab + mu * pba;
-                if (r == s) v += mu * (pe[0 * NN + a * NB + b] + pe[3 * NN + a * NB + b] + pe[5 * NN + a * NB + b]);
-                oe[i] = v;
-            }
-        }
-        __syncthreads();
+    }
+    int buf = 0;
+    for (int64_t e0 = c0; e0 < c1; e0 += CPP, buf ^= 1) {
+        const int n = c1 - e0 < CPP ? int(c1 - e0) : CPP;
+        const int64_t en = e0 + CPP;
+        const int nn = en < c1 ? (c1 - en < CPP ? int(c1 - en) : CPP) : 0;
+        small_pass<CELL, P, T>(g, e0, n, buf, en, nn, flags, smem, tid);
     }
 }
 
@@ -165,17 +332,26 @@ template <typename T>
 struct BatchLds {
     static constexpr int MM = sizeof(T) == 8 ? MM_F64 : MM_F32;
     static constexpr int v0 = Q2Layout<MM>::BYTES;
-    static constexpr int v1 = Fused<FE_CELL_TET, 1, T>::BYTES;
-    static constexpr int v2 = Fused<FE_CELL_TET, 2, T>::BYTES;
-    static constexpr int v3 = Fused<FE_CELL_HEX, 1, T>::BYTES;
+    static constexpr int v1 = SmallMM<FE_CELL_TET, 1, T>::BYTES;
+    static constexpr int v2 = SmallMM<FE_CELL_TET, 2, T>::BYTES;
+    static constexpr int v3 = SmallMM<FE_CELL_HEX, 1, T>::BYTES;
     static constexpr int m01 = v0 > v1 ? v0 : v1, m23 = v2 > v3 ? v2 : v3;
     static constexpr int BYTES = m01 > m23 ? m01 : m23;
 };
 
+// Q2 items.
+template <int MM>
+__device__ __forceinline__ void q2_item(const GroupDev &g, int64_t c0, int64_t c1, unsigned *flags, unsigned char *smem,
+                                     int tid)
+{
+    const Q2Job job{g.n_cells, g.n_nodes, g.coords, g.conn, g.mat, g.out_el, g.out_mass, g.out_lap, flags, g.tab};
+    q2_run<MM, true>(job, c0, c1, 1, smem, tid);
+}
+
 __global__ void k_batch_reset(unsigned long long *ctr) { ctr[0] = 0ULL; }
 
 template <typename T>
-__global__ __launch_bounds__(256, 3) void k_batch(const BatchDev *B, unsigned long long *ctr, unsigned *flags)
+__global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) void k_batch(const BatchDev *B, unsigned long long *ctr, unsigned *flags)
 {
     __shared__ __align__(16) unsigned char smem[BatchLds<T>::BYTES];
     __shared__ long long s_item;
@@ -185,23 +361,34 @@ __global__ __launch_bounds__(256, 3) void k_batch(const BatchDev *B, unsigned lo
     for (;;) {
         if (threadIdx.x == 0) s_item = static_cast<long long>(atomicAdd(ctr, 1ULL));
         __syncthreads();
-        const int64_t it = s_item;
+        // the item number is the same for the whole workgroup; saying so
+        // (readfirstlane) keeps the group descriptor and every branch on it
+        // in scalar registers instead of per-lane ones
+        const long long sv = s_item;
+        const int64_t it = static_cast<int64_t>(
+            (static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(sv >> 32)))) << 32) |
+            static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(sv & 0xffffffff))));
         __syncthreads();
         if (it >= n_items) break;  // every workgroup leaves once the queue is drained
+        // the thread index, re-read each item through an opaque move: the
+        // per-thread offsets the item routines derive from it are then
+        // recomputed per item instead of being hoisted out of this loop and
+        // kept live (in registers the routines need) for the whole kernel
+        int tid;
+        asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"(static_cast<int>(threadIdx.x)));
         int gi = 0;
         while (gi + 1 < ng && it >= B->g[gi + 1].item0) gi++;
         const GroupDev &g = B->g[gi];
         const int64_t c0 = (it - g.item0) * g.tile;
         const int64_t c1 = c0 + g.tile < g.n_cells ? c0 + g.tile : g.n_cells;
         if (g.cell == FE_CELL_HEX && g.order == 2) {
-            const Q2Job job{g.n_cells, g.n_nodes, g.coords, g.conn, g.mat, g.out_el, g.out_mass, g.out_lap, flags, g.tab};
-            q2_run<MM, true>(job, c0, c1, 1, smem);
+            q2_item<MM>(g, c0, c1, flags, smem, tid);
         } else if (g.cell == FE_CELL_HEX && g.order == 1) {
-            fused_tile<FE_CELL_HEX, 1, T>(g, c0, c1, flags, smem);
+            small_tile<FE_CELL_HEX, 1, T>(g, c0, c1, flags, smem, tid);
         } else if (g.cell == FE_CELL_TET && g.order == 1) {
-            fused_tile<FE_CELL_TET, 1, T>(g, c0, c1, flags, smem);
+            small_tile<FE_CELL_TET, 1, T>(g, c0, c1, flags, smem, tid);
         } else if (g.cell == FE_CELL_TET && g.order == 2) {
-            fused_tile<FE_CELL_TET, 2, T>(g, c0, c1, flags, smem);
+            small_tile<FE_CELL_TET, 2, T>(g, c0, c1, flags, smem, tid);
         }
     }
 }
@@ -209,12 +396,9 @@ __global__ __launch_bounds__(256, 3) void k_batch(const BatchDev *B, unsigned lo
 int group_pass_cells(int cell, int order, bool f64)
 {
     if (cell == FE_CELL_HEX && order == 2) return 1;
-    if (f64) {
-        if (cell == FE_CELL_HEX) return Fused<FE_CELL_HEX, 1, double>::E;
-        return order == 1 ? Fused<FE_CELL_TET, 1, double>::E : Fused<FE_CELL_TET, 2, double>::E;
-    }
-    if (cell == FE_CELL_HEX) return Fused<FE_CELL_HEX, 1, float>::E;
-    return order == 1 ? Fused<FE_CELL_TET, 1, float>::E : Fused<FE_CELL_TET, 2, float>::E;
+    if (cell == FE_CELL_HEX) return f64 ? SmallMM<FE_CELL_HEX, 1, double>::CPP : SmallMM<FE_CELL_HEX, 1, float>::CPP;
+    if (order == 1) return f64 ? SmallMM<FE_CELL_TET, 1, double>::CPP : SmallMM<FE_CELL_TET, 1, float>::CPP;
+    return f64 ? SmallMM<FE_CELL_TET, 2, double>::CPP : SmallMM<FE_CELL_TET, 2, float>::CPP;
 }
 
 }  // namespace

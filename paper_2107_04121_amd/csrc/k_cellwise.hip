@@ -52,7 +52,7 @@ __global__ __launch_bounds__(64) void k_cw_scalar(ExecArgs A)
 {
     using C = CwScalar<CELL, P, FORM, T>;
     constexpr int NB = C::NB, NQ = C::NQ, NP = C::NP, ND = C::ND, RC = C::RC, SS = C::SS;
-    constexpr bool AFFINE = C::S::AFFINE, X_LDS = C::X_LDS;
+    constexpr bool X_LDS = C::X_LDS;
     __shared__ T stage[64 * SS];
     __shared__ double xs[X_LDS ? 64 * XLds<NB>::STRIDE : 1];
     const int lane = threadIdx.x;
@@ -75,86 +75,7 @@ __global__ __launch_bounds__(64) void k_cw_scalar(ExecArgs A)
     }
 
     T acc[NP];
-#pragma unroll
-    for (int p = 0; p < NP; p++) acc[p] = T(0);
-
-    double adj[3][3];
-    double det = 0.0;
-    if constexpr (AFFINE) {
-        det = jac_adj<NB, NQ>(x, bfgT, 0, adj);
-        if (valid && !(det > 0.0)) fault |= FAULT_DET;
-    }
-    if constexpr (FORM == FE_FORM_LAPLACE && AFFINE) {
-        // constant gradients: K = (sum_q w_q / det J) H H^T
-        double wsum = 0.0;
-        for (int q = 0; q < NQ; q++) wsum += w[q];
-        const double s = wsum / det;
-        T H[NB][3], sH[NB][3];
-#pragma unroll
-        for (int a = 0; a < NB; a++)
-#pragma unroll
-            for (int i = 0; i < 3; i++) {
-                const double h = h_comp<NB, NQ>(bfgT, adj, 0, a, i);
-                H[a][i] = static_cast<T>(h);
-                sH[a][i] = static_cast<T>(s * h);
-            }
-#pragma unroll
-        for (int a = 0; a < NB; a++)
-#pragma unroll
-            for (int b = a; b < NB; b++)
-                acc[tri(a, b, NB)] = sH[a][0] * H[b][0] + sH[a][1] * H[b][1] + sH[a][2] * H[b][2];
-    } else {
-#pragma unroll 1
-        for (int q = 0; q < NQ; q++) {
-            if constexpr (!AFFINE) {
-                det = jac_adj<NB, NQ>(x, bfgT, q, adj);
-                if (valid && !(det > 0.0)) fault |= FAULT_DET;
-            }
-            if constexpr (FORM == FE_FORM_LAPLACE) {
-                const double s = w[q] / det;
-                T H[NB][3];
-#pragma unroll
-                for (int a = 0; a < NB; a++)
-#pragma unroll
-                    for (int i = 0; i < 3; i++) H[a][i] = static_cast<T>(h_comp<NB, NQ>(bfgT, adj, q, a, i));
-                if constexpr (sizeof(T) == 8) {
-                    // acc += s (H_a . H_b): no scaled copy of H, fewer registers
-#pragma unroll
-                    for (int a = 0; a < NB; a++)
-#pragma unroll
-                        for (int b = a; b < NB; b++) {
-                            const T d = H[a][0] * H[b][0] + H[a][1] * H[b][1] + H[a][2] * H[b][2];
-                            acc[tri(a, b, NB)] = fma(static_cast<T>(s), d, acc[tri(a, b, NB)]);
-                        }
-                } else {
-                    const T sf = static_cast<T>(s);
-#pragma unroll
-                    for (int a = 0; a < NB; a++) {
-                        const T h0 = sf * H[a][0], h1 = sf * H[a][1], h2 = sf * H[a][2];
-#pragma unroll
-                        for (int b = a; b < NB; b++) {
-                            T v = acc[tri(a, b, NB)];
-                            v = fma(h0, H[b][0], v);
-                            v = fma(h1, H[b][1], v);
-                            v = fma(h2, H[b][2], v);
-                            acc[tri(a, b, NB)] = v;
-                        }
-                    }
-                }
-            } else {
-                const T wd = static_cast<T>(w[q] * det);
-                T phi[NB];
-#pragma unroll
-                for (int a = 0; a < NB; a++) phi[a] = static_cast<T>(bf[q * NB + a]);
-#pragma unroll
-                for (int a = 0; a < NB; a++) {
-                    const T wa = wd * phi[a];
-#pragma unroll
-                    for (int b = a; b < NB; b++) acc[tri(a, b, NB)] = fma(wa, phi[b], acc[tri(a, b, NB)]);
-                }
-            }
-        }
-    }
+    acc_scalar<CELL, P, FORM == FE_FORM_VMASS ? FE_FORM_MASS : FORM, T>(x, w, bf, bfgT, valid, fault, acc);
 
     if (fault) raise_fault(A.flags, fault);
 
@@ -201,8 +122,8 @@ __device__ __forceinline__ void elast_block(const ExecArgs &A, int64_t e0, const
 {
     using C = CwElast<CELL, P, T>;
     constexpr int NB = C::NB, NQ = C::NQ, ND = C::ND, RH = C::RH, SS = C::SS;
-    constexpr bool AFFINE = C::S::AFFINE, DIAG = R == S;
-    constexpr int NACC = DIAG ? NB * (NB + 1) / 2 : NB * NB;
+    constexpr bool DIAG = R == S;
+    constexpr int NACC = ElastAcc<NB, R, S>::N;
     const int tid = threadIdx.x, lane = tid & 63;
     const int64_t e = e0 + lane;
     const bool valid = e < A.n_cells;
@@ -212,68 +133,8 @@ __device__ __forceinline__ void elast_block(const ExecArgs &A, int64_t e0, const
     const bool per_qp = A.mat_kind == FE_MAT_ISO_QP;
     const XLds<NB> x{xs + lane * XLds<NB>::STRIDE};
 
-    T lam = T(0), mu = T(0);
-    if (valid && !per_qp) {
-        lam = mat[2 * e];
-        mu = mat[2 * e + 1];
-    }
     T acc[NACC];
-#pragma unroll
-    for (int p = 0; p < NACC; p++) acc[p] = T(0);
-    double adj[3][3];
-    double det = 0.0;
-    if constexpr (AFFINE) {
-        det = jac_adj<NB, NQ>(x, bfgT, 0, adj);
-        if (valid && !(det > 0.0)) fault |= FAULT_DET;
-    }
-#pragma unroll 1
-    for (int q = 0; q < NQ; q++) {
-        if constexpr (!AFFINE) {
-            det = jac_adj<NB, NQ>(x, bfgT, q, adj);
-            if (valid && !(det > 0.0)) fault |= FAULT_DET;
-        }
-        if (valid && per_qp) {
-            lam = mat[2 * (e * NQ + q)];
-            mu = mat[2 * (e * NQ + q) + 1];
-        }
-        const T sd = static_cast<T>(w[q] / det);
-        const int qg = AFFINE ? 0 : q;  // table column of the gradients
-        if constexpr (DIAG) {
-            T H[NB][3];
-#pragma unroll
-            for (int a = 0; a < NB; a++)
-#pragma unroll
-                for (int i = 0; i < 3; i++) H[a][i] = static_cast<T>(h_comp<NB, NQ>(bfgT, adj, qg, a, i));
-            const T c1 = sd * (lam + mu), c2 = sd * mu;
-#pragma unroll
-            for (int a = 0; a < NB; a++) {
-                const T y = c1 * H[a][R], z0 = c2 * H[a][0], z1 = c2 * H[a][1], z2 = c2 * H[a][2];
-#pragma unroll
-                for (int b = a; b < NB; b++) {
-                    T v = acc[tri(a, b, NB)];
-                    v = fma(y, H[b][R], v);
-                    v = fma(z0, H[b][0], v);
-                    v = fma(z1, H[b][1], v);
-                    v = fma(z2, H[b][2], v);
-                    acc[tri(a, b, NB)] = v;
-                }
-            }
-        } else {
-            T Hr[NB], Hs[NB];
-#pragma unroll
-            for (int a = 0; a < NB; a++) {
-                Hr[a] = static_cast<T>(h_comp<NB, NQ>(bfgT, adj, qg, a, R));
-                Hs[a] = static_cast<T>(h_comp<NB, NQ>(bfgT, adj, qg, a, S));
-            }
-            const T sl = sd * lam, sm = sd * mu;
-#pragma unroll
-            for (int a = 0; a < NB; a++) {
-                const T u = sl * Hr[a], v = sm * Hs[a];
-#pragma unroll
-                for (int b = 0; b < NB; b++) acc[a * NB + b] = fma(u, Hs[b], fma(v, Hr[b], acc[a * NB + b]));
-            }
-        }
-    }
+    acc_elast<CELL, P, T, R, S>(x, w, bfgT, mat, per_qp, e, valid, fault, acc);
 
     if (fault) raise_fault(A.flags, fault);
 
@@ -283,27 +144,8 @@ __device__ __forceinline__ void elast_block(const ExecArgs &A, int64_t e0, const
     for (int c = 0; c < 3; c++) {
 #pragma unroll
         for (int h = 0; h < NB / RH; h++) {
-            if (c == R) {  // rows of block (R, S)
-#pragma unroll
-                for (int rr = 0; rr < RH; rr++) {
-                    const int a = h * RH + rr;
-#pragma unroll
-                    for (int b = 0; b < NB; b++) {
-                        T v;
-                        if constexpr (DIAG) v = a <= b ? acc[tri(a, b, NB)] : acc[tri(b, a, NB)];
-                        else v = acc[a * NB + b];
-                        stage[lane * SS + rr * ND + S * NB + b] = v;
-                    }
-                }
-            }
-            if (!DIAG && c == S) {  // rows of block (S, R) = (R, S)^T
-#pragma unroll
-                for (int rr = 0; rr < RH; rr++) {
-                    const int b = h * RH + rr;
-#pragma unroll
-                    for (int a = 0; a < NB; a++) stage[lane * SS + rr * ND + R * NB + a] = acc[a * NB + b];
-                }
-            }
+            if (c == R) stage_block<NB, ND, RH, R, S, false>(acc, stage + lane * SS, h * RH, S * NB);
+            if (!DIAG && c == S) stage_block<NB, ND, RH, R, S, true>(acc, stage + lane * SS, h * RH, R * NB);
             __syncthreads();
             const int64_t row0 = c * NB + h * RH;
             for (int k = tid; k < 64 * RH * ND; k += ELAST_THREADS) {

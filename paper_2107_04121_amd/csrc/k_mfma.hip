@@ -43,7 +43,7 @@ __global__ __launch_bounds__(256, MM == MM_F32 ? 4 : 3) void k_elast_q2(ExecArgs
     int64_t e, e_end, stride;
     cell_range(A.xcd_remap, A.n_cells, e, e_end, stride);
     const Q2Job job{A.n_cells, A.n_nodes, A.coords, A.conn, A.mat, A.out, nullptr, nullptr, A.flags, A.tab};
-    q2_run<MM, false>(job, e, e_end, stride, smem);
+    q2_run<MM, false>(job, e, e_end, stride, smem, threadIdx.x);
 }
 
 template <int MM>

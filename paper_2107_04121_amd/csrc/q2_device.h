@@ -39,7 +39,9 @@ struct Q2Layout {
     static constexpr int KP = MM == MM_BF16X3 ? 32 : 28;  // padded K (quadrature points)
     // kept for the whole launch: 1-D tables and weights
     static constexpr int OFF_TB = 0;                      // double B1[9], D1[9], w[27]
-    static constexpr int OFF_U = align16(OFF_TB + (9 + 9 + NQ) * 8);
+    // the next cell's coordinates and coefficients, parked before the flush
+    static constexpr int OFF_N = align16(OFF_TB + (9 + 9 + NQ) * 8);  // double xn[81], T lmn[2]
+    static constexpr int OFF_U = align16(OFF_N + 81 * 8 + 2 * 8);
     // phase A (per cell): geometry and GEMM operand
     static constexpr int OFF_X = OFF_U;                   // double xc[3][28] (component-major)
     static constexpr int OFF_J = OFF_X + 3 * 28 * 8;      // double J[27][9]
@@ -248,7 +250,8 @@ struct Q2Job {
 // product on the matrix cores), sharing the geometry.  smem must hold
 // Q2Layout<MM>::BYTES.  Ends with the workgroup synchronised.
 template <int MM, bool MULTI>
-__device__ __forceinline__ void q2_run(const Q2Job &A, int64_t e, int64_t e_end, int64_t stride, unsigned char *smem)
+__device__ __forceinline__ void q2_run(const Q2Job &A, int64_t e, int64_t e_end, int64_t stride, unsigned char *smem,
+                                       int tid)
 {
     using L = Q2Layout<MM>;
     using T = typename L::T;
@@ -257,12 +260,14 @@ __device__ __forceinline__ void q2_run(const Q2Job &A, int64_t e, int64_t e_end,
     double *B1 = reinterpret_cast<double *>(smem + L::OFF_TB);
     double *D1 = B1 + 9;
     double *wq = D1 + 9;
+    double *xn = reinterpret_cast<double *>(smem + L::OFF_N);
+    T *lmn = reinterpret_cast<T *>(xn + 81);
     double *xc = reinterpret_cast<double *>(smem + L::OFF_X);
     double *Jq = reinterpret_cast<double *>(smem + L::OFF_J);
     double *wd = reinterpret_cast<double *>(smem + L::OFF_WD);
     T *Gs = reinterpret_cast<T *>(smem + L::OFF_G);
     T *Ks = reinterpret_cast<T *>(smem + L::OFF_K);
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int wave = tid >> 6, lane = tid & 63;
     if (e >= e_end) return;  // uniform over the workgroup
 
     if (tid < 9) {
@@ -274,20 +279,26 @@ __device__ __forceinline__ void q2_run(const Q2Job &A, int64_t e, int64_t e_end,
     const T *mat = static_cast<const T *>(A.mat);
     // this thread's node coordinate (threads < 81: node a = tid/3, axis tid%3)
     const int ga = tid / 3, gc = tid - 3 * (tid / 3);
-    double xval = 0.0;
+    // the first cell's coordinates and coefficients go to the parking slots
+    // the loop reads every cell's data from (see the park step below)
     if (tid < NB * 3) {
         const int64_t n = checked_node(A.conn, e * NB + ga, A.n_nodes, A.flags);
-        xval = A.coords[3 * n + gc];
+        xn[tid] = A.coords[3 * n + gc];
     }
-    T lam = mat[2 * e], mu = mat[2 * e + 1];
+    if (tid == 0) {
+        lmn[0] = mat[2 * e];
+        lmn[1] = mat[2 * e + 1];
+    }
+    __syncthreads();
 
     for (;;) {
         const int64_t en = e + stride;
         const bool has_next = en < e_end;
+        const T lam = lmn[0], mu = lmn[1];  // read before the park step rewrites them
 
         // 1. this cell's coordinates to LDS (component-major); zero the
         //    GEMM operand; prefetch the next cell's connectivity
-        if (tid < NB * 3) xc[gc * 28 + ga] = xval;
+        if (tid < NB * 3) xc[gc * 28 + ga] = xn[tid];
         if (tid == 255) wd[NQ] = 0.0;
         // zero the operand padding: rows a = 27..32 of each component, and
         // columns k = 27..KP-1 of the real rows
@@ -300,8 +311,6 @@ __device__ __forceinline__ void q2_run(const Q2Job &A, int64_t e, int64_t e_end,
                 Gs[((row / NB) * 33 + row % NB) * L::KS + k] = T(0);
             }
         }
-        int32_t nn = 0;
-        if (has_next && tid < NB * 3) nn = A.conn[en * NB + ga];
         __syncthreads();
 
         // 2. J[i][j] at quadrature point q, one entry per thread (243
@@ -333,19 +342,17 @@ __device__ __forceinline__ void q2_run(const Q2Job &A, int64_t e, int64_t e_end,
         // 3. det J and J^-1 per quadrature point (FP64, recomputed by each
         //    of the 9 threads of a point), w det J; then
         //    G[q][i][a] = sum_j dphi_a/dxi_j Jinv[j][i] (stored as T), one
-        //    (q, i, a2) triple per thread, 9 basis functions each.  The next
-        //    cell's coordinates and coefficients are prefetched here.
-        double xnext = 0.0;
+        //    (q, i, a2) triple per thread, 9 basis functions each.
+        //
+        //    Prefetch of the next cell, in two hops that are each waited for
+        //    one phase after they are issued: its connectivity and
+        //    coefficients here, its coordinates after the GEMM, parked in LDS
+        //    after the epilogue.  Every wait thus falls before this cell's
+        //    flush; the previous cell's flush drains during phases 1-4.
+        int32_t nn = 0;
         T lamn = T(0), mun = T(0);
         if (has_next) {
-            if (tid < NB * 3) {
-                int64_t n = nn;
-                if (n < 0 || n >= A.n_nodes) {
-                    raise_fault(A.flags, FAULT_INDEX);
-                    n = 0;
-                }
-                xnext = A.coords[3 * n + gc];
-            }
+            if (tid < NB * 3) nn = A.conn[en * NB + ga];
             lamn = mat[2 * en];
             mun = mat[2 * en + 1];
         }
@@ -396,6 +403,20 @@ __device__ __forceinline__ void q2_run(const Q2Job &A, int64_t e, int64_t e_end,
             }
         }
         __syncthreads();  // every wave is done reading the operands
+
+        // second prefetch hop: the next cell's coordinates.  The empty asm
+        // keeps the first use of the connectivity value (and so the wait for
+        // its load) here instead of next to the load.
+        double xnext = 0.0;
+        if (has_next && tid < NB * 3) {
+            asm volatile("" : "+v"(nn));
+            int64_t n = nn;
+            if (n < 0 || n >= A.n_nodes) {
+                raise_fault(A.flags, FAULT_INDEX);
+                n = 0;
+            }
+            xnext = A.coords[3 * n + gc];
+        }
 
         // 5. the blocks r <= s of P go straight to their places in the
         //    staging area that holds the cell's matrix row-major, shifted by
@@ -475,48 +496,52 @@ __device__ __forceinline__ void q2_run(const Q2Job &A, int64_t e, int64_t e_end,
                 }
             }
         }
+        // park the prefetched next-cell data in LDS: no loaded register stays
+        // live across the flush, so nothing after the flush waits for its
+        // stores to drain (vector memory counters complete in order)
+        if (has_next) {
+            if (tid < NB * 3) xn[tid] = xnext;
+            if (tid == 0) {
+                lmn[0] = lamn;
+                lmn[1] = mun;
+            }
+        }
         __syncthreads();
 
         // 7. linear flush: consecutive lanes store consecutive 16-byte vectors
-        //    of the cell's contiguous output (all LDS reads first); partial
-        //    head/tail vectors go entry by entry
+        //    of the cell's contiguous output (LDS reads batched ahead of the
+        //    stores); the few entries before the first and after the last
+        //    whole vector go one by one
         {
             T *out = static_cast<T *>(A.out);
             TV *aligned = reinterpret_cast<TV *>(out + (base - h));
-            const int nvec = (NK + h + L::VEC - 1) / L::VEC;
             const TV *k16 = reinterpret_cast<const TV *>(Ks);
+            const int vf = h ? 1 : 0, vl = (NK + h) / L::VEC;  // whole vectors [vf, vl)
             constexpr int BATCH = 4;
 #pragma unroll
             for (int j0 = 0; j0 < L::NV; j0 += BATCH) {
                 TV buf[BATCH];
 #pragma unroll
                 for (int j = 0; j < BATCH; j++) {
-                    const int v = tid + 256 * (j0 + j);
-                    if (j0 + j < L::NV && v < nvec) buf[j] = k16[v];
+                    const int v = vf + tid + 256 * (j0 + j);
+                    if (v < vl) buf[j] = k16[v];
                 }
 #pragma unroll
                 for (int j = 0; j < BATCH; j++) {
-                    const int v = tid + 256 * (j0 + j);
-                    if (j0 + j >= L::NV || v >= nvec) break;
-                    const int lo = v * L::VEC - h;
-                    if (lo >= 0 && lo + L::VEC <= NK) {
-                        out_store(buf[j], aligned + v);
-                    } else {
-#pragma unroll
-                        for (int u = 0; u < L::VEC; u++) {
-                            const int f = lo + u;
-                            if (f >= 0 && f < NK) out[base + f] = buf[j][u];
-                        }
-                    }
+                    const int v = vf + tid + 256 * (j0 + j);
+                    if (v < vl) out_store(buf[j], aligned + v);
                 }
+            }
+            if (tid < 2 * L::VEC) {
+                const int f = tid < L::VEC ? tid : vl * L::VEC - h + (tid - L::VEC);
+                const bool head = tid < L::VEC && f < vf * L::VEC - h;
+                const bool tail = tid >= L::VEC && f < NK;
+                if (head || tail) out[base + f] = Ks[h + f];
             }
         }
         __syncthreads();  // the staging area is reused by the next cell
         if (!has_next) break;
         e = en;
-        xval = xnext;
-        lam = lamn;
-        mu = mun;
     }
 }
 
