@@ -6,301 +6,437 @@
 // contraction.  On a tensor-product cell every one of those contractions over
 // the (p+1)^3 nodes factors into three one-dimensional ones:
 //   dx_i/dxi_0 (q) = sum_a2 B[q2][a2] sum_a1 B[q1][a1] sum_a0 D[q0][a0] x_i[a]
-// (B, D: 1-D basis values/derivatives at the 1-D Gauss points), and the
-// transposed contraction
+// (B, D: 1-D basis values/derivatives at the 1-D Gauss points, [q][a]), and
+// the transposed contraction
 //   r[a] = sum_q0 ( D[q0][a0] W0 + B[q0][a0] W12 ),
 //   W0 = sum_q1 B[q1][a1] sum_q2 B[q2][a2] F0,
 //   W12 = sum_q1 ( D[q1][a1] sum_q2 B[q2][a2] F1 + B[q1][a1] sum_q2 D[q2][a2] F2 ),
-// which cuts the geometry work from 9 n_b n_q to about 48 (p+1)^4 FMA per
-// component.  The Jacobian, its determinant and inverse stay FP64; u, the
-// flux and the residual use the plan's precision.
+// which cuts the work from O(p^6) to O(p^4) per cell.  The Jacobian, its
+// determinant and inverse stay FP64; u, the flux and the residual use the
+// plan's precision.
 //
-// Mapping: one lane per point (node index and quadrature-point index share
-// the lexicographic (i0, i1, i2) numbering), (p+1)^3 lanes per cell, as many
-// cells per 256-thread workgroup as fit; each 1-D stage reads its 4 (or 3,
-// 2) operands from LDS.  Output layouts: cell-major [n_cells][n_comp][n_b]
-// (default) or cell-minor [n_comp][n_b][n_cells].
-#include "fe_device.h"
+// Mapping: one lane per pencil, i.e. per line of N1 = p+1 points along one
+// axis, so each 1-D contraction runs in the lane's registers; a cell takes
+// N1^2 lanes of one wave (64 / N1^2 cells per wave).  Between the three axes
+// the pencil values are transposed through the cell's LDS arrays; the lanes
+// of a cell belong to one wave, so only wave-level ordering is needed, never
+// a workgroup barrier.  Every array plane is padded by one entry.  The
+// geometry is evaluated one coordinate component at a time and u one DOF
+// component at a time, so a cell needs three stage arrays.
+//
+// Output layouts: cell-major [n_cells][n_comp][n_b] (default) or cell-minor
+// [n_comp][n_b][n_cells].
+#include "cw_device.h"
 
 namespace fe {
 namespace {
 
+using cw::ctab;
+using cw::ctab_t;
+
+// LDS writes of a wave before this point are seen by its LDS reads after it
+// (a wave's LDS operations execute in order; this keeps the compiler from
+// moving them across).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int P, int FORM, typename T>
 struct SF {
-    static constexpr int N1 = P + 1, NP = N1 * N1 * N1;
+    static constexpr int N1 = P + 1, NPL = N1 * N1, NP = N1 * NPL;
+    static constexpr int CW = 64 / NPL;  // cells per wave
+    static constexpr int CB = 4 * CW;    // cells per 256-thread workgroup
     static constexpr int NC = form_nc(FORM);
-    static constexpr int C = 256 / NP;  // cells per workgroup
     static constexpr bool GRAD = FORM == FE_FORM_LAPLACE || FORM == FE_FORM_ELASTICITY;
-    // LDS per cell: coordinates, geometry stage buffers (FP64), u, u stage
-    // buffers, residual stage buffers (T); phases reuse one scratch region
-    static constexpr int GEO = (3 + 2 * 3 + 3 * 3) * NP * 8;
-    static constexpr int UST = (NC + 2 * NC + 3 * NC) * NP * (int)sizeof(T);
-    static constexpr int RST = (3 * NC + 3 * NC + 2 * NC) * NP * (int)sizeof(T);
-    static constexpr int SCR = GEO > UST ? (GEO > RST ? GEO : RST) : (UST > RST ? UST : RST);
-    static constexpr int PER = SCR + NP * (int)sizeof(T);  // + per-point energy
-    static constexpr int BYTES = C * PER + 4 * N1 * N1 * 8;
+    static constexpr int ZS = NPL + 1;       // stride of the x2 planes (padded)
+    static constexpr int AS = N1 * ZS + 1;   // one stage array (entries, padded)
+    // three arrays per cell (in double slots); the cell stride is an odd
+    // multiple of 8 doubles (16 four-byte banks), so consecutive cells of a
+    // wave start half a bank row apart
+    static constexpr int CELL = ((3 * AS + 7) / 8 % 2 == 0 ? (3 * AS + 7) / 8 + 1 : (3 * AS + 7) / 8) * 8;
 };
 
-// One 1-D contraction along axis AX for lane l = (i0, i1, i2):
-//   out = sum_k M[k][idx] f(.., k at AX, ..)   when TR (transposed: sum over
-//         the quadrature index k, the lane's AX index is the basis index)
-//   out = sum_k M[idx][k] f(.., k at AX, ..)   otherwise
-template <int N1, int AX, bool TR, typename T, typename M>
-__device__ __forceinline__ T c1d(const T *f, const M *tab, int l, int idx)
+// 1-D tables B[q][a], D[q][a]: FP64 through the scalar unit for the
+// geometry, or converted once into registers in the contraction type.
+struct TabC {
+    const ctab_t *B, *D;
+    __device__ __forceinline__ double b(int i) const { return B[i]; }
+    __device__ __forceinline__ double d(int i) const { return D[i]; }
+};
+template <typename V, int NN>
+struct TabR {
+    V B[NN], D[NN];
+    __device__ __forceinline__ V b(int i) const { return B[i]; }
+    __device__ __forceinline__ V d(int i) const { return D[i]; }
+};
+
+template <int N1, int ZS>
+__device__ __forceinline__ int idx(int x0, int x1, int x2)
 {
-    constexpr int S = AX == 0 ? 1 : (AX == 1 ? N1 : N1 * N1);
-    const int base = l - idx * S;
-    T s = T(0);
+    return x0 + N1 * x1 + ZS * x2;
+}
+
+// Three 1-D passes of one scalar field f given on the lane's axis-0 pencil
+// (nodes (a0, p0, p1), a0 = 0..N1-1), through the cell's stage arrays L.
+// GRAD: returns the reference gradient at the lane's axis-2 pencil of points
+// (p0, p1, q2): g[q2][j] = d f / d xi_j; else the value v[q2].
+template <int N1, int ZS, int AS, bool GRAD, typename V, typename TB>
+__device__ __forceinline__ void forward3(const V (&f)[N1], V *L, const TB &tb, int p0, int p1, bool slot,
+                                         V (&g)[N1][3], V (&v)[N1])
+{
+    V b0[N1], d0[N1];
 #pragma unroll
-    for (int k = 0; k < N1; k++) s += static_cast<T>(TR ? tab[k * N1 + idx] : tab[idx * N1 + k]) * f[base + k * S];
-    return s;
+    for (int q = 0; q < N1; q++) {
+        V sb = V(0), sd = V(0);
+#pragma unroll
+        for (int a = 0; a < N1; a++) {
+            sb += static_cast<V>(tb.b(q * N1 + a)) * f[a];
+            if constexpr (GRAD) sd += static_cast<V>(tb.d(q * N1 + a)) * f[a];
+        }
+        b0[q] = sb;
+        d0[q] = sd;
+    }
+    if (slot)
+#pragma unroll
+        for (int q = 0; q < N1; q++) {
+            L[idx<N1, ZS>(q, p0, p1)] = b0[q];
+            if constexpr (GRAD) L[AS + idx<N1, ZS>(q, p0, p1)] = d0[q];
+        }
+    wave_sync();
+    // axis 1: lane = pencil (p0, *, p1)
+    V gb[N1], gd[N1];
+#pragma unroll
+    for (int k = 0; k < N1; k++) {
+        gb[k] = L[idx<N1, ZS>(p0, k, p1)];
+        if constexpr (GRAD) gd[k] = L[AS + idx<N1, ZS>(p0, k, p1)];
+    }
+    V bb[N1], bd[N1], db[N1];
+#pragma unroll
+    for (int q = 0; q < N1; q++) {
+        V s0 = V(0), s1 = V(0), s2 = V(0);
+#pragma unroll
+        for (int k = 0; k < N1; k++) {
+            s0 += static_cast<V>(tb.b(q * N1 + k)) * gb[k];
+            if constexpr (GRAD) {
+                s1 += static_cast<V>(tb.d(q * N1 + k)) * gb[k];
+                s2 += static_cast<V>(tb.b(q * N1 + k)) * gd[k];
+            }
+        }
+        bb[q] = s0;
+        bd[q] = s1;
+        db[q] = s2;
+    }
+    // this lane's own pencil positions only: no other lane reads them now
+    if (slot)
+#pragma unroll
+        for (int q = 0; q < N1; q++) {
+            L[idx<N1, ZS>(p0, q, p1)] = bb[q];
+            if constexpr (GRAD) {
+                L[AS + idx<N1, ZS>(p0, q, p1)] = bd[q];
+                L[2 * AS + idx<N1, ZS>(p0, q, p1)] = db[q];
+            }
+        }
+    wave_sync();
+    // axis 2: lane = pencil (p0, p1, *)
+    V cb[N1], cd[N1], ce[N1];
+#pragma unroll
+    for (int k = 0; k < N1; k++) {
+        cb[k] = L[idx<N1, ZS>(p0, p1, k)];
+        if constexpr (GRAD) {
+            cd[k] = L[AS + idx<N1, ZS>(p0, p1, k)];
+            ce[k] = L[2 * AS + idx<N1, ZS>(p0, p1, k)];
+        }
+    }
+    wave_sync();  // the arrays are rewritten by the next pass
+#pragma unroll
+    for (int q = 0; q < N1; q++) {
+        V s0 = V(0), s1 = V(0), s2 = V(0);
+#pragma unroll
+        for (int k = 0; k < N1; k++) {
+            if constexpr (GRAD) {
+                s0 += static_cast<V>(tb.b(q * N1 + k)) * ce[k];  // D B B
+                s1 += static_cast<V>(tb.b(q * N1 + k)) * cd[k];  // B D B
+                s2 += static_cast<V>(tb.d(q * N1 + k)) * cb[k];  // B B D
+            } else {
+                s0 += static_cast<V>(tb.b(q * N1 + k)) * cb[k];
+            }
+        }
+        if constexpr (GRAD) {
+            g[q][0] = s0;
+            g[q][1] = s1;
+            g[q][2] = s2;
+        } else {
+            v[q] = s0;
+        }
+    }
 }
 
 template <int P, int FORM, typename T>
 __global__ __launch_bounds__(256) void k_sf(ExecArgs A, int cell_minor)
 {
     using S = SF<P, FORM, T>;
-    constexpr int N1 = S::N1, NP = S::NP, NC = S::NC, C = S::C;
-    extern __shared__ __align__(16) unsigned char smem[];
-    double *Bd = reinterpret_cast<double *>(smem);  // B[q][a], D[q][a] FP64
-    double *Dd = Bd + N1 * N1;
-    T *Bt = reinterpret_cast<T *>(Dd + N1 * N1);     // same in T
-    T *Dt = Bt + N1 * N1;
-    unsigned char *cells = smem + 4 * N1 * N1 * 8;
+    constexpr int N1 = S::N1, NPL = S::NPL, NP = S::NP, CW = S::CW, NC = S::NC, ZS = S::ZS, AS = S::AS;
+    constexpr bool GRAD = S::GRAD;
+    __shared__ double lds[S::CB * S::CELL];
 
-    const int tid = threadIdx.x;
-    const int cs = tid / NP, l = tid - cs * NP;
-    const int i0 = l % N1, i1 = (l / N1) % N1, i2 = l / (N1 * N1);
-    const int64_t e = logical_block(A.xcd_remap) * C + cs;
-    const bool live = cs < C && e < A.n_cells;
-    unsigned char *mine = cells + (cs < C ? cs : 0) * S::PER;
-    double *X = reinterpret_cast<double *>(mine);  // [3][NP] then stage buffers
-    T *en = reinterpret_cast<T *>(mine + S::SCR);
-
-    if (tid < N1 * N1) {
-        Bd[tid] = A.tab.B1[tid];
-        Dd[tid] = A.tab.D1[tid];
-        Bt[tid] = static_cast<T>(A.tab.B1[tid]);
-        Dt[tid] = static_cast<T>(A.tab.D1[tid]);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int cw = lane / NPL, pp = lane - cw * NPL;
+    const int p0 = pp % N1, p1 = pp / N1;
+    const bool slot = cw < CW;  // lanes 64 - 64 % NPL .. 63 hold no cell
+    const int cslot = slot ? cw : 0;
+    const int64_t e = logical_block(A.xcd_remap) * S::CB + wave * CW + cslot;
+    const bool live = slot && e < A.n_cells;
+    double *Ld = lds + (wave * CW + cslot) * S::CELL;
+    T *Lt = reinterpret_cast<T *>(Ld);
+    const TabC tc{ctab(A.tab.B1), ctab(A.tab.D1)};
+    TabR<T, N1 * N1> tt;
+#pragma unroll
+    for (int i = 0; i < N1 * N1; i++) {
+        tt.B[i] = static_cast<T>(tc.b(i));
+        tt.D[i] = static_cast<T>(tc.d(i));
     }
-    // gather coordinates and u of this lane's node (node index = l)
-    T u[NC];
-    if (live) {
-        const int64_t n = checked_node(A.conn, e * NP + l, A.n_nodes, A.flags);
-#pragma unroll
-        for (int i = 0; i < 3; i++) X[i * NP + l] = A.coords[3 * n + i];
-        const T *U = static_cast<const T *>(A.dofs);
-#pragma unroll
-        for (int c = 0; c < NC; c++) u[c] = U[n * NC + c];
-    }
-    __syncthreads();
+    unsigned fault = 0;
 
-    // ---- geometry (FP64): J[i][j] at quadrature point l by sum factorization
-    double J[3][3] = {};
-    if constexpr (S::GRAD || true) {
-        double *tA = X + 3 * NP;       // [2][3][NP]  tB, tD
-        double *tB = tA + 6 * NP;      // [3][3][NP]  uBB, uBD, uDB
-        if (live) {
-#pragma unroll
-            for (int i = 0; i < 3; i++) {
-                tA[(0 * 3 + i) * NP + l] = c1d<N1, 0, false>(X + i * NP, Bd, l, i0);
-                tA[(1 * 3 + i) * NP + l] = c1d<N1, 0, false>(X + i * NP, Dd, l, i0);
-            }
-        }
-        __syncthreads();
-        if (live) {
-#pragma unroll
-            for (int i = 0; i < 3; i++) {
-                tB[(0 * 3 + i) * NP + l] = c1d<N1, 1, false>(tA + (0 * 3 + i) * NP, Bd, l, i1);
-                tB[(1 * 3 + i) * NP + l] = c1d<N1, 1, false>(tA + (0 * 3 + i) * NP, Dd, l, i1);
-                tB[(2 * 3 + i) * NP + l] = c1d<N1, 1, false>(tA + (1 * 3 + i) * NP, Bd, l, i1);
-            }
-        }
-        __syncthreads();
-        if (live) {
-#pragma unroll
-            for (int i = 0; i < 3; i++) {
-                J[i][0] = c1d<N1, 2, false>(tB + (2 * 3 + i) * NP, Bd, l, i2);
-                J[i][1] = c1d<N1, 2, false>(tB + (1 * 3 + i) * NP, Bd, l, i2);
-                J[i][2] = c1d<N1, 2, false>(tB + (0 * 3 + i) * NP, Dd, l, i2);
-            }
-        }
-        __syncthreads();  // stage buffers are reused below
-    }
-    double Jid[3][3];
-    const double det = inverse3(J, Jid);
-    if (live && !(det > 0.0)) raise_fault(A.flags, FAULT_DET);
-    const double wq = A.tab.w[l];
-    const T w = static_cast<T>(wq * det);
-    T Ji[3][3];
-#pragma unroll
-    for (int j = 0; j < 3; j++)
-#pragma unroll
-        for (int d = 0; d < 3; d++) Ji[j][d] = static_cast<T>(Jid[j][d]);
-
-    // ---- values / reference gradients of u at the point, in T
-    T *Us = reinterpret_cast<T *>(mine);  // [NC][NP], then stage buffers
-    T *uA = Us + NC * NP;                 // [2][NC][NP]
-    T *uB = uA + 2 * NC * NP;             // [3][NC][NP]
-    if (live)
-#pragma unroll
-        for (int c = 0; c < NC; c++) Us[c * NP + l] = u[c];
-    __syncthreads();
-    T Hx[NC][3];
-    T val[NC];
-    if constexpr (S::GRAD) {
-        if (live) {
-#pragma unroll
-            for (int c = 0; c < NC; c++) {
-                uA[(0 * NC + c) * NP + l] = c1d<N1, 0, false>(Us + c * NP, Bt, l, i0);
-                uA[(1 * NC + c) * NP + l] = c1d<N1, 0, false>(Us + c * NP, Dt, l, i0);
-            }
-        }
-        __syncthreads();
-        if (live) {
-#pragma unroll
-            for (int c = 0; c < NC; c++) {
-                uB[(0 * NC + c) * NP + l] = c1d<N1, 1, false>(uA + (0 * NC + c) * NP, Bt, l, i1);
-                uB[(1 * NC + c) * NP + l] = c1d<N1, 1, false>(uA + (0 * NC + c) * NP, Dt, l, i1);
-                uB[(2 * NC + c) * NP + l] = c1d<N1, 1, false>(uA + (1 * NC + c) * NP, Bt, l, i1);
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int c = 0; c < NC; c++) {
-            Hx[c][0] = live ? c1d<N1, 2, false>(uB + (2 * NC + c) * NP, Bt, l, i2) : T(0);
-            Hx[c][1] = live ? c1d<N1, 2, false>(uB + (1 * NC + c) * NP, Bt, l, i2) : T(0);
-            Hx[c][2] = live ? c1d<N1, 2, false>(uB + (0 * NC + c) * NP, Dt, l, i2) : T(0);
-        }
-    } else {
-        if (live)
-#pragma unroll
-            for (int c = 0; c < NC; c++) uA[c * NP + l] = c1d<N1, 0, false>(Us + c * NP, Bt, l, i0);
-        __syncthreads();
-        if (live)
-#pragma unroll
-            for (int c = 0; c < NC; c++) uB[c * NP + l] = c1d<N1, 1, false>(uA + c * NP, Bt, l, i1);
-        __syncthreads();
-#pragma unroll
-        for (int c = 0; c < NC; c++) val[c] = live ? c1d<N1, 2, false>(uB + c * NP, Bt, l, i2) : T(0);
-    }
-    __syncthreads();  // stage buffers are reused below
-
-    // ---- flux at the point (reference space) and the energy density
-    T F[NC][3];
-    T energy = T(0);
-    if constexpr (S::GRAD) {
-        T H[NC][3];
-#pragma unroll
-        for (int c = 0; c < NC; c++)
-#pragma unroll
-            for (int d = 0; d < 3; d++) H[c][d] = Hx[c][0] * Ji[0][d] + Hx[c][1] * Ji[1][d] + Hx[c][2] * Ji[2][d];
-        T Sg[NC][3];
-        if constexpr (FORM == FE_FORM_LAPLACE) {
-#pragma unroll
-            for (int d = 0; d < 3; d++) Sg[0][d] = H[0][d];
-            energy = w * (H[0][0] * H[0][0] + H[0][1] * H[0][1] + H[0][2] * H[0][2]);
+    // gather the lane's pencil of nodes a = a0 + N1 * pp (contiguous local
+    // numbers): coordinates FP64, u in T
+    double X[N1][3];
+    T U[N1][NC];
+    {
+        int32_t nd[N1];
+        const int32_t *cp = A.conn + (live ? e : 0) * NP + N1 * pp;
+        if constexpr (N1 == 4) {
+            const int4 v = *reinterpret_cast<const int4 *>(cp);
+            nd[0] = v.x;
+            nd[1] = v.y;
+            nd[2] = v.z;
+            nd[3] = v.w;
+        } else if constexpr (N1 == 2) {
+            const int2 v = *reinterpret_cast<const int2 *>(cp);
+            nd[0] = v.x;
+            nd[1] = v.y;
         } else {
-            const T *mat = static_cast<const T *>(A.mat);
-            T lam = T(0), mu = T(0);
-            if (live) {
-                if (A.mat_kind == FE_MAT_ISO_QP) {
-                    lam = mat[2 * (e * NP + l)];
-                    mu = mat[2 * (e * NP + l) + 1];
-                } else {
-                    lam = mat[2 * e];
-                    mu = mat[2 * e + 1];
-                }
+#pragma unroll
+            for (int a = 0; a < N1; a++) nd[a] = cp[a];
+        }
+        const T *Ug = static_cast<const T *>(A.dofs);
+#pragma unroll
+        for (int a = 0; a < N1; a++) {
+            int64_t n = nd[a];
+            if (n < 0 || n >= A.n_nodes) {
+                if (live) fault |= FAULT_INDEX;
+                n = 0;
             }
-            const T tr = H[0][0] + H[1][1] + H[2][2];
-            T ee = T(0);
 #pragma unroll
-            for (int c = 0; c < 3; c++)
+            for (int i = 0; i < 3; i++) X[a][i] = A.coords[3 * n + i];
 #pragma unroll
-                for (int d = 0; d < 3; d++) {
-                    Sg[c][d] = mu * (H[c][d] + H[d][c]) + (c == d ? lam * tr : T(0));
-                    ee += H[c][d] * Sg[c][d];
-                }
-            energy = w * ee;
+            for (int c = 0; c < NC; c++) U[a][c] = Ug[n * NC + c];
+        }
+    }
+
+    // ---- geometry (FP64), one coordinate component at a time
+    double J[N1][3][3];
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        double f[N1], g[N1][3], v[N1];
+#pragma unroll
+        for (int a = 0; a < N1; a++) f[a] = X[a][i];
+        forward3<N1, ZS, AS, true>(f, Ld, tc, p0, p1, slot, g, v);
+#pragma unroll
+        for (int q = 0; q < N1; q++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) J[q][i][j] = g[q][j];
+    }
+    // det J, J^-1 and w det J at the lane's points (p0, p1, q2)
+    T Ji[N1][3][3], wd[N1];
+#pragma unroll
+    for (int q = 0; q < N1; q++) {
+        double Jid[3][3];
+        const double det = inverse3(J[q], Jid);
+        if (live && !(det > 0.0)) fault |= FAULT_DET;
+        const int qi = pp + NPL * q;
+        wd[q] = static_cast<T>(A.tab.w[qi] * det);
+#pragma unroll
+        for (int j = 0; j < 3; j++)
+#pragma unroll
+            for (int d = 0; d < 3; d++) Ji[q][j][d] = static_cast<T>(Jid[j][d]);
+    }
+
+    // ---- u at the points: reference gradients (GRAD) or values
+    T gx[N1][NC][3], val[N1][NC];
+#pragma unroll
+    for (int c = 0; c < NC; c++) {
+        T f[N1], g[N1][3], v[N1];
+#pragma unroll
+        for (int a = 0; a < N1; a++) f[a] = U[a][c];
+        forward3<N1, ZS, AS, GRAD>(f, Lt, tt, p0, p1, slot, g, v);
+#pragma unroll
+        for (int q = 0; q < N1; q++) {
+            if constexpr (GRAD) {
+#pragma unroll
+                for (int j = 0; j < 3; j++) gx[q][c][j] = g[q][j];
+            } else {
+                val[q][c] = v[q];
+            }
+        }
+    }
+
+    // ---- flux at the points (reference space, weight folded in) and energy
+    T F[N1][NC][3];
+    T energy = T(0);
+    const T *mat = static_cast<const T *>(A.mat);
+    T lam = T(0), mu = T(0);
+    if constexpr (FORM == FE_FORM_ELASTICITY)
+        if (live && A.mat_kind != FE_MAT_ISO_QP) {
+            lam = mat[2 * e];
+            mu = mat[2 * e + 1];
         }
 #pragma unroll
-        for (int c = 0; c < NC; c++)
+    for (int q = 0; q < N1; q++) {
+        if constexpr (GRAD) {
+            T H[NC][3];  // physical gradient of u
 #pragma unroll
-            for (int j = 0; j < 3; j++) F[c][j] = w * (Ji[j][0] * Sg[c][0] + Ji[j][1] * Sg[c][1] + Ji[j][2] * Sg[c][2]);
-    } else {
+            for (int c = 0; c < NC; c++)
 #pragma unroll
-        for (int c = 0; c < NC; c++) {
-            F[c][0] = w * val[c];
-            energy += w * val[c] * val[c];
+                for (int d = 0; d < 3; d++)
+                    H[c][d] = gx[q][c][0] * Ji[q][0][d] + gx[q][c][1] * Ji[q][1][d] + gx[q][c][2] * Ji[q][2][d];
+            T Sg[NC][3];
+            if constexpr (FORM == FE_FORM_LAPLACE) {
+#pragma unroll
+                for (int d = 0; d < 3; d++) Sg[0][d] = H[0][d];
+                energy += wd[q] * (H[0][0] * H[0][0] + H[0][1] * H[0][1] + H[0][2] * H[0][2]);
+            } else {
+                if (live && A.mat_kind == FE_MAT_ISO_QP) {
+                    const int64_t k = e * NP + pp + NPL * q;
+                    lam = mat[2 * k];
+                    mu = mat[2 * k + 1];
+                }
+                const T tr = H[0][0] + H[1][1] + H[2][2];
+                T ee = T(0);
+#pragma unroll
+                for (int c = 0; c < 3; c++)
+#pragma unroll
+                    for (int d = 0; d < 3; d++) {
+                        Sg[c][d] = mu * (H[c][d] + H[d][c]) + (c == d ? lam * tr : T(0));
+                        ee += H[c][d] * Sg[c][d];
+                    }
+                energy += wd[q] * ee;
+            }
+#pragma unroll
+            for (int c = 0; c < NC; c++)
+#pragma unroll
+                for (int j = 0; j < 3; j++)
+                    F[q][c][j] = wd[q] * (Ji[q][j][0] * Sg[c][0] + Ji[q][j][1] * Sg[c][1] + Ji[q][j][2] * Sg[c][2]);
+        } else {
+#pragma unroll
+            for (int c = 0; c < NC; c++) {
+                F[q][c][0] = wd[q] * val[q][c];
+                energy += wd[q] * val[q][c] * val[q][c];
+            }
         }
     }
 
     T *out = static_cast<T *>(A.out);
     if (A.eval) {
-        if (live) en[l] = energy;
-        __syncthreads();
-        if (live && l == 0) {
+        // cell sum of the lanes' point sums
+        if (slot) Lt[pp] = energy;
+        wave_sync();
+        if (live && pp == 0) {
             T s = T(0);
-            for (int k = 0; k < NP; k++) s += en[k];
+            for (int k = 0; k < NPL; k++) s += Lt[k];
             out[e] = s;
         }
+        if (fault) raise_fault(A.flags, fault);
         return;
     }
 
-    // ---- transposed contraction with the test functions
-    T *Fs = reinterpret_cast<T *>(mine);  // [NC][3][NP]
-    T *rC = Fs + 3 * NC * NP;             // [3][NC][NP]
-    T *rB = rC + 3 * NC * NP;             // [2][NC][NP]
-    if (live)
+    // ---- transposed contraction with the test functions, per component
+    T res[NC][N1];
 #pragma unroll
-        for (int c = 0; c < NC; c++)
+    for (int c = 0; c < NC; c++) {
+        // axis 2: lane = pencil (p0, p1, *) of points -> basis index a2
+        if (slot)
 #pragma unroll
-            for (int j = 0; j < (S::GRAD ? 3 : 1); j++) Fs[(c * 3 + j) * NP + l] = F[c][j];
-    __syncthreads();
-    T res[NC];
-    if constexpr (S::GRAD) {
-        if (live) {
+            for (int a = 0; a < N1; a++) {
+                T s0 = T(0), s1 = T(0), s2 = T(0);
 #pragma unroll
-            for (int c = 0; c < NC; c++) {
-                rC[(0 * NC + c) * NP + l] = c1d<N1, 2, true>(Fs + (c * 3 + 0) * NP, Bt, l, i2);
-                rC[(1 * NC + c) * NP + l] = c1d<N1, 2, true>(Fs + (c * 3 + 1) * NP, Bt, l, i2);
-                rC[(2 * NC + c) * NP + l] = c1d<N1, 2, true>(Fs + (c * 3 + 2) * NP, Dt, l, i2);
+                for (int q = 0; q < N1; q++) {
+                    s0 += tt.b(q * N1 + a) * F[q][c][0];
+                    if constexpr (GRAD) {
+                        s1 += tt.b(q * N1 + a) * F[q][c][1];
+                        s2 += tt.d(q * N1 + a) * F[q][c][2];
+                    }
+                }
+                Lt[idx<N1, ZS>(p0, p1, a)] = s0;
+                if constexpr (GRAD) {
+                    Lt[AS + idx<N1, ZS>(p0, p1, a)] = s1;
+                    Lt[2 * AS + idx<N1, ZS>(p0, p1, a)] = s2;
+                }
+            }
+        wave_sync();
+        // axis 1: lane = pencil (p0, *, p1) -> a1
+        {
+            T r0[N1], r1[N1], r2[N1];
+#pragma unroll
+            for (int k = 0; k < N1; k++) {
+                r0[k] = Lt[idx<N1, ZS>(p0, k, p1)];
+                if constexpr (GRAD) {
+                    r1[k] = Lt[AS + idx<N1, ZS>(p0, k, p1)];
+                    r2[k] = Lt[2 * AS + idx<N1, ZS>(p0, k, p1)];
+                }
+            }
+            if (slot)
+#pragma unroll
+                for (int a = 0; a < N1; a++) {
+                    T s0 = T(0), s1 = T(0);
+#pragma unroll
+                    for (int k = 0; k < N1; k++) {
+                        s0 += tt.b(k * N1 + a) * r0[k];
+                        if constexpr (GRAD)
+                            s1 += tt.d(k * N1 + a) * r1[k] + tt.b(k * N1 + a) * r2[k];
+                    }
+                    Lt[idx<N1, ZS>(p0, a, p1)] = s0;
+                    if constexpr (GRAD) Lt[AS + idx<N1, ZS>(p0, a, p1)] = s1;
+                }
+        }
+        wave_sync();
+        // axis 0: lane = pencil (*, p0, p1) -> a0
+        {
+            T s0v[N1], s1v[N1];
+#pragma unroll
+            for (int k = 0; k < N1; k++) {
+                s0v[k] = Lt[idx<N1, ZS>(k, p0, p1)];
+                if constexpr (GRAD) s1v[k] = Lt[AS + idx<N1, ZS>(k, p0, p1)];
+            }
+#pragma unroll
+            for (int a = 0; a < N1; a++) {
+                T s = T(0);
+#pragma unroll
+                for (int k = 0; k < N1; k++) {
+                    if constexpr (GRAD)
+                        s += tt.d(k * N1 + a) * s0v[k] + tt.b(k * N1 + a) * s1v[k];
+                    else
+                        s += tt.b(k * N1 + a) * s0v[k];
+                }
+                res[c][a] = s;
             }
         }
-        __syncthreads();
-        if (live) {
-#pragma unroll
-            for (int c = 0; c < NC; c++) {
-                rB[(0 * NC + c) * NP + l] = c1d<N1, 1, true>(rC + (0 * NC + c) * NP, Bt, l, i1);
-                rB[(1 * NC + c) * NP + l] = c1d<N1, 1, true>(rC + (1 * NC + c) * NP, Dt, l, i1) +
-                                            c1d<N1, 1, true>(rC + (2 * NC + c) * NP, Bt, l, i1);
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int c = 0; c < NC; c++)
-            res[c] = live ? c1d<N1, 0, true>(rB + (0 * NC + c) * NP, Dt, l, i0) +
-                                c1d<N1, 0, true>(rB + (1 * NC + c) * NP, Bt, l, i0)
-                          : T(0);
-    } else {
-        if (live)
-#pragma unroll
-            for (int c = 0; c < NC; c++) rC[c * NP + l] = c1d<N1, 2, true>(Fs + (c * 3) * NP, Bt, l, i2);
-        __syncthreads();
-        if (live)
-#pragma unroll
-            for (int c = 0; c < NC; c++) rB[c * NP + l] = c1d<N1, 1, true>(rC + c * NP, Bt, l, i1);
-        __syncthreads();
-#pragma unroll
-        for (int c = 0; c < NC; c++) res[c] = live ? c1d<N1, 0, true>(rB + c * NP, Bt, l, i0) : T(0);
+        wave_sync();  // the arrays are rewritten for the next component
     }
+    if (fault) raise_fault(A.flags, fault);
     if (live) {
         if (cell_minor) {
 #pragma unroll
-            for (int c = 0; c < NC; c++) out[(c * NP + l) * A.n_cells + e] = res[c];
+            for (int c = 0; c < NC; c++)
+#pragma unroll
+                for (int a = 0; a < N1; a++) out[(int64_t)(c * NP + N1 * pp + a) * A.n_cells + e] = res[c][a];
         } else {
 #pragma unroll
-            for (int c = 0; c < NC; c++) out[(e * NC + c) * NP + l] = res[c];
+            for (int c = 0; c < NC; c++)
+#pragma unroll
+                for (int a = 0; a < N1; a++) out[(e * NC + c) * NP + N1 * pp + a] = res[c][a];
         }
     }
 }
@@ -310,15 +446,12 @@ int launch_sf(const Plan &p, const ExecArgs &A, hipStream_t st)
 {
     using S = SF<P, FORM, T>;
     if (A.n_cells <= 0) return FE_OK;
-    const int64_t blocks = (A.n_cells + S::C - 1) / S::C;
+    const int64_t blocks = (A.n_cells + S::CB - 1) / S::CB;
     if (blocks > 0x7fffffff) {
         set_error("too many cells for one launch");
         return FE_ERR_INVALID_ARG;
     }
-    if (S::BYTES > 64 * 1024)
-        FE_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_sf<P, FORM, T>),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, S::BYTES));
-    hipLaunchKernelGGL((k_sf<P, FORM, T>), dim3((unsigned)blocks), dim3(256), S::BYTES, st, A,
+    hipLaunchKernelGGL((k_sf<P, FORM, T>), dim3((unsigned)blocks), dim3(256), 0, st, A,
                        p.opts.layout == FE_LAYOUT_CELL_MINOR ? 1 : 0);
     FE_HIP_CHECK(hipGetLastError());
     return FE_OK;
