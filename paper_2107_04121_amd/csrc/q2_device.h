@@ -359,17 +359,33 @@ __device__ __forceinline__ void q2_run(const Q2Job &A, int64_t e, int64_t e_end,
         if (tid < NQ * 9) {
             const int q = tid % NQ, r9 = tid / NQ, ci = r9 / 3, a2 = r9 - 3 * (r9 / 3);
             const int q0 = q % 3, q1 = (q / 3) % 3, q2 = q / 9;
-            double J[3][3], Ji[3][3];
+            double J[3][3];
 #pragma unroll
             for (int r = 0; r < 3; r++)
 #pragma unroll
                 for (int c = 0; c < 3; c++) J[r][c] = Jq[q * 9 + r * 3 + c];
-            const double det = inverse3(J, Ji);
+            // column ci of J^-1 = adj J / det J: only that column of the
+            // adjugate, and 1/det by the hardware reciprocal refined with two
+            // Newton steps (r <- r + r (1 - det r)), accurate to ~1 ulp
+            double adj0[3], adjc[3];
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+                adj0[j] = J[1][(j + 1) % 3] * J[2][(j + 2) % 3] - J[1][(j + 2) % 3] * J[2][(j + 1) % 3];
+                const double k1 = sel3(ci, J[1][(j + 1) % 3], J[2][(j + 1) % 3], J[0][(j + 1) % 3]);
+                const double k2 = sel3(ci, J[2][(j + 2) % 3], J[0][(j + 2) % 3], J[1][(j + 2) % 3]);
+                const double k3 = sel3(ci, J[1][(j + 2) % 3], J[2][(j + 2) % 3], J[0][(j + 2) % 3]);
+                const double k4 = sel3(ci, J[2][(j + 1) % 3], J[0][(j + 1) % 3], J[1][(j + 1) % 3]);
+                adjc[j] = k1 * k2 - k3 * k4;
+            }
+            const double det = J[0][0] * adj0[0] + J[0][1] * adj0[1] + J[0][2] * adj0[2];
+            double rd = __builtin_amdgcn_rcp(det);
+            rd = fma(rd, fma(-det, rd, 1.0), rd);
+            rd = fma(rd, fma(-det, rd, 1.0), rd);
             if (r9 == 0) {
                 if (!(det > 0.0)) raise_fault(A.flags, FAULT_DET);
                 wd[q] = wq[q] * det;
             }
-            const double c0 = Ji[0][ci], c1 = Ji[1][ci], c2 = Ji[2][ci];
+            const double c0 = adjc[0] * rd, c1 = adjc[1] * rd, c2 = adjc[2] * rd;
             const double bz = B1[q2 * 3 + a2], dz = D1[q2 * 3 + a2];
             T *dst = Gs + ci * 33 * L::KS + q;
 #pragma unroll
