@@ -1,0 +1,161 @@
+"""GPU parity at the benchmark sizes, in the launch configurations the
+benchmark times: outputs on sampled cells (first, last, cells at the XCD
+range boundaries of the persistent kernels, and seeded random ones) against
+the FP64 oracle computed cell by cell, plus properties that hold for every
+cell of the full output (symmetry, zero Laplace row sums, rigid translations
+in the elasticity kernel).
+
+Gates as in the other parity tests: FP64 1e-12, FP32 1e-5, BF16X3 1e-4 of
+each cell's max-norm.
+"""
+import numpy as np
+import pytest
+
+import meshgen
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5, "bf16x3": 1e-4}
+
+
+def _t(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    return t if dtype is None else t.to(dtype)
+
+
+def _sample(n_cells, k=40, seed=7):
+    rng = np.random.default_rng(seed)
+    idx = set(rng.choice(n_cells, size=min(k, n_cells), replace=False).tolist())
+    # first / last cells and the boundaries of eight contiguous ranges
+    for x in range(9):
+        c = min(n_cells - 1, (x * ((n_cells + 7) // 8)))
+        idx.update({c, max(0, c - 1)})
+    idx.update({0, n_cells - 1})
+    return np.array(sorted(idx))
+
+
+def _sub(mesh, idx):
+    return meshgen.Mesh(coords=mesh.coords, conn=mesh.conn[idx], cell=mesh.cell, order=mesh.order, h=mesh.h)
+
+
+def _err(got, ref):
+    n = ref.shape[0]
+    g = np.asarray(got, dtype=np.float64).reshape(n, -1)
+    r = ref.reshape(n, -1)
+    return float((np.abs(g - r).max(1) / np.abs(r).max(1)).max())
+
+
+def test_q1_laplace_16cube_full(orc):
+    """Q1 Laplace matrices and residuals on all 4,096 cells (16^3, +-0.2h)."""
+    import paper_2107_04121_amd as fe
+    mesh = meshgen.hex_mesh(16, 1, alpha=0.2, seed=0)
+    U = meshgen.dofs(mesh.n_nodes, 1, seed=0)
+    pm = fe.Plan("hex", 1, "laplace", "matrix", "fp64")
+    pr = fe.Plan("hex", 1, "laplace", "residual", "fp64")
+    print(f"[fullsize] q1 16^3 {pm.variant}/{pr.variant}", flush=True)
+    K = pm(_t(mesh.coords), _t(mesh.conn))
+    r = pr(_t(mesh.coords), _t(mesh.conn), dofs=_t(U))
+    pm.check()
+    pr.check()
+    assert _err(K.cpu().numpy(), orc.matrix(mesh, "laplace")) < TOL["fp64"]
+    assert _err(r.cpu().numpy(), orc.residual(mesh, "laplace", U)) < TOL["fp64"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_q2_elasticity_48cube(orc, prec):
+    """Q2 elasticity matrices on 48^3 = 110,592 cells: sampled cells against
+    the oracle; every cell symmetric and free of rigid translations."""
+    import torch
+    import paper_2107_04121_amd as fe
+    mesh = meshgen.hex_mesh(48, 2, alpha=0.15, seed=0)
+    lm = meshgen.lame_cell(mesh.n_cells, seed=0)
+    plan = fe.Plan("hex", 2, "elasticity", "matrix", prec, material="iso_cell")
+    print(f"[fullsize] q2 48^3 {prec} {plan.variant}", flush=True)
+    K = plan(_t(mesh.coords), _t(mesh.conn), material=_t(lm, plan.dtype))
+    plan.check()
+    idx = _sample(mesh.n_cells)
+    ref = orc.matrix(_sub(mesh, idx), "elasticity", lm[idx], "iso_cell")
+    err = _err(K[_t(idx)].cpu().numpy(), ref)
+    print(f"[fullsize] q2 48^3 {prec} sampled err {err:.2e}", flush=True)
+    assert err < TOL[prec]
+    # whole output: K = K^T and K t = 0 for the three translations t
+    scale = K.abs().amax(dim=(1, 2))
+    asym = (K - K.transpose(1, 2)).abs().amax(dim=(1, 2)) / scale
+    assert float(asym.max()) < 4 * TOL[prec]
+    for c in range(3):
+        t = torch.zeros(81, dtype=K.dtype, device=K.device)
+        t[c * 27:(c + 1) * 27] = 1
+        row = (K @ t).abs().amax(dim=1) / scale
+        assert float(row.max()) < 50 * TOL[prec], (c, float(row.max()))
+
+
+def test_q1_laplace_128cube_rowsums():
+    """Q1 Laplace matrices on 128^3 cells: every row sums to zero and every
+    matrix is symmetric (FP64)."""
+    import paper_2107_04121_amd as fe
+    mesh = meshgen.hex_mesh(128, 1, alpha=0.2, seed=0)
+    plan = fe.Plan("hex", 1, "laplace", "matrix", "fp64")
+    K = plan(_t(mesh.coords), _t(mesh.conn))
+    plan.check()
+    scale = K.abs().amax(dim=(1, 2))
+    assert float((K.sum(dim=2).abs().amax(dim=1) / scale).max()) < 1e-13
+    assert float(((K - K.transpose(1, 2)).abs().amax(dim=(1, 2)) / scale).max()) == 0.0
+
+
+@pytest.mark.parametrize("form", ["laplace", "elasticity"])
+def test_q3_residual_96cube(orc, form):
+    """Q3 residuals on 96^3 = 884,736 cells, FP32 with FP64 geometry, both
+    output layouts: sampled cells against the oracle."""
+    import paper_2107_04121_amd as fe
+    mesh = meshgen.hex_mesh(96, 3, alpha=0.15, seed=0)
+    nc = 3 if form == "elasticity" else 1
+    U = meshgen.dofs(mesh.n_nodes, nc, seed=0)
+    lm = meshgen.lame_cell(mesh.n_cells, seed=0) if nc == 3 else None
+    kind = "iso_cell" if nc == 3 else None
+    idx = _sample(mesh.n_cells, 24)
+    ref = orc.residual(_sub(mesh, idx), form, U, None if lm is None else lm[idx], kind)
+    X, C = _t(mesh.coords), _t(mesh.conn)
+    for layout in ("cell_major", "cell_minor"):
+        plan = fe.Plan("hex", 3, form, "residual", "fp32", material=kind, layout=layout)
+        print(f"[fullsize] q3 96^3 {form} {layout} {plan.variant}", flush=True)
+        out = plan(X, C, material=None if lm is None else _t(lm, plan.dtype), dofs=_t(U, plan.dtype))
+        plan.check()
+        it = _t(idx)
+        got = out[it] if layout == "cell_major" else out.movedim(-1, 0)[it]
+        err = _err(got.cpu().numpy(), ref)
+        print(f"[fullsize] q3 96^3 {form} {layout} sampled err {err:.2e}", flush=True)
+        assert err < TOL["fp32"]
+        del out
+
+
+def test_batch_uneven_full_groups(orc):
+    """The batched uneven mesh at its full sizes (300k P1, 120k P2 tets, 200k
+    Q1, 40k Q2 hex, three forms each, FP32, tuned tiles): sampled cells of
+    every group and form against the oracle."""
+    import paper_2107_04121_amd as fe
+    specs = [("tet", 1, (50, 40, 25)), ("tet", 2, (40, 25, 20)), ("hex", 1, (100, 50, 40)),
+             ("hex", 2, (40, 40, 25))]
+    ss = np.random.SeedSequence(0).spawn(4)
+    meshes, groups = [], []
+    for (cell, p, dims), s in zip(specs, ss):
+        seed = int(s.generate_state(1)[0])
+        m = (meshgen.tet_mesh(dims, p, alpha=0.15, seed=seed) if cell == "tet"
+             else meshgen.hex_mesh(dims, p, alpha=0.15, seed=seed))
+        lm = meshgen.lame_cell(m.n_cells, seed=seed)
+        meshes.append((m, lm))
+        groups.append(dict(cell=cell, order=p, coords=_t(m.coords), conn=_t(m.conn),
+                           material=_t(lm).float(), forms=("mass", "laplace", "elasticity")))
+    b = fe.Batch(groups, precision="fp32", autotune=True)
+    print(f"[fullsize] batch tiles {b.tiles}", flush=True)
+    b.run()
+    b.check()
+    for (m, lm), o in zip(meshes, b.outputs):
+        idx = _sample(m.n_cells, 16)
+        sub = _sub(m, idx)
+        it = _t(idx)
+        for form, ref in (("mass", orc.matrix(sub, "mass")), ("laplace", orc.matrix(sub, "laplace")),
+                          ("elasticity", orc.matrix(sub, "elasticity", lm[idx], "iso_cell"))):
+            err = _err(o[form][it].cpu().numpy(), ref)
+            print(f"[fullsize] batch {m.cell}{m.order} {form} err {err:.2e}", flush=True)
+            assert err < TOL["fp32"], (m.cell, m.order, form, err)
