@@ -88,6 +88,10 @@ LaunchFn select_mfma(const Plan &p);
 LaunchFn select_sumfact(const Plan &p);
 LaunchFn select_cellwise(const Plan &p);
 
+// Gradient of the elasticity eval value on hexahedra by sum factorization
+// (FE_ERR_UNSUPPORTED when the plan is not covered).
+int adjoint_sumfact(const Plan &p, const ExecArgs &A, double scale, void *gmat, void *part, hipStream_t st);
+
 int n_comp_of(int form);
 size_t matrix_first_bytes(const Plan &p, int64_t n_cells);
 int launch_matrix_first(const Plan &p, const ExecArgs &A, hipStream_t st);

@@ -308,11 +308,14 @@ size_t grad_part_bytes(const Plan &p, int64_t n_cells)
 int energy_grad_impl(const Plan &p, const fe_incidence_s *inc, const ExecArgs &A, double scale, void *gmat,
                      double *gcoords, void *part, hipStream_t st)
 {
-    int rc;
-    if (p.prec == FE_PREC_FP64)
-        rc = dispatch_grad<double>(p.cell, p.order, A, scale, gmat, gcoords ? part : nullptr, st);
-    else
-        rc = dispatch_grad<float>(p.cell, p.order, A, scale, gmat, gcoords ? part : nullptr, st);
+    // hexahedra: the sum-factorized kernel; tetrahedra: the per-point kernel
+    int rc = adjoint_sumfact(p, A, scale, gmat, gcoords ? part : nullptr, st);
+    if (rc == FE_ERR_UNSUPPORTED) {
+        if (p.prec == FE_PREC_FP64)
+            rc = dispatch_grad<double>(p.cell, p.order, A, scale, gmat, gcoords ? part : nullptr, st);
+        else
+            rc = dispatch_grad<float>(p.cell, p.order, A, scale, gmat, gcoords ? part : nullptr, st);
+    }
     if (rc || !gcoords) return rc;
     return gather_launch(inc, 3, p.prec == FE_PREC_FP64, true, part, scale, gcoords, st);
 }

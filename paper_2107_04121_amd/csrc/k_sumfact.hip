@@ -26,6 +26,14 @@
 //
 // Output layouts: cell-major [n_cells][n_comp][n_b] (default) or cell-minor
 // [n_comp][n_b][n_cells].
+//
+// ADJ (elasticity only): the gradient of the eval value J = sum u^T K u.
+// The same geometry and gradient passes, then at every point
+//   dJ/dlambda = w det (tr eps)^2,  dJ/dmu = 2 w det eps:eps,
+//   M = w det (W I - 2 H^T sigma),  W = eps:sigma,  H = grad u,
+// and the transposed passes applied to the reference-space flux M J^-T give
+// the per-(cell, node) partials of dJ/dx (the energy-momentum form), in the
+// cell-major residual layout.
 #include "cw_device.h"
 
 namespace fe {
@@ -174,8 +182,8 @@ __device__ __forceinline__ void forward3(const V (&f)[N1], V *L, const TB &tb, i
     }
 }
 
-template <int P, int FORM, typename T>
-__global__ __launch_bounds__(256) void k_sf(ExecArgs A, int cell_minor)
+template <int P, int FORM, typename T, bool ADJ>
+__global__ __launch_bounds__(256) void k_sf(ExecArgs A, int cell_minor, T *gmat, double scale)
 {
     using S = SF<P, FORM, T>;
     constexpr int N1 = S::N1, NPL = S::NPL, NP = S::NP, CW = S::CW, NC = S::NC, ZS = S::ZS, AS = S::AS;
@@ -286,6 +294,7 @@ __global__ __launch_bounds__(256) void k_sf(ExecArgs A, int cell_minor)
     // ---- flux at the points (reference space, weight folded in) and energy
     T F[N1][NC][3];
     T energy = T(0);
+    T gsum[2] = {T(0), T(0)};  // ADJ with per-cell coefficients: this lane's dJ/dc
     const T *mat = static_cast<const T *>(A.mat);
     T lam = T(0), mu = T(0);
     if constexpr (FORM == FE_FORM_ELASTICITY)
@@ -307,6 +316,53 @@ __global__ __launch_bounds__(256) void k_sf(ExecArgs A, int cell_minor)
 #pragma unroll
                 for (int d = 0; d < 3; d++) Sg[0][d] = H[0][d];
                 energy += wd[q] * (H[0][0] * H[0][0] + H[0][1] * H[0][1] + H[0][2] * H[0][2]);
+            } else if constexpr (ADJ) {
+                if (live && A.mat_kind == FE_MAT_ISO_QP) {
+                    const int64_t k = e * NP + pp + NPL * q;
+                    lam = mat[2 * k];
+                    mu = mat[2 * k + 1];
+                }
+                const T tr = H[0][0] + H[1][1] + H[2][2];
+                T eps[3][3], sig[3][3], ee = T(0), W = T(0);
+#pragma unroll
+                for (int r = 0; r < 3; r++)
+#pragma unroll
+                    for (int d = 0; d < 3; d++) {
+                        eps[r][d] = T(0.5) * (H[r][d] + H[d][r]);
+                        ee += eps[r][d] * eps[r][d];
+                    }
+#pragma unroll
+                for (int r = 0; r < 3; r++)
+#pragma unroll
+                    for (int d = 0; d < 3; d++) {
+                        sig[r][d] = T(2) * mu * eps[r][d] + (r == d ? lam * tr : T(0));
+                        W += eps[r][d] * sig[r][d];
+                    }
+                const T g0 = wd[q] * tr * tr, g1 = T(2) * wd[q] * ee;
+                if (A.mat_kind == FE_MAT_ISO_QP) {
+                    if (live && gmat) {
+                        const int64_t k = e * NP + pp + NPL * q;
+                        gmat[2 * k] = static_cast<T>(scale * static_cast<double>(g0));
+                        gmat[2 * k + 1] = static_cast<T>(scale * static_cast<double>(g1));
+                    }
+                } else {
+                    gsum[0] += g0;
+                    gsum[1] += g1;
+                }
+                // M[k][l] = w det (W delta_kl - 2 sum_r H[r][k] sig[r][l]); the
+                // reference flux for the transposed passes is M J^-T
+#pragma unroll
+                for (int k = 0; k < 3; k++) {
+                    T Mk[3];
+#pragma unroll
+                    for (int l = 0; l < 3; l++) {
+                        const T s2 = H[0][k] * sig[0][l] + H[1][k] * sig[1][l] + H[2][k] * sig[2][l];
+                        Mk[l] = wd[q] * ((k == l ? W : T(0)) - T(2) * s2);
+                    }
+#pragma unroll
+                    for (int j = 0; j < 3; j++) F[q][k][j] = Mk[0] * Ji[q][j][0] + Mk[1] * Ji[q][j][1] + Mk[2] * Ji[q][j][2];
+                }
+                continue;
             } else {
                 if (live && A.mat_kind == FE_MAT_ISO_QP) {
                     const int64_t k = e * NP + pp + NPL * q;
@@ -339,6 +395,30 @@ __global__ __launch_bounds__(256) void k_sf(ExecArgs A, int cell_minor)
     }
 
     T *out = static_cast<T *>(A.out);
+    if constexpr (ADJ) {
+        if (A.mat_kind != FE_MAT_ISO_QP && gmat) {
+            // per-cell dJ/dc: sum of the cell's lanes
+            if (slot) {
+                Lt[2 * pp] = gsum[0];
+                Lt[2 * pp + 1] = gsum[1];
+            }
+            wave_sync();
+            if (live && pp == 0) {
+                double s0 = 0.0, s1 = 0.0;
+                for (int k = 0; k < NPL; k++) {
+                    s0 += static_cast<double>(Lt[2 * k]);
+                    s1 += static_cast<double>(Lt[2 * k + 1]);
+                }
+                gmat[2 * e] = static_cast<T>(scale * s0);
+                gmat[2 * e + 1] = static_cast<T>(scale * s1);
+            }
+            wave_sync();  // the arrays are rewritten below
+        }
+        if (!out) {
+            if (fault) raise_fault(A.flags, fault);
+            return;
+        }
+    }
     if (A.eval) {
         // cell sum of the lanes' point sums
         if (slot) Lt[pp] = energy;
@@ -451,8 +531,8 @@ int launch_sf(const Plan &p, const ExecArgs &A, hipStream_t st)
         set_error("too many cells for one launch");
         return FE_ERR_INVALID_ARG;
     }
-    hipLaunchKernelGGL((k_sf<P, FORM, T>), dim3((unsigned)blocks), dim3(256), 0, st, A,
-                       p.opts.layout == FE_LAYOUT_CELL_MINOR ? 1 : 0);
+    hipLaunchKernelGGL((k_sf<P, FORM, T, false>), dim3((unsigned)blocks), dim3(256), 0, st, A,
+                       p.opts.layout == FE_LAYOUT_CELL_MINOR ? 1 : 0, static_cast<T *>(nullptr), 1.0);
     FE_HIP_CHECK(hipGetLastError());
     return FE_OK;
 }
@@ -478,7 +558,45 @@ LaunchFn pick_order(int order, int form)
     return nullptr;
 }
 
+template <int P, typename T>
+int launch_sf_adj(const ExecArgs &A, double scale, void *gmat, void *part, hipStream_t st)
+{
+    using S = SF<P, FE_FORM_ELASTICITY, T>;
+    if (A.n_cells <= 0) return FE_OK;
+    const int64_t blocks = (A.n_cells + S::CB - 1) / S::CB;
+    if (blocks > 0x7fffffff) {
+        set_error("too many cells for one launch");
+        return FE_ERR_INVALID_ARG;
+    }
+    ExecArgs B = A;
+    B.out = part;
+    B.eval = 0;
+    hipLaunchKernelGGL((k_sf<P, FE_FORM_ELASTICITY, T, true>), dim3((unsigned)blocks), dim3(256), 0, st, B, 0,
+                       static_cast<T *>(gmat), scale);
+    FE_HIP_CHECK(hipGetLastError());
+    return FE_OK;
+}
+
+template <typename T>
+int adj_order(int order, const ExecArgs &A, double scale, void *gmat, void *part, hipStream_t st)
+{
+    if (order == 1) return launch_sf_adj<1, T>(A, scale, gmat, part, st);
+    if (order == 2) return launch_sf_adj<2, T>(A, scale, gmat, part, st);
+    if (order == 3) return launch_sf_adj<3, T>(A, scale, gmat, part, st);
+    return FE_ERR_UNSUPPORTED;
+}
+
 }  // namespace
+
+int adjoint_sumfact(const Plan &p, const ExecArgs &A, double scale, void *gmat, void *part, hipStream_t st)
+{
+    if (p.cell != FE_CELL_HEX || p.form != FE_FORM_ELASTICITY ||
+        (p.mat_kind != FE_MAT_ISO_CELL && p.mat_kind != FE_MAT_ISO_QP))
+        return FE_ERR_UNSUPPORTED;
+    if (p.prec == FE_PREC_FP64) return adj_order<double>(p.order, A, scale, gmat, part, st);
+    if (p.prec == FE_PREC_FP32) return adj_order<float>(p.order, A, scale, gmat, part, st);
+    return FE_ERR_UNSUPPORTED;
+}
 
 LaunchFn select_sumfact(const Plan &p)
 {
