@@ -1,0 +1,620 @@
+// Matrix-core (MFMA) element-matrix kernel for Q2 and Q3 hexahedra: scalar
+// and vector mass, Laplace, and linear elasticity with per-cell isotropic
+// coefficients, in FP64, FP32 or BF16X3, with FP64 geometry.
+//
+// Every form of the table of example weak forms in matrix mode is read off
+// products of ONE operand per cell, built from the geometry:
+//   Laplace / elasticity  g[q][(c,a)] = sqrt(w_q det J_q) G_c[q][a]  (c = 0..2)
+//   mass                  g[q][a]     = sqrt(w_q det J_q) phi_a(q)
+// (w_q > 0 and det J > 0, so the square root is real; a cell with det J <= 0
+// raises the fault flag).  With P[(r,a),(s,b)] = sum_q g[q][(r,a)] g[q][(s,b)]:
+//   mass        M = P                      vector mass = I_3 (x) M
+//   Laplace     K = P_00 + P_11 + P_22
+//   elasticity  K_rs = lambda P_rs + mu P_rs^T + delta_rs mu (P_00 + P_11 + P_22)
+// which is w det B^T D B of the linear-elasticity expression for isotropic D
+// (the same recombination the Q2 elasticity kernel uses).  Both MFMA
+// operands come from the same array, so a diagonal tile is exactly symmetric.
+//
+// The output is cut into 16x16 tiles.  Per cell only tiles on or above the
+// diagonal are multiplied, grouped into jobs whose outputs (including the
+// mirrored tiles below the diagonal) need no other job's products:
+//   DIAG(i,j)        elasticity, diagonal blocks: P_tt(i,j) for t = 0,1,2 ->
+//                    K_tt(i,j) = (lambda + mu) P_tt(i,j) + mu sum_t' P_t't'(i,j)
+//   PAIR(r,s,i<j)    elasticity, r < s: P_rs(i,j), P_rs(j,i) -> K_rs(i,j),
+//                    K_rs(j,i) and their mirrors in K_sr
+//   SINGLE(r,s,i)    elasticity, r < s: P_rs(i,i) -> K_rs(i,i), K_sr(i,i)
+//   LAP(i,j)         Laplace: sum_t P_tt(i,j)
+//   MASS(i,j)        mass: P(i,j) (vector mass: the three diagonal blocks,
+//                    zeros in the six others)
+// Jobs are spread over the waves of the workgroup by a static longest-first
+// schedule.  A wave runs its jobs back to back with no workgroup barrier;
+// mirrored tiles are transposed through a small per-wave LDS buffer, and
+// every tile is stored straight from the accumulator layout (each store
+// instruction writes four 16-entry row segments of the row-major output).
+//
+// One workgroup per cell at a time, persistent over an XCD-contiguous range
+// of cells.  Per cell:
+//   1. J entries at every quadrature point by sum factorization over the
+//      tensor-product 1-D tables (FP64);
+//   2. det J, J^-1 and sqrt(w det J) per point (FP64);
+//   3. the operand g in LDS in the contraction type (two bf16 arrays, high
+//      and low parts, for BF16X3), row (c,a) padded to a multiple of 16,
+//      columns = quadrature points, row stride chosen so the 16 rows x 4
+//      (or 4 x 8-point) fragment reads hit distinct LDS banks;
+//   4. the jobs on the matrix cores:
+//        FP64: v_mfma_f64_16x16x4f64, FP32: v_mfma_f32_16x16x4f32,
+//        BF16X3: v_mfma_f32_16x16x32_bf16 on hi*hi + hi*lo + lo*hi.
+// The next cell's connectivity is loaded during step 2, its coordinates
+// during step 4, and parked in LDS at the end of step 4.
+#include "q2_device.h"
+
+namespace fe {
+namespace {
+
+using q2::bf8;
+using q2::cell_range;
+using q2::d4;
+using q2::f4;
+using q2::MM_BF16X3;
+using q2::MM_F32;
+using q2::MM_F64;
+using q2::MMT;
+
+constexpr int WAVES = 8;
+constexpr int THREADS = 64 * WAVES;
+
+enum : int { J_DIAG = 0, J_PAIR = 1, J_SINGLE = 2, J_LAP = 3, J_MASS = 4 };
+
+constexpr int align_to(int x, int a) { return (x + a - 1) / a * a; }
+
+// LDS row stride (entries) of the operand for a padded depth KP: conflict-free
+// fragment reads (FP64: stride = 2 mod 4 doubles; FP32: 4 mod 8 floats;
+// bf16: 8 mod 16 halves).
+constexpr int op_stride(int mm, int kp)
+{
+    int ks = kp;
+    if (mm == MM_F64)
+        while (ks % 4 != 2) ks++;
+    else if (mm == MM_F32)
+        while (ks % 8 != 4) ks++;
+    else
+        while (ks % 16 != 8) ks++;
+    return ks;
+}
+
+// Static schedule: jobs in order of decreasing weight (matrix-core tiles),
+// each given to the least loaded wave.
+struct Sched {
+    uint32_t job[WAVES][32];
+    int n[WAVES];
+};
+
+constexpr uint32_t enc(int kind, int r, int s, int i, int j)
+{
+    return static_cast<uint32_t>(kind | (r << 4) | (s << 6) | (i << 8) | (j << 12));
+}
+
+constexpr Sched make_sched(int form, int nt)
+{
+    Sched S{};
+    uint32_t jobs[128] = {};
+    int wt[128] = {};
+    int nj = 0;
+    if (form == FE_FORM_ELASTICITY) {
+        for (int i = 0; i < nt; i++)
+            for (int j = i; j < nt; j++) {
+                jobs[nj] = enc(J_DIAG, 0, 0, i, j);
+                wt[nj++] = 3;
+            }
+        for (int r = 0; r < 3; r++)
+            for (int s = r + 1; s < 3; s++)
+                for (int i = 0; i < nt; i++)
+                    for (int j = i + 1; j < nt; j++) {
+                        jobs[nj] = enc(J_PAIR, r, s, i, j);
+                        wt[nj++] = 2;
+                    }
+        for (int r = 0; r < 3; r++)
+            for (int s = r + 1; s < 3; s++)
+                for (int i = 0; i < nt; i++) {
+                    jobs[nj] = enc(J_SINGLE, r, s, i, i);
+                    wt[nj++] = 1;
+                }
+    } else {
+        const int kind = form == FE_FORM_LAPLACE ? J_LAP : J_MASS;
+        for (int i = 0; i < nt; i++)
+            for (int j = i; j < nt; j++) {
+                jobs[nj] = enc(kind, 0, 0, i, j);
+                wt[nj++] = kind == J_LAP ? 3 : 1;
+            }
+    }
+    int load[WAVES] = {};
+    for (int k = 0; k < nj; k++) {
+        int w = 0;
+        for (int v = 1; v < WAVES; v++)
+            if (load[v] < load[w]) w = v;
+        S.job[w][S.n[w]++] = jobs[k];
+        load[w] += wt[k];
+    }
+    return S;
+}
+
+template <int P, int FORM, int MM>
+struct HexMM {
+    static constexpr int N1 = P + 1, NB = N1 * N1 * N1, NQ = NB;
+    static constexpr bool MASSF = FORM == FE_FORM_MASS || FORM == FE_FORM_VMASS;
+    static constexpr int NC = MASSF ? 1 : 3;  // operand components
+    static constexpr int NCO = form_nc(FORM);  // output components
+    static constexpr int ND = NCO * NB;        // output row length
+    static constexpr int NBP = align_to(NB, 16), NT = NBP / 16;
+    static constexpr bool RAGGED = NB % 16 != 0;
+    using T = typename MMT<MM>::T;      // accumulation and output type
+    using ACC = typename MMT<MM>::acc;  // 16x16 accumulator fragment
+    using OPT = typename std::conditional<MM == MM_BF16X3, __bf16, T>::type;
+    static constexpr int KP = align_to(NQ, MM == MM_BF16X3 ? 32 : 4);
+    static constexpr int KS = op_stride(MM, KP);
+    static constexpr int ROWS = NC * NBP;
+    static constexpr int NOP = MM == MM_BF16X3 ? 2 : 1;  // operand arrays (hi, lo)
+    static constexpr int TS = 16 + (sizeof(T) == 8 ? 2 : 1);  // transpose buffer row stride
+    // LDS layout (bytes)
+    static constexpr int OFF_TB = 0;  // double B1[N1][N1], D1[N1][N1], w[NQ]
+    static constexpr int OFF_X = q2::align16(OFF_TB + (2 * N1 * N1 + NQ) * 8);  // double xs[3][NB], T lm[2]
+    static constexpr int OFF_OP = q2::align16(OFF_X + 3 * NB * 8 + 16);
+    static constexpr int OP_BYTES = q2::align16(ROWS * KS * (int)sizeof(OPT));
+    static constexpr int OFF_SC = OFF_OP + NOP * OP_BYTES;
+    // scratch, used in turn by the geometry (J, then sqrt(wd) J^-1) and by
+    // the per-wave transpose buffers of the job phase
+    static constexpr int SC_GEO = NQ * 10 * 8;
+    static constexpr int SC_TR = WAVES * 16 * TS * (int)sizeof(T);
+    static constexpr int BYTES = q2::align16(OFF_SC + (SC_GEO > SC_TR ? SC_GEO : SC_TR));
+    static constexpr Sched SCHED = make_sched(FORM == FE_FORM_VMASS ? FE_FORM_MASS : FORM, NT);
+};
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// accumulator row of element v for this lane (column = lane % 16)
+template <int MM>
+__device__ __forceinline__ int acc_row(int lane, int v)
+{
+    return MM == MM_F64 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v;
+}
+
+// acc[u] += sum over k in [k0, k1) of g[rowsA[u] + m][k] g[rowsB[u] + n][k]
+// (rows = operand row of the tile's first entry)
+template <class H, int NU>
+__device__ __forceinline__ void mma_run(typename H::ACC *acc, const typename H::OPT *op, const int *ra, const int *rb,
+                                        int k0, int k1, int lane)
+{
+    using OPT = typename H::OPT;
+    constexpr int KS = H::KS;
+    const int m = lane & 15, grp = lane >> 4;
+    if constexpr (H::NOP == 1) {
+#pragma unroll 4
+        for (int k = k0; k < k1; k += 4) {
+            OPT a[NU], b[NU];
+#pragma unroll
+            for (int u = 0; u < NU; u++) {
+                a[u] = op[(ra[u] + m) * KS + k + grp];
+                b[u] = op[(rb[u] + m) * KS + k + grp];
+            }
+#pragma unroll
+            for (int u = 0; u < NU; u++) {
+                if constexpr (sizeof(OPT) == 8)
+                    acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc[u], 0, 0, 0);
+                else
+                    acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], b[u], acc[u], 0, 0, 0);
+            }
+        }
+    } else {
+        const OPT *lo = op + H::OP_BYTES / sizeof(OPT);
+#pragma unroll 2
+        for (int k = k0; k < k1; k += 32) {
+            bf8 ah[NU], al[NU], bh[NU], bl[NU];
+#pragma unroll
+            for (int u = 0; u < NU; u++) {
+                const int oa = (ra[u] + m) * KS + k + 8 * grp, ob = (rb[u] + m) * KS + k + 8 * grp;
+                ah[u] = *reinterpret_cast<const bf8 *>(op + oa);
+                al[u] = *reinterpret_cast<const bf8 *>(lo + oa);
+                bh[u] = *reinterpret_cast<const bf8 *>(op + ob);
+                bl[u] = *reinterpret_cast<const bf8 *>(lo + ob);
+            }
+#pragma unroll
+            for (int u = 0; u < NU; u++) acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[u], bh[u], acc[u], 0, 0, 0);
+#pragma unroll
+            for (int u = 0; u < NU; u++) acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[u], bl[u], acc[u], 0, 0, 0);
+#pragma unroll
+            for (int u = 0; u < NU; u++) acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[u], bh[u], acc[u], 0, 0, 0);
+        }
+    }
+}
+
+// x^T in the accumulator layout, through this wave's LDS buffer
+template <class H>
+__device__ __forceinline__ typename H::ACC transpose(const typename H::ACC &x, typename H::T *buf, int lane)
+{
+    constexpr int MM = sizeof(typename H::T) == 8 ? MM_F64 : MM_F32;
+    const int col = lane & 15;
+    typename H::ACC y;
+#pragma unroll
+    for (int v = 0; v < 4; v++) buf[acc_row<MM>(lane, v) * H::TS + col] = x[v];
+    wave_sync();
+#pragma unroll
+    for (int v = 0; v < 4; v++) y[v] = buf[col * H::TS + acc_row<MM>(lane, v)];
+    wave_sync();
+    return y;
+}
+
+// store tile (output rows row0.., columns col0..) of one cell's matrix;
+// rl / cl = valid rows / columns of the tile (16 unless the block is ragged)
+template <class H>
+__device__ __forceinline__ void store_tile(typename H::T *oc, int row0, int col0, int rl, int cl,
+                                           const typename H::ACC &x, int lane)
+{
+    constexpr int MM = sizeof(typename H::T) == 8 ? MM_F64 : MM_F32;
+    const int col = lane & 15;
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+        const int row = acc_row<MM>(lane, v);
+        if (!H::RAGGED || (row < rl && col < cl))
+            __builtin_nontemporal_store(x[v], oc + static_cast<int64_t>(row0 + row) * H::ND + col0 + col);
+    }
+}
+
+template <class H>
+__device__ __forceinline__ int valid(int t)  // valid entries of tile t of a block
+{
+    return H::NB - 16 * t < 16 ? H::NB - 16 * t : 16;
+}
+
+// One job of the current cell.  oc = the cell's output matrix.
+template <class H, int FORM>
+__device__ __forceinline__ void run_job(uint32_t jb, const typename H::OPT *op, typename H::T *oc,
+                                        typename H::T *buf, typename H::T lam, typename H::T mu, int lane)
+{
+    using T = typename H::T;
+    using ACC = typename H::ACC;
+    constexpr int NB = H::NB, NBP = H::NBP, KP = H::KP;
+    const int kind = jb & 15, r = (jb >> 4) & 3, s = (jb >> 6) & 3, i = (jb >> 8) & 15, j = (jb >> 12) & 15;
+    const int vi = valid<H>(i), vj = valid<H>(j);
+    if (kind == J_DIAG || kind == J_LAP) {
+        ACC c[3] = {};
+        const int ra[3] = {16 * i, NBP + 16 * i, 2 * NBP + 16 * i};
+        const int rb[3] = {16 * j, NBP + 16 * j, 2 * NBP + 16 * j};
+        mma_run<H, 3>(c, op, ra, rb, 0, KP, lane);
+        ACC S;
+#pragma unroll
+        for (int v = 0; v < 4; v++) S[v] = c[0][v] + c[1][v] + c[2][v];
+        if (kind == J_LAP) {
+            store_tile<H>(oc, 16 * i, 16 * j, vi, vj, S, lane);
+            if (i != j) store_tile<H>(oc, 16 * j, 16 * i, vj, vi, transpose<H>(S, buf, lane), lane);
+            return;
+        }
+        const T lm = lam + mu;
+#pragma unroll
+        for (int t = 0; t < 3; t++) {
+            ACC k;
+#pragma unroll
+            for (int v = 0; v < 4; v++) k[v] = lm * c[t][v] + mu * S[v];
+            store_tile<H>(oc, t * NB + 16 * i, t * NB + 16 * j, vi, vj, k, lane);
+        }
+        if (i != j) {
+            const ACC St = transpose<H>(S, buf, lane);
+#pragma unroll
+            for (int t = 0; t < 3; t++) {
+                const ACC ct = transpose<H>(c[t], buf, lane);
+                ACC k;
+#pragma unroll
+                for (int v = 0; v < 4; v++) k[v] = lm * ct[v] + mu * St[v];
+                store_tile<H>(oc, t * NB + 16 * j, t * NB + 16 * i, vj, vi, k, lane);
+            }
+        }
+    } else if (kind == J_PAIR) {
+        ACC c[2] = {};
+        const int ra[2] = {r * NBP + 16 * i, r * NBP + 16 * j};
+        const int rb[2] = {s * NBP + 16 * j, s * NBP + 16 * i};
+        mma_run<H, 2>(c, op, ra, rb, 0, KP, lane);
+        // A = P_rs(i,j) = c[0], B = P_rs(j,i) = c[1]
+        const ACC Bt = transpose<H>(c[1], buf, lane);
+        ACC x;
+#pragma unroll
+        for (int v = 0; v < 4; v++) x[v] = lam * c[0][v] + mu * Bt[v];
+        store_tile<H>(oc, r * NB + 16 * i, s * NB + 16 * j, vi, vj, x, lane);  // K_rs(i,j)
+#pragma unroll
+        for (int v = 0; v < 4; v++) x[v] = lam * Bt[v] + mu * c[0][v];
+        store_tile<H>(oc, s * NB + 16 * i, r * NB + 16 * j, vi, vj, x, lane);  // K_sr(i,j)
+        const ACC At = transpose<H>(c[0], buf, lane);
+#pragma unroll
+        for (int v = 0; v < 4; v++) x[v] = lam * c[1][v] + mu * At[v];
+        store_tile<H>(oc, r * NB + 16 * j, s * NB + 16 * i, vj, vi, x, lane);  // K_rs(j,i)
+#pragma unroll
+        for (int v = 0; v < 4; v++) x[v] = lam * At[v] + mu * c[1][v];
+        store_tile<H>(oc, s * NB + 16 * j, r * NB + 16 * i, vj, vi, x, lane);  // K_sr(j,i)
+    } else if (kind == J_SINGLE) {
+        // two half-depth products in flight, summed
+        ACC c[2] = {};
+        constexpr int KH = align_to(KP / 2, H::NOP == 2 ? 32 : 4);
+        const int ra[1] = {r * NBP + 16 * i}, rb[1] = {s * NBP + 16 * i};
+        mma_run<H, 1>(c, op, ra, rb, 0, KH, lane);
+        if constexpr (KH < KP) mma_run<H, 1>(c + 1, op, ra, rb, KH, KP, lane);
+        ACC a;
+#pragma unroll
+        for (int v = 0; v < 4; v++) a[v] = c[0][v] + c[1][v];
+        const ACC at = transpose<H>(a, buf, lane);
+        ACC x;
+#pragma unroll
+        for (int v = 0; v < 4; v++) x[v] = lam * a[v] + mu * at[v];
+        store_tile<H>(oc, r * NB + 16 * i, s * NB + 16 * i, vi, vi, x, lane);
+#pragma unroll
+        for (int v = 0; v < 4; v++) x[v] = lam * at[v] + mu * a[v];
+        store_tile<H>(oc, s * NB + 16 * i, r * NB + 16 * i, vi, vi, x, lane);
+    } else {  // J_MASS
+        ACC c[2] = {};
+        constexpr int KH = align_to(KP / 2, H::NOP == 2 ? 32 : 4);
+        const int ra[1] = {16 * i}, rb[1] = {16 * j};
+        mma_run<H, 1>(c, op, ra, rb, 0, KH, lane);
+        if constexpr (KH < KP) mma_run<H, 1>(c + 1, op, ra, rb, KH, KP, lane);
+        ACC mt;
+#pragma unroll
+        for (int v = 0; v < 4; v++) mt[v] = c[0][v] + c[1][v];
+        if constexpr (FORM == FE_FORM_MASS) {
+            store_tile<H>(oc, 16 * i, 16 * j, vi, vj, mt, lane);
+            if (i != j) store_tile<H>(oc, 16 * j, 16 * i, vj, vi, transpose<H>(mt, buf, lane), lane);
+        } else {
+            const ACC tt = i != j ? transpose<H>(mt, buf, lane) : mt;
+            const ACC z = {};
+#pragma unroll
+            for (int rr = 0; rr < 3; rr++)
+#pragma unroll
+                for (int ss = 0; ss < 3; ss++) {
+                    store_tile<H>(oc, rr * NB + 16 * i, ss * NB + 16 * j, vi, vj, rr == ss ? mt : z, lane);
+                    if (i != j) store_tile<H>(oc, rr * NB + 16 * j, ss * NB + 16 * i, vj, vi, rr == ss ? tt : z, lane);
+                }
+        }
+    }
+}
+
+template <int P, int FORM, int MM>
+__global__ __launch_bounds__(THREADS, MM == MM_F64 ? 1 : 2) void k_hexmm(ExecArgs A)
+{
+    using H = HexMM<P, FORM, MM>;
+    using T = typename H::T;
+    using OPT = typename H::OPT;
+    constexpr int N1 = H::N1, NB = H::NB, NQ = H::NQ, NC = H::NC, NBP = H::NBP, KS = H::KS;
+    constexpr bool ELAST = FORM == FE_FORM_ELASTICITY;
+    __shared__ __align__(16) unsigned char smem[H::BYTES];
+    double *B1 = reinterpret_cast<double *>(smem + H::OFF_TB);
+    double *D1 = B1 + N1 * N1;
+    double *wq = D1 + N1 * N1;
+    double *xs = reinterpret_cast<double *>(smem + H::OFF_X);  // [3][NB]
+    T *lms = reinterpret_cast<T *>(xs + 3 * NB);
+    OPT *op = reinterpret_cast<OPT *>(smem + H::OFF_OP);
+    double *Jq = reinterpret_cast<double *>(smem + H::OFF_SC);  // [NQ][9]
+    double *Mq = Jq;                                            // [NQ][10]: sqrt(wd) J^-1, sqrt(wd)
+    T *tbuf = reinterpret_cast<T *>(smem + H::OFF_SC);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    T *buf = tbuf + wave * 16 * H::TS;
+
+    int64_t e, e_end, stride;
+    cell_range(A.xcd_remap, A.n_cells, e, e_end, stride);
+    if (e >= e_end) return;  // uniform over the workgroup
+    const T *mat = static_cast<const T *>(A.mat);
+
+    // tables, operand padding (never rewritten), the first cell's data
+    for (int k = tid; k < N1 * N1; k += THREADS) {
+        B1[k] = A.tab.B1[k];
+        D1[k] = A.tab.D1[k];
+    }
+    for (int k = tid; k < NQ; k += THREADS) wq[k] = A.tab.w[k];
+    for (int k = tid; k < H::NOP * H::OP_BYTES / (int)sizeof(OPT); k += THREADS) op[k] = OPT(0);
+    const int ga = tid / 3, gc = tid - 3 * (tid / 3);  // node / axis of this thread's coordinate
+    if (tid < 3 * NB) {
+        const int64_t n = checked_node(A.conn, e * NB + ga, A.n_nodes, A.flags);
+        xs[gc * NB + ga] = A.coords[3 * n + gc];
+    }
+    if constexpr (ELAST)
+        if (tid < 2) lms[tid] = mat[2 * e + tid];
+    __syncthreads();
+
+    for (;;) {
+        const int64_t en = e + stride;
+        const bool has_next = en < e_end;
+        T lam = T(0), mu = T(0);
+        if constexpr (ELAST) {
+            lam = lms[0];
+            mu = lms[1];
+        }
+
+        // 1. J[i][j] at each point: sum over the tensor-product nodes with
+        //    the 1-D value / derivative tables
+        for (int it = tid; it < NQ * 9; it += THREADS) {
+            const int q = it % NQ, ij = it / NQ, i = ij / 3, jj = ij - 3 * (ij / 3);
+            const int q0 = q % N1, q1 = (q / N1) % N1, q2 = q / (N1 * N1);
+            const double *T0 = (jj == 0 ? D1 : B1) + q0 * N1;
+            const double *T1 = (jj == 1 ? D1 : B1) + q1 * N1;
+            const double *T2 = (jj == 2 ? D1 : B1) + q2 * N1;
+            const double *x = xs + i * NB;
+            double s2 = 0.0;
+#pragma unroll
+            for (int a2 = 0; a2 < N1; a2++) {
+                double s1 = 0.0;
+#pragma unroll
+                for (int a1 = 0; a1 < N1; a1++) {
+                    const double *xr = x + N1 * (a1 + N1 * a2);
+                    double s0 = 0.0;
+#pragma unroll
+                    for (int a0 = 0; a0 < N1; a0++) s0 = fma(T0[a0], xr[a0], s0);
+                    s1 = fma(T1[a1], s0, s1);
+                }
+                s2 = fma(T2[a2], s1, s2);
+            }
+            Jq[q * 9 + ij] = s2;
+        }
+        // first prefetch hop: the next cell's connectivity and coefficients
+        int32_t nn = 0;
+        T lamn = T(0);
+        if (has_next) {
+            if (tid < 3 * NB) nn = A.conn[en * NB + ga];
+            if constexpr (ELAST)
+                if (tid < 2) lamn = mat[2 * en + tid];
+        }
+        __syncthreads();
+
+        // 2. det J, J^-1, sqrt(w det J) per point
+        double Mv[10];
+        const int q = tid;
+        if (q < NQ) {
+            double J[3][3], Ji[3][3];
+#pragma unroll
+            for (int r = 0; r < 3; r++)
+#pragma unroll
+                for (int c = 0; c < 3; c++) J[r][c] = Jq[q * 9 + r * 3 + c];
+            const double det = inverse3(J, Ji);
+            if (!(det > 0.0)) raise_fault(A.flags, FAULT_DET);
+            const double sw = sqrt(wq[q] * (det > 0.0 ? det : 0.0));
+#pragma unroll
+            for (int jj = 0; jj < 3; jj++)
+#pragma unroll
+                for (int i = 0; i < 3; i++) Mv[jj * 3 + i] = sw * Ji[jj][i];
+            Mv[9] = sw;
+        }
+        __syncthreads();  // every J read before Mq (same space) is written
+        if (q < NQ)
+#pragma unroll
+            for (int k = 0; k < 10; k++) Mq[q * 10 + k] = Mv[k];
+        __syncthreads();
+
+        // 3. the operand: item (q, a1, a2) writes g for a0 = 0..N1-1 and the
+        //    NC components; consecutive threads take consecutive points
+        for (int it = tid; it < NQ * N1 * N1; it += THREADS) {
+            const int qq = it % NQ, a12 = it / NQ, a1 = a12 % N1, a2 = a12 / N1;
+            const int q0 = qq % N1, q1 = (qq / N1) % N1, q2 = qq / (N1 * N1);
+            const double by = B1[q1 * N1 + a1], bz = B1[q2 * N1 + a2];
+            const double *M = Mq + qq * 10;
+            double g[NC][N1];
+            if constexpr (NC == 1) {
+                const double f = M[9] * by * bz;
+#pragma unroll
+                for (int a0 = 0; a0 < N1; a0++) g[0][a0] = f * B1[q0 * N1 + a0];
+            } else {
+                const double dy = D1[q1 * N1 + a1], dz = D1[q2 * N1 + a2];
+                const double m[9] = {M[0], M[1], M[2], M[3], M[4], M[5], M[6], M[7], M[8]};
+#pragma unroll
+                for (int a0 = 0; a0 < N1; a0++) {
+                    const double bx = B1[q0 * N1 + a0], dx = D1[q0 * N1 + a0];
+                    const double d0 = dx * by * bz, d1 = bx * dy * bz, d2 = bx * by * dz;
+#pragma unroll
+                    for (int c = 0; c < 3; c++) g[c][a0] = d0 * m[c] + d1 * m[3 + c] + d2 * m[6 + c];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < NC; c++)
+#pragma unroll
+                for (int a0 = 0; a0 < N1; a0++) {
+                    const int o = (c * NBP + a0 + N1 * a12) * KS + qq;
+                    if constexpr (H::NOP == 1) {
+                        op[o] = static_cast<OPT>(g[c][a0]);
+                    } else {
+                        const float x = static_cast<float>(g[c][a0]);
+                        const __bf16 h = static_cast<__bf16>(x);
+                        op[o] = h;
+                        op[H::OP_BYTES / sizeof(OPT) + o] = static_cast<__bf16>(x - static_cast<float>(h));
+                    }
+                }
+        }
+        __syncthreads();
+
+        // second prefetch hop: the next cell's coordinates (the empty asm
+        // keeps the wait for the connectivity load here)
+        double xnext = 0.0;
+        if (has_next && tid < 3 * NB) {
+            asm volatile("" : "+v"(nn));
+            int64_t n = nn;
+            if (n < 0 || n >= A.n_nodes) {
+                raise_fault(A.flags, FAULT_INDEX);
+                n = 0;
+            }
+            xnext = A.coords[3 * n + gc];
+        }
+
+        // 4. this wave's jobs
+        {
+            T *oc = static_cast<T *>(A.out) + e * static_cast<int64_t>(H::ND) * H::ND;
+            const int nj = H::SCHED.n[wave];
+            for (int jj = 0; jj < nj; jj++) run_job<H, FORM>(H::SCHED.job[wave][jj], op, oc, buf, lam, mu, lane);
+        }
+
+        // park the next cell's data (x is only read in step 1, the
+        // coefficients at the top of the loop)
+        if (has_next) {
+            if (tid < 3 * NB) xs[gc * NB + ga] = xnext;
+            if constexpr (ELAST)
+                if (tid < 2) lms[tid] = lamn;
+        }
+        __syncthreads();
+        if (!has_next) break;
+        e = en;
+    }
+}
+
+template <int P, int FORM, int MM>
+int launch_hexmm(const Plan &, const ExecArgs &A, hipStream_t st)
+{
+    if (A.n_cells <= 0) return FE_OK;
+    if (A.n_cells > 0x7fffffffLL) {
+        set_error("too many cells for one launch");
+        return FE_ERR_INVALID_ARG;
+    }
+    static int resident[64] = {0};
+    int dev = 0;
+    FE_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return FE_ERR_INVALID_ARG;
+    if (!resident[dev]) {
+        int per_cu = 0, cus = 0;
+        FE_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_hexmm<P, FORM, MM>, THREADS, 0));
+        FE_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        resident[dev] = per_cu * cus > 8 ? (per_cu * cus) & ~7 : 8;
+    }
+    const int64_t grid = A.n_cells < resident[dev] ? A.n_cells : resident[dev];
+    hipLaunchKernelGGL((k_hexmm<P, FORM, MM>), dim3((unsigned)grid), dim3(THREADS), 0, st, A);
+    FE_HIP_CHECK(hipGetLastError());
+    return FE_OK;
+}
+
+template <int P, int MM>
+LaunchFn pick_form(const Plan &p)
+{
+    switch (p.form) {
+    case FE_FORM_MASS: return launch_hexmm<P, FE_FORM_MASS, MM>;
+    case FE_FORM_VMASS: return launch_hexmm<P, FE_FORM_VMASS, MM>;
+    case FE_FORM_LAPLACE: return launch_hexmm<P, FE_FORM_LAPLACE, MM>;
+    case FE_FORM_ELASTICITY:
+        return p.mat_kind == FE_MAT_ISO_CELL ? launch_hexmm<P, FE_FORM_ELASTICITY, MM> : nullptr;
+    }
+    return nullptr;
+}
+
+template <int MM>
+LaunchFn pick_order(const Plan &p)
+{
+    if (p.order == 2) return pick_form<2, MM>(p);
+    if (p.order == 3) return pick_form<3, MM>(p);
+    return nullptr;
+}
+
+}  // namespace
+
+LaunchFn select_hexmm(const Plan &p)
+{
+    if (p.cell != FE_CELL_HEX || p.mode != FE_MODE_MATRIX) return nullptr;
+    if (p.prec == FE_PREC_FP64) return pick_order<MM_F64>(p);
+    if (p.prec == FE_PREC_FP32) return pick_order<MM_F32>(p);
+    if (p.prec == FE_PREC_BF16X3) return pick_order<MM_BF16X3>(p);
+    return nullptr;
+}
+
+}  // namespace fe
