@@ -67,16 +67,18 @@ enum : int { J_DIAG = 0, J_PAIR = 1, J_SINGLE = 2, J_LAP = 3, J_MASS = 4 };
 
 constexpr int align_to(int x, int a) { return (x + a - 1) / a * a; }
 
-// LDS row stride (entries) of the operand for a padded depth KP: conflict-free
-// fragment reads (FP64: stride = 2 mod 4 doubles; FP32: 4 mod 8 floats;
-// bf16: 8 mod 16 halves).
+// LDS row stride (entries) of the operand for a padded depth KP, so that the
+// fragment reads (16 rows x 4 points, or 16 rows x 8 points for bf16) hit
+// distinct banks of the 32 four-byte LDS banks in every pass: FP64 odd,
+// FP32 2 mod 4, bf16 8 mod 16 (measured with the LDS bank-conflict
+// counter).
 constexpr int op_stride(int mm, int kp)
 {
     int ks = kp;
     if (mm == MM_F64)
-        while (ks % 4 != 2) ks++;
+        while (ks % 2 != 1) ks++;
     else if (mm == MM_F32)
-        while (ks % 8 != 4) ks++;
+        while (ks % 4 != 2) ks++;
     else
         while (ks % 16 != 8) ks++;
     return ks;
@@ -154,7 +156,7 @@ struct HexMM {
     static constexpr int KS = op_stride(MM, KP);
     static constexpr int ROWS = NC * NBP;
     static constexpr int NOP = MM == MM_BF16X3 ? 2 : 1;  // operand arrays (hi, lo)
-    static constexpr int TS = 16 + (sizeof(T) == 8 ? 2 : 1);  // transpose buffer row stride
+    static constexpr int TS = 17;  // transpose buffer row stride (conflict-free for FP64)
     // LDS layout (bytes)
     static constexpr int OFF_TB = 0;  // double B1[N1][N1], D1[N1][N1], w[NQ]
     static constexpr int OFF_X = q2::align16(OFF_TB + (2 * N1 * N1 + NQ) * 8);  // double xs[3][NB], T lm[2]
@@ -193,20 +195,39 @@ __device__ __forceinline__ void mma_run(typename H::ACC *acc, const typename H::
     constexpr int KS = H::KS;
     const int m = lane & 15, grp = lane >> 4;
     if constexpr (H::NOP == 1) {
-#pragma unroll 4
-        for (int k = k0; k < k1; k += 4) {
-            OPT a[NU], b[NU];
+        // fragments double-buffered: step k + 4 is loaded while step k
+        // multiplies, so the wave does not wait for LDS before every MFMA
+        OPT a[2][NU], b[2][NU];
+        auto load = [&](int buf, int k) {
 #pragma unroll
             for (int u = 0; u < NU; u++) {
-                a[u] = op[(ra[u] + m) * KS + k + grp];
-                b[u] = op[(rb[u] + m) * KS + k + grp];
+                a[buf][u] = op[(ra[u] + m) * KS + k + grp];
+                b[buf][u] = op[(rb[u] + m) * KS + k + grp];
             }
+        };
+        auto mfma = [&](int buf) {
 #pragma unroll
             for (int u = 0; u < NU; u++) {
                 if constexpr (sizeof(OPT) == 8)
-                    acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc[u], 0, 0, 0);
+                    acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[buf][u], b[buf][u], acc[u], 0, 0, 0);
                 else
-                    acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], b[u], acc[u], 0, 0, 0);
+                    acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[buf][u], b[buf][u], acc[u], 0, 0, 0);
+            }
+        };
+        // (the scheduling barriers keep the compiler from regrouping the
+        // loads after the products that do not need them)
+        load(0, k0);
+#pragma unroll
+        for (int k = k0; k < k1; k += 8) {
+            if (k + 4 < k1) load(1, k + 4);
+            __builtin_amdgcn_sched_barrier(0);
+            mfma(0);
+            __builtin_amdgcn_sched_barrier(0);
+            if (k + 4 < k1) {
+                if (k + 8 < k1) load(0, k + 8);
+                __builtin_amdgcn_sched_barrier(0);
+                mfma(1);
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
     } else {
@@ -270,14 +291,93 @@ __device__ __forceinline__ int valid(int t)  // valid entries of tile t of a blo
     return H::NB - 16 * t < 16 ? H::NB - 16 * t : 16;
 }
 
+// Elasticity output of a DIAG job from c[t] = P_tt(i,j), t = 0,1,2:
+// K_tt(i,j) = (lambda + mu) P_tt(i,j) + mu sum_t' P_t't'(i,j), and the
+// mirrored tiles K_tt(j,i) = K_tt(i,j)^T when i != j.
+template <class H>
+__device__ __forceinline__ void epi_diag(const typename H::ACC *c, typename H::T *oc, typename H::T *buf,
+                                         typename H::T lam, typename H::T mu, int i, int j, int lane)
+{
+    using T = typename H::T;
+    using ACC = typename H::ACC;
+    constexpr int NB = H::NB;
+    const int vi = valid<H>(i), vj = valid<H>(j);
+    ACC S;
+#pragma unroll
+    for (int v = 0; v < 4; v++) S[v] = c[0][v] + c[1][v] + c[2][v];
+    const T lm = lam + mu;
+#pragma unroll
+    for (int t = 0; t < 3; t++) {
+        ACC k;
+#pragma unroll
+        for (int v = 0; v < 4; v++) k[v] = lm * c[t][v] + mu * S[v];
+        store_tile<H>(oc, t * NB + 16 * i, t * NB + 16 * j, vi, vj, k, lane);
+    }
+    if (i != j) {
+        const ACC St = transpose<H>(S, buf, lane);
+#pragma unroll
+        for (int t = 0; t < 3; t++) {
+            const ACC ct = transpose<H>(c[t], buf, lane);
+            ACC k;
+#pragma unroll
+            for (int v = 0; v < 4; v++) k[v] = lm * ct[v] + mu * St[v];
+            store_tile<H>(oc, t * NB + 16 * j, t * NB + 16 * i, vj, vi, k, lane);
+        }
+    }
+}
+
+// Elasticity output of a PAIR job from A = c[0] = P_rs(i,j), B = c[1] =
+// P_rs(j,i) (r < s): K_rs(i,j) = lambda A + mu B^T, K_rs(j,i) = lambda B +
+// mu A^T, and their transposes in block (s,r).
+template <class H>
+__device__ __forceinline__ void epi_pair(const typename H::ACC *c, typename H::T *oc, typename H::T *buf,
+                                         typename H::T lam, typename H::T mu, int r, int s, int i, int j, int lane)
+{
+    using ACC = typename H::ACC;
+    constexpr int NB = H::NB;
+    const int vi = valid<H>(i), vj = valid<H>(j);
+    const ACC Bt = transpose<H>(c[1], buf, lane);
+    ACC x;
+#pragma unroll
+    for (int v = 0; v < 4; v++) x[v] = lam * c[0][v] + mu * Bt[v];
+    store_tile<H>(oc, r * NB + 16 * i, s * NB + 16 * j, vi, vj, x, lane);  // K_rs(i,j)
+#pragma unroll
+    for (int v = 0; v < 4; v++) x[v] = lam * Bt[v] + mu * c[0][v];
+    store_tile<H>(oc, s * NB + 16 * i, r * NB + 16 * j, vi, vj, x, lane);  // K_sr(i,j)
+    const ACC At = transpose<H>(c[0], buf, lane);
+#pragma unroll
+    for (int v = 0; v < 4; v++) x[v] = lam * c[1][v] + mu * At[v];
+    store_tile<H>(oc, r * NB + 16 * j, s * NB + 16 * i, vj, vi, x, lane);  // K_rs(j,i)
+#pragma unroll
+    for (int v = 0; v < 4; v++) x[v] = lam * At[v] + mu * c[1][v];
+    store_tile<H>(oc, s * NB + 16 * j, r * NB + 16 * i, vj, vi, x, lane);  // K_sr(j,i)
+}
+
+// Elasticity output of a SINGLE job from a = P_rs(i,i) (r < s).
+template <class H>
+__device__ __forceinline__ void epi_single(const typename H::ACC &a, typename H::T *oc, typename H::T *buf,
+                                           typename H::T lam, typename H::T mu, int r, int s, int i, int lane)
+{
+    using ACC = typename H::ACC;
+    constexpr int NB = H::NB;
+    const int vi = valid<H>(i);
+    const ACC at = transpose<H>(a, buf, lane);
+    ACC x;
+#pragma unroll
+    for (int v = 0; v < 4; v++) x[v] = lam * a[v] + mu * at[v];
+    store_tile<H>(oc, r * NB + 16 * i, s * NB + 16 * i, vi, vi, x, lane);
+#pragma unroll
+    for (int v = 0; v < 4; v++) x[v] = lam * at[v] + mu * a[v];
+    store_tile<H>(oc, s * NB + 16 * i, r * NB + 16 * i, vi, vi, x, lane);
+}
+
 // One job of the current cell.  oc = the cell's output matrix.
 template <class H, int FORM>
 __device__ __forceinline__ void run_job(uint32_t jb, const typename H::OPT *op, typename H::T *oc,
                                         typename H::T *buf, typename H::T lam, typename H::T mu, int lane)
 {
-    using T = typename H::T;
     using ACC = typename H::ACC;
-    constexpr int NB = H::NB, NBP = H::NBP, KP = H::KP;
+    constexpr int NBP = H::NBP, KP = H::KP;
     const int kind = jb & 15, r = (jb >> 4) & 3, s = (jb >> 6) & 3, i = (jb >> 8) & 15, j = (jb >> 12) & 15;
     const int vi = valid<H>(i), vj = valid<H>(j);
     if (kind == J_DIAG || kind == J_LAP) {
@@ -285,92 +385,46 @@ __device__ __forceinline__ void run_job(uint32_t jb, const typename H::OPT *op, 
         const int ra[3] = {16 * i, NBP + 16 * i, 2 * NBP + 16 * i};
         const int rb[3] = {16 * j, NBP + 16 * j, 2 * NBP + 16 * j};
         mma_run<H, 3>(c, op, ra, rb, 0, KP, lane);
+        if (kind == J_DIAG) {
+            epi_diag<H>(c, oc, buf, lam, mu, i, j, lane);
+            return;
+        }
         ACC S;
 #pragma unroll
         for (int v = 0; v < 4; v++) S[v] = c[0][v] + c[1][v] + c[2][v];
-        if (kind == J_LAP) {
-            store_tile<H>(oc, 16 * i, 16 * j, vi, vj, S, lane);
-            if (i != j) store_tile<H>(oc, 16 * j, 16 * i, vj, vi, transpose<H>(S, buf, lane), lane);
-            return;
-        }
-        const T lm = lam + mu;
-#pragma unroll
-        for (int t = 0; t < 3; t++) {
-            ACC k;
-#pragma unroll
-            for (int v = 0; v < 4; v++) k[v] = lm * c[t][v] + mu * S[v];
-            store_tile<H>(oc, t * NB + 16 * i, t * NB + 16 * j, vi, vj, k, lane);
-        }
-        if (i != j) {
-            const ACC St = transpose<H>(S, buf, lane);
-#pragma unroll
-            for (int t = 0; t < 3; t++) {
-                const ACC ct = transpose<H>(c[t], buf, lane);
-                ACC k;
-#pragma unroll
-                for (int v = 0; v < 4; v++) k[v] = lm * ct[v] + mu * St[v];
-                store_tile<H>(oc, t * NB + 16 * j, t * NB + 16 * i, vj, vi, k, lane);
-            }
-        }
+        store_tile<H>(oc, 16 * i, 16 * j, vi, vj, S, lane);
+        if (i != j) store_tile<H>(oc, 16 * j, 16 * i, vj, vi, transpose<H>(S, buf, lane), lane);
     } else if (kind == J_PAIR) {
         ACC c[2] = {};
         const int ra[2] = {r * NBP + 16 * i, r * NBP + 16 * j};
         const int rb[2] = {s * NBP + 16 * j, s * NBP + 16 * i};
         mma_run<H, 2>(c, op, ra, rb, 0, KP, lane);
-        // A = P_rs(i,j) = c[0], B = P_rs(j,i) = c[1]
-        const ACC Bt = transpose<H>(c[1], buf, lane);
-        ACC x;
-#pragma unroll
-        for (int v = 0; v < 4; v++) x[v] = lam * c[0][v] + mu * Bt[v];
-        store_tile<H>(oc, r * NB + 16 * i, s * NB + 16 * j, vi, vj, x, lane);  // K_rs(i,j)
-#pragma unroll
-        for (int v = 0; v < 4; v++) x[v] = lam * Bt[v] + mu * c[0][v];
-        store_tile<H>(oc, s * NB + 16 * i, r * NB + 16 * j, vi, vj, x, lane);  // K_sr(i,j)
-        const ACC At = transpose<H>(c[0], buf, lane);
-#pragma unroll
-        for (int v = 0; v < 4; v++) x[v] = lam * c[1][v] + mu * At[v];
-        store_tile<H>(oc, r * NB + 16 * j, s * NB + 16 * i, vj, vi, x, lane);  // K_rs(j,i)
-#pragma unroll
-        for (int v = 0; v < 4; v++) x[v] = lam * At[v] + mu * c[1][v];
-        store_tile<H>(oc, s * NB + 16 * j, r * NB + 16 * i, vj, vi, x, lane);  // K_sr(j,i)
-    } else if (kind == J_SINGLE) {
-        // two half-depth products in flight, summed
+        epi_pair<H>(c, oc, buf, lam, mu, r, s, i, j, lane);
+    } else {
+        // SINGLE / MASS: two half-depth products in flight, summed
         ACC c[2] = {};
         constexpr int KH = align_to(KP / 2, H::NOP == 2 ? 32 : 4);
-        const int ra[1] = {r * NBP + 16 * i}, rb[1] = {s * NBP + 16 * i};
+        const int ra[1] = {kind == J_SINGLE ? r * NBP + 16 * i : 16 * i};
+        const int rb[1] = {kind == J_SINGLE ? s * NBP + 16 * i : 16 * j};
         mma_run<H, 1>(c, op, ra, rb, 0, KH, lane);
         if constexpr (KH < KP) mma_run<H, 1>(c + 1, op, ra, rb, KH, KP, lane);
         ACC a;
 #pragma unroll
         for (int v = 0; v < 4; v++) a[v] = c[0][v] + c[1][v];
-        const ACC at = transpose<H>(a, buf, lane);
-        ACC x;
-#pragma unroll
-        for (int v = 0; v < 4; v++) x[v] = lam * a[v] + mu * at[v];
-        store_tile<H>(oc, r * NB + 16 * i, s * NB + 16 * i, vi, vi, x, lane);
-#pragma unroll
-        for (int v = 0; v < 4; v++) x[v] = lam * at[v] + mu * a[v];
-        store_tile<H>(oc, s * NB + 16 * i, r * NB + 16 * i, vi, vi, x, lane);
-    } else {  // J_MASS
-        ACC c[2] = {};
-        constexpr int KH = align_to(KP / 2, H::NOP == 2 ? 32 : 4);
-        const int ra[1] = {16 * i}, rb[1] = {16 * j};
-        mma_run<H, 1>(c, op, ra, rb, 0, KH, lane);
-        if constexpr (KH < KP) mma_run<H, 1>(c + 1, op, ra, rb, KH, KP, lane);
-        ACC mt;
-#pragma unroll
-        for (int v = 0; v < 4; v++) mt[v] = c[0][v] + c[1][v];
-        if constexpr (FORM == FE_FORM_MASS) {
-            store_tile<H>(oc, 16 * i, 16 * j, vi, vj, mt, lane);
-            if (i != j) store_tile<H>(oc, 16 * j, 16 * i, vj, vi, transpose<H>(mt, buf, lane), lane);
+        if (kind == J_SINGLE) {
+            epi_single<H>(a, oc, buf, lam, mu, r, s, i, lane);
+        } else if constexpr (FORM == FE_FORM_MASS) {
+            store_tile<H>(oc, 16 * i, 16 * j, vi, vj, a, lane);
+            if (i != j) store_tile<H>(oc, 16 * j, 16 * i, vj, vi, transpose<H>(a, buf, lane), lane);
         } else {
-            const ACC tt = i != j ? transpose<H>(mt, buf, lane) : mt;
+            constexpr int NB = H::NB;
+            const ACC tt = i != j ? transpose<H>(a, buf, lane) : a;
             const ACC z = {};
 #pragma unroll
             for (int rr = 0; rr < 3; rr++)
 #pragma unroll
                 for (int ss = 0; ss < 3; ss++) {
-                    store_tile<H>(oc, rr * NB + 16 * i, ss * NB + 16 * j, vi, vj, rr == ss ? mt : z, lane);
+                    store_tile<H>(oc, rr * NB + 16 * i, ss * NB + 16 * j, vi, vj, rr == ss ? a : z, lane);
                     if (i != j) store_tile<H>(oc, rr * NB + 16 * j, ss * NB + 16 * i, vj, vi, rr == ss ? tt : z, lane);
                 }
         }
@@ -561,6 +615,375 @@ __global__ __launch_bounds__(THREADS, MM == MM_F64 ? 1 : 2) void k_hexmm(ExecArg
     }
 }
 
+// ---------------------------------------------------------------------------
+// Q3 elasticity (per-cell coefficients) with producer and consumer waves.
+//
+// The operand is split by quadrature points into two halves (points 0..31
+// and 32..63), each in its own LDS buffer.  Eight consumer waves keep the
+// accumulators of all their jobs' tiles across both halves; four producer
+// waves build each half together, 8 points each (their Jacobians, inverses
+// and operand columns), synchronising only inside their own wave, at raised
+// wave priority since they are on the critical path.  Per cell, two phases
+// separated by workgroup barriers:
+//   A  consumers multiply on half 0; producers build half 1 of this cell and
+//      load the next cell's coordinates and coefficients into the other
+//      parity slot;
+//   B  consumers multiply on half 1, then write the output of their even job
+//      slots; producers build half 0 of the next cell.
+// The odd slots' output is written at the start of the next phase A, so a
+// cell's stores spread over both phases and drain while the matrix cores
+// work.  Every wave executes the same barriers.
+template <int MM>
+struct Q3WS {
+    static constexpr int N1 = 4, NB = 64, NQ = 64, NBP = 64, NT = 4, ND = 192;
+    static constexpr bool RAGGED = false;
+    using T = typename MMT<MM>::T;
+    using ACC = typename MMT<MM>::acc;
+    using OPT = typename std::conditional<MM == MM_BF16X3, __bf16, T>::type;
+    static constexpr int KP = 32;  // points per half
+    static constexpr int KS = op_stride(MM, KP);
+    static constexpr int ROWS = 3 * NBP;
+    static constexpr int NOP = MM == MM_BF16X3 ? 2 : 1;
+    static constexpr int TS = 17;
+    static constexpr int OP_BYTES = q2::align16(ROWS * KS * (int)sizeof(OPT));  // one array of one half
+    static constexpr int CONS = WAVES, PROD = 4, THREADS = 64 * (CONS + PROD), QW = KP / PROD;
+    static constexpr int OFF_TB = 0;                                   // double B1[16], D1[16], w[64]
+    static constexpr int OFF_X = OFF_TB + (2 * N1 * N1 + NQ) * 8;      // double xs[2][3][64]
+    static constexpr int OFF_LM = OFF_X + 2 * 3 * NB * 8;              // T lm[2][2]
+    static constexpr int OFF_GEO = q2::align16(OFF_LM + 4 * 8);        // double geo[PROD][QW][10]
+    static constexpr int OFF_OP = q2::align16(OFF_GEO + PROD * QW * 10 * 8);  // OPT op[2][NOP][ROWS][KS]
+    static constexpr int OFF_TR = OFF_OP + 2 * NOP * OP_BYTES;         // T tbuf[CONS][16][TS]
+    static constexpr int BYTES = q2::align16(OFF_TR + CONS * 16 * TS * (int)sizeof(T));
+    static constexpr Sched SCHED = make_sched(FE_FORM_ELASTICITY, NT);
+};
+
+constexpr int sched_slots(const Sched &S)
+{
+    int m = 0;
+    for (int w = 0; w < WAVES; w++) m = S.n[w] > m ? S.n[w] : m;
+    return m;
+}
+
+// largest number of tiles any wave's job in slot jj multiplies
+constexpr int slot_cap(const Sched &S, int jj)
+{
+    int m = 0;
+    for (int w = 0; w < WAVES; w++)
+        if (jj < S.n[w]) {
+            const int k = S.job[w][jj] & 15, t = k == J_DIAG ? 3 : (k == J_PAIR ? 2 : 1);
+            m = t > m ? t : m;
+        }
+    return m;
+}
+
+// one half of the depth for the tiles of the job in a slot of capacity CAP
+template <int MM, int CAP>
+__device__ __forceinline__ void ws_mma(typename Q3WS<MM>::ACC (&acc)[3], uint32_t jb, const typename Q3WS<MM>::OPT *op,
+                                       int lane)
+{
+    using H = Q3WS<MM>;
+    const int kind = jb & 15, r = (jb >> 4) & 3, s = (jb >> 6) & 3, i = (jb >> 8) & 15, j = (jb >> 12) & 15;
+    if (kind == J_DIAG) {
+        if constexpr (CAP >= 3) {
+            const int ra[3] = {16 * i, 64 + 16 * i, 128 + 16 * i}, rb[3] = {16 * j, 64 + 16 * j, 128 + 16 * j};
+            mma_run<H, 3>(acc, op, ra, rb, 0, H::KP, lane);
+        }
+    } else if (kind == J_PAIR) {
+        if constexpr (CAP >= 2) {
+            const int ra[2] = {r * 64 + 16 * i, r * 64 + 16 * j}, rb[2] = {s * 64 + 16 * j, s * 64 + 16 * i};
+            mma_run<H, 2>(acc, op, ra, rb, 0, H::KP, lane);
+        }
+    } else {
+        const int ra[1] = {r * 64 + 16 * i}, rb[1] = {s * 64 + 16 * i};
+        mma_run<H, 1>(acc, op, ra, rb, 0, H::KP, lane);
+    }
+}
+
+template <int MM, int CAP>
+__device__ __forceinline__ void ws_epi(const typename Q3WS<MM>::ACC (&acc)[3], uint32_t jb, typename Q3WS<MM>::T *oc,
+                                       typename Q3WS<MM>::T *buf, typename Q3WS<MM>::T lam, typename Q3WS<MM>::T mu,
+                                       int lane)
+{
+    using H = Q3WS<MM>;
+    const int kind = jb & 15, r = (jb >> 4) & 3, s = (jb >> 6) & 3, i = (jb >> 8) & 15, j = (jb >> 12) & 15;
+    if (kind == J_DIAG) {
+        if constexpr (CAP >= 3) epi_diag<H>(acc, oc, buf, lam, mu, i, j, lane);
+    } else if (kind == J_PAIR) {
+        if constexpr (CAP >= 2) epi_pair<H>(acc, oc, buf, lam, mu, r, s, i, j, lane);
+    } else {
+        epi_single<H>(acc[0], oc, buf, lam, mu, r, s, i, lane);
+    }
+}
+
+// Consumer work of one phase over slots JJ.. of this wave:
+//   PH = 0: (write the previous cell's odd slots,) zero, multiply on half 0;
+//   PH = 1: multiply on half 1, write the even slots;
+//   PH = 2: write the odd slots (after the last cell).
+template <int MM, int PH, int JJ>
+__device__ __forceinline__ void ws_slots(typename Q3WS<MM>::ACC (&acc)[sched_slots(Q3WS<MM>::SCHED)][3], int wave,
+                                         const typename Q3WS<MM>::OPT *op, typename Q3WS<MM>::T *oc,
+                                         typename Q3WS<MM>::T *oc_prev, typename Q3WS<MM>::T *buf,
+                                         typename Q3WS<MM>::T lam, typename Q3WS<MM>::T mu, int lane)
+{
+    using H = Q3WS<MM>;
+    constexpr int NS = sched_slots(H::SCHED);
+    if constexpr (JJ < NS) {
+        constexpr int CAP = slot_cap(H::SCHED, JJ);
+        if (JJ < H::SCHED.n[wave]) {
+            const uint32_t jb = H::SCHED.job[wave][JJ];
+            if constexpr (PH == 0) {
+                if ((JJ & 1) && oc_prev) ws_epi<MM, CAP>(acc[JJ], jb, oc_prev, buf, lam, mu, lane);
+#pragma unroll
+                for (int u = 0; u < 3; u++) acc[JJ][u] = typename H::ACC{};
+                ws_mma<MM, CAP>(acc[JJ], jb, op, lane);
+            } else if constexpr (PH == 1) {
+                ws_mma<MM, CAP>(acc[JJ], jb, op, lane);
+                if (!(JJ & 1)) ws_epi<MM, CAP>(acc[JJ], jb, oc, buf, lam, mu, lane);
+            } else {
+                if (JJ & 1) ws_epi<MM, CAP>(acc[JJ], jb, oc, buf, lam, mu, lane);
+            }
+        }
+        ws_slots<MM, PH, JJ + 1>(acc, wave, op, oc, oc_prev, buf, lam, mu, lane);
+    }
+}
+
+// Producer pw: geometry of the points 32 h + 8 pw .. + 7 of half h of the
+// cell whose coordinates are x[3][64], and their columns of the operand
+// half opd.
+template <int MM>
+__device__ __forceinline__ void ws_produce(int pw, int h, const double *x, const double *B1, const double *D1,
+                                           const double *wq, double *geo, typename Q3WS<MM>::OPT *opd, int lane,
+                                           unsigned *flags)
+{
+    using H = Q3WS<MM>;
+    using OPT = typename H::OPT;
+    constexpr int QW = H::QW, KS = H::KS;
+    const int cb = QW * pw, qb = H::KP * h + cb;
+    // J[i][0..2] at point qb + lane % QW for component i = lane / QW
+    if (lane < 3 * QW) {
+        const int ql = lane % QW, i = lane / QW, q = qb + ql;
+        const int q0 = q & 3, q1 = (q >> 2) & 3, q2 = q >> 4;
+        double b0[4], d0[4], b1[4], d1[4], b2[4], d2[4];
+#pragma unroll
+        for (int a = 0; a < 4; a++) {
+            b0[a] = B1[q0 * 4 + a];
+            d0[a] = D1[q0 * 4 + a];
+            b1[a] = B1[q1 * 4 + a];
+            d1[a] = D1[q1 * 4 + a];
+            b2[a] = B1[q2 * 4 + a];
+            d2[a] = D1[q2 * 4 + a];
+        }
+        const double *xi = x + 64 * i;
+        double j0 = 0.0, j1 = 0.0, j2 = 0.0;
+#pragma unroll
+        for (int a2 = 0; a2 < 4; a2++) {
+            double tdb = 0.0, tbd = 0.0, tbb = 0.0;
+#pragma unroll
+            for (int a1 = 0; a1 < 4; a1++) {
+                const double *xr = xi + 4 * a1 + 16 * a2;
+                double sb = 0.0, sd = 0.0;
+#pragma unroll
+                for (int a0 = 0; a0 < 4; a0++) {
+                    sb = fma(b0[a0], xr[a0], sb);
+                    sd = fma(d0[a0], xr[a0], sd);
+                }
+                tdb = fma(b1[a1], sd, tdb);
+                tbd = fma(d1[a1], sb, tbd);
+                tbb = fma(b1[a1], sb, tbb);
+            }
+            j0 = fma(b2[a2], tdb, j0);
+            j1 = fma(b2[a2], tbd, j1);
+            j2 = fma(d2[a2], tbb, j2);
+        }
+        geo[ql * 10 + i * 3 + 0] = j0;
+        geo[ql * 10 + i * 3 + 1] = j1;
+        geo[ql * 10 + i * 3 + 2] = j2;
+    }
+    wave_sync();
+    // sqrt(w det J) J^-1 and sqrt(w det J) per point (lane = point)
+    if (lane < QW) {
+        double J[3][3], Ji[3][3];
+#pragma unroll
+        for (int r = 0; r < 3; r++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) J[r][c] = geo[lane * 10 + r * 3 + c];
+        const double det = inverse3(J, Ji);
+        if (!(det > 0.0)) raise_fault(flags, FAULT_DET);
+        const double sw = sqrt(wq[qb + lane] * (det > 0.0 ? det : 0.0));
+#pragma unroll
+        for (int jj = 0; jj < 3; jj++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) geo[lane * 10 + jj * 3 + c] = sw * Ji[jj][c];
+        geo[lane * 10 + 9] = sw;
+    }
+    wave_sync();
+    // operand columns: item (point, a1, a2) writes a0 = 0..3, components 0..2
+#pragma unroll
+    for (int k = 0; k < QW * 16 / 64; k++) {
+        const int it = lane + 64 * k, ql = it % QW, a12 = it / QW, a1 = a12 & 3, a2 = a12 >> 2;
+        const int q = qb + ql, q0 = q & 3, q1 = (q >> 2) & 3, q2 = q >> 4;
+        const double *M = geo + ql * 10;
+        const double by = B1[q1 * 4 + a1], dy = D1[q1 * 4 + a1], bz = B1[q2 * 4 + a2], dz = D1[q2 * 4 + a2];
+        double m[9];
+#pragma unroll
+        for (int t = 0; t < 9; t++) m[t] = M[t];
+        const double byz = by * bz, dyz = dy * bz, bdz = by * dz;
+#pragma unroll
+        for (int a0 = 0; a0 < 4; a0++) {
+            const double bx = B1[q0 * 4 + a0], dx = D1[q0 * 4 + a0];
+            const double g0 = dx * byz, g1 = bx * dyz, g2 = bx * bdz;
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                const double g = g0 * m[c] + g1 * m[3 + c] + g2 * m[6 + c];
+                const int o = (c * 64 + a0 + 4 * a12) * KS + cb + ql;
+                if constexpr (H::NOP == 1) {
+                    opd[o] = static_cast<OPT>(g);
+                } else {
+                    const float xf = static_cast<float>(g);
+                    const __bf16 h = static_cast<__bf16>(xf);
+                    opd[o] = h;
+                    opd[H::OP_BYTES / sizeof(OPT) + o] = static_cast<__bf16>(xf - static_cast<float>(h));
+                }
+            }
+        }
+    }
+}
+
+template <int MM>
+__global__ __launch_bounds__(Q3WS<MM>::THREADS, 1) void k_elast_q3ws(ExecArgs A)
+{
+    using H = Q3WS<MM>;
+    using T = typename H::T;
+    using OPT = typename H::OPT;
+    using ACC = typename H::ACC;
+    constexpr int NS = sched_slots(H::SCHED);
+    __shared__ __align__(16) unsigned char smem[H::BYTES];
+    double *B1 = reinterpret_cast<double *>(smem + H::OFF_TB);
+    double *D1 = B1 + 16;
+    double *wq = D1 + 16;
+    double *xs = reinterpret_cast<double *>(smem + H::OFF_X);  // [2][3][64]
+    T *lms = reinterpret_cast<T *>(smem + H::OFF_LM);          // [2][2]
+    OPT *op0 = reinterpret_cast<OPT *>(smem + H::OFF_OP);
+    OPT *op1 = reinterpret_cast<OPT *>(smem + H::OFF_OP + H::NOP * H::OP_BYTES);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const bool consumer = wave < H::CONS;
+    const int pw = wave - H::CONS;
+    double *geo = reinterpret_cast<double *>(smem + H::OFF_GEO) + (consumer ? 0 : pw * H::QW * 10);
+    T *buf = reinterpret_cast<T *>(smem + H::OFF_TR) + (consumer ? wave : 0) * 16 * H::TS;
+
+    int64_t e, e_end, stride;
+    cell_range(A.xcd_remap, A.n_cells, e, e_end, stride);
+    if (e >= e_end) return;  // uniform over the workgroup
+    const T *mat = static_cast<const T *>(A.mat);
+    T *out = static_cast<T *>(A.out);
+    constexpr int64_t NK = 192 * 192;
+
+    for (int k = tid; k < 16; k += H::THREADS) {
+        B1[k] = A.tab.B1[k];
+        D1[k] = A.tab.D1[k];
+    }
+    for (int k = tid; k < 64; k += H::THREADS) wq[k] = A.tab.w[k];
+    const int pt = tid - 64 * H::CONS;  // producer thread 0..255
+    if (!consumer) {
+        if (pt < 192) {
+            const int a = pt / 3, c = pt - 3 * (pt / 3);
+            const int64_t n = checked_node(A.conn, e * 64 + a, A.n_nodes, A.flags);
+            xs[c * 64 + a] = A.coords[3 * n + c];
+        }
+        if (pt < 2) lms[pt] = mat[2 * e + pt];
+    }
+    __syncthreads();
+    if (!consumer) ws_produce<MM>(pw, 0, xs, B1, D1, wq, geo, op0, lane, A.flags);
+    __syncthreads();
+
+    // The two roles run separate loops with the same barriers in the same
+    // order (the role is uniform per wave), so the consumers' accumulators
+    // are not live in the producers' code.
+    if (consumer) {
+        ACC acc[NS][3];
+        T lam = T(0), mu = T(0);
+        T *oc_prev = nullptr;
+        int par = 0;
+        for (;;) {
+            const bool has_next = e + stride < e_end;
+            T *oc = out + e * NK;
+            ws_slots<MM, 0, 0>(acc, wave, op0, oc, oc_prev, buf, lam, mu, lane);
+            __syncthreads();
+            lam = lms[par * 2];
+            mu = lms[par * 2 + 1];
+            ws_slots<MM, 1, 0>(acc, wave, op1, oc, nullptr, buf, lam, mu, lane);
+            __syncthreads();
+            oc_prev = oc;
+            if (!has_next) break;
+            e += stride;
+            par ^= 1;
+        }
+        ws_slots<MM, 2, 0>(acc, wave, op0, oc_prev, nullptr, buf, lam, mu, lane);
+    } else {
+        __builtin_amdgcn_s_setprio(2);
+        const int a0 = pt / 3, c0 = pt - 3 * (pt / 3);  // this thread's coordinate (pt < 192)
+        int par = 0;
+        for (;;) {
+            const int64_t en = e + stride;
+            const bool has_next = en < e_end;
+            // the next cell's connectivity and coefficients now, its
+            // coordinates after this phase's build; parked at the end
+            int32_t nn = 0;
+            T l = T(0);
+            if (has_next) {
+                if (pt < 192) nn = A.conn[en * 64 + a0];
+                if (pt < 2) l = mat[2 * en + pt];
+            }
+            ws_produce<MM>(pw, 1, xs + par * 192, B1, D1, wq, geo, op1, lane, A.flags);
+            if (has_next) {
+                double xn = 0.0;
+                if (pt < 192) {
+                    asm volatile("" : "+v"(nn));
+                    int64_t n = nn;
+                    if (n < 0 || n >= A.n_nodes) {
+                        raise_fault(A.flags, FAULT_INDEX);
+                        n = 0;
+                    }
+                    xn = A.coords[3 * n + c0];
+                    xs[(par ^ 1) * 192 + c0 * 64 + a0] = xn;
+                }
+                if (pt < 2) lms[(par ^ 1) * 2 + pt] = l;
+            }
+            __syncthreads();
+            if (has_next) ws_produce<MM>(pw, 0, xs + (par ^ 1) * 192, B1, D1, wq, geo, op0, lane, A.flags);
+            __syncthreads();
+            if (!has_next) break;
+            e = en;
+            par ^= 1;
+        }
+    }
+}
+
+template <int MM>
+int launch_q3ws(const Plan &, const ExecArgs &A, hipStream_t st)
+{
+    if (A.n_cells <= 0) return FE_OK;
+    if (A.n_cells > 0x7fffffffLL) {
+        set_error("too many cells for one launch");
+        return FE_ERR_INVALID_ARG;
+    }
+    static int resident[64] = {0};
+    int dev = 0;
+    FE_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return FE_ERR_INVALID_ARG;
+    if (!resident[dev]) {
+        int per_cu = 0, cus = 0;
+        FE_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_elast_q3ws<MM>, Q3WS<MM>::THREADS, 0));
+        FE_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        resident[dev] = per_cu * cus > 8 ? (per_cu * cus) & ~7 : 8;
+    }
+    const int64_t grid = A.n_cells < resident[dev] ? A.n_cells : resident[dev];
+    hipLaunchKernelGGL(k_elast_q3ws<MM>, dim3((unsigned)grid), dim3(Q3WS<MM>::THREADS), 0, st, A);
+    FE_HIP_CHECK(hipGetLastError());
+    return FE_OK;
+}
+
 template <int P, int FORM, int MM>
 int launch_hexmm(const Plan &, const ExecArgs &A, hipStream_t st)
 {
@@ -593,7 +1016,9 @@ LaunchFn pick_form(const Plan &p)
     case FE_FORM_VMASS: return launch_hexmm<P, FE_FORM_VMASS, MM>;
     case FE_FORM_LAPLACE: return launch_hexmm<P, FE_FORM_LAPLACE, MM>;
     case FE_FORM_ELASTICITY:
-        return p.mat_kind == FE_MAT_ISO_CELL ? launch_hexmm<P, FE_FORM_ELASTICITY, MM> : nullptr;
+        if (p.mat_kind != FE_MAT_ISO_CELL) return nullptr;
+        if constexpr (P == 3) return launch_q3ws<MM>;
+        return launch_hexmm<P, FE_FORM_ELASTICITY, MM>;
     }
     return nullptr;
 }
