@@ -20,9 +20,10 @@
 // N1^2 lanes of one wave (64 / N1^2 cells per wave).  Between the three axes
 // the pencil values are transposed through the cell's LDS arrays; the lanes
 // of a cell belong to one wave, so only wave-level ordering is needed, never
-// a workgroup barrier.  Every array plane is padded by one entry.  The
-// geometry is evaluated one coordinate component at a time and u one DOF
-// component at a time, so a cell needs three stage arrays.
+// a workgroup barrier.  The arrays are laid out so that these transposes
+// hit distinct LDS banks (see idx).  The geometry is evaluated one
+// coordinate component at a time and u one DOF component at a time, so a
+// cell needs three stage arrays.
 //
 // Output layouts: cell-major [n_cells][n_comp][n_b] (default) or cell-minor
 // [n_comp][n_b][n_cells].
@@ -59,8 +60,10 @@ struct SF {
     static constexpr int CB = 4 * CW;    // cells per 256-thread workgroup
     static constexpr int NC = form_nc(FORM);
     static constexpr bool GRAD = FORM == FE_FORM_LAPLACE || FORM == FE_FORM_ELASTICITY;
-    static constexpr int ZS = NPL + 1;       // stride of the x2 planes (padded)
-    static constexpr int AS = N1 * ZS + 1;   // one stage array (entries, padded)
+    // stage-array layout (see idx): Q3 uses a dense XOR-swizzled 4x4x4 block;
+    // other orders pad the x2 planes and the array by one entry
+    static constexpr int ZS = NPL + 1;
+    static constexpr int AS = N1 == 4 ? NP : N1 * ZS + 1;
     // three arrays per cell (in double slots); the cell stride is an odd
     // multiple of 8 doubles (16 four-byte banks), so consecutive cells of a
     // wave start half a bank row apart
@@ -81,10 +84,20 @@ struct TabR {
     __device__ __forceinline__ V d(int i) const { return D[i]; }
 };
 
+// Position of (x0, x1, x2) in a stage array.  Every pass reads or writes
+// with one coordinate fixed and the lanes of a cell spread over the other
+// two.  For N1 = 4, (x0 ^ x2) + 4 (x1 ^ x2) + 16 x2 maps each of the three
+// patterns onto 16 distinct double slots modulo 16, i.e. onto all 32
+// four-byte LDS banks (16 lanes per pass for 8-byte accesses; two cells of
+// 4-byte entries at an offset of 16 banks for 4-byte accesses): no bank
+// conflicts.
 template <int N1, int ZS>
 __device__ __forceinline__ int idx(int x0, int x1, int x2)
 {
-    return x0 + N1 * x1 + ZS * x2;
+    if constexpr (N1 == 4)
+        return (x0 ^ x2) + 4 * (x1 ^ x2) + 16 * x2;
+    else
+        return x0 + N1 * x1 + ZS * x2;
 }
 
 // Three 1-D passes of one scalar field f given on the lane's axis-0 pencil
