@@ -60,14 +60,16 @@ struct SF {
     static constexpr int CB = 4 * CW;    // cells per 256-thread workgroup
     static constexpr int NC = form_nc(FORM);
     static constexpr bool GRAD = FORM == FE_FORM_LAPLACE || FORM == FE_FORM_ELASTICITY;
-    // stage-array layout (see idx): Q3 uses a dense XOR-swizzled 4x4x4 block;
-    // other orders pad the x2 planes and the array by one entry
-    static constexpr int ZS = NPL + 1;
-    static constexpr int AS = N1 == 4 ? NP : N1 * ZS + 1;
-    // three arrays per cell (in double slots); the cell stride is an odd
-    // multiple of 8 doubles (16 four-byte banks), so consecutive cells of a
-    // wave start half a bank row apart
-    static constexpr int CELL = ((3 * AS + 7) / 8 % 2 == 0 ? (3 * AS + 7) / 8 + 1 : (3 * AS + 7) / 8) * 8;
+    // stage-array layout (see idx).  Q3: a dense XOR-swizzled 4x4x4 block,
+    // no bank conflicts.  Q2: plane stride 20, array stride 49 and cell
+    // stride 153 doubles, the best of a search over strides for the bank
+    // conflicts of the nine transpose patterns (at most 2-way; 4-way with
+    // the plain padded layout).  Other orders: planes and arrays padded by
+    // one entry, the cell stride an odd multiple of 8 doubles.
+    static constexpr int ZS = N1 == 3 ? 20 : NPL + 1;
+    static constexpr int AS = N1 == 4 ? NP : (N1 == 3 ? 49 : N1 * ZS + 1);
+    static constexpr int CELL = N1 == 3 ? 153
+                                        : ((3 * AS + 7) / 8 % 2 == 0 ? (3 * AS + 7) / 8 + 1 : (3 * AS + 7) / 8) * 8;
 };
 
 // 1-D tables B[q][a], D[q][a]: FP64 through the scalar unit for the
