@@ -19,7 +19,10 @@ Other configurations of the same hot path (--config):
       40k Q2 hex, mass + Laplace + elasticity each, FP32; vs separate
       launches and vs untuned tiles;
   c5  energy J = sum u_e^T K_e u_e of Q2 elasticity on 32^3 cells with
-      per-point coefficients: forward + adjoint (dJ/dc, dJ/dx, dJ/du).
+      per-point coefficients: forward + adjoint (dJ/dc, dJ/dx, dJ/du);
+  c6  Q3 linear-elasticity element matrices (64 nodes, 192 DOFs, 4x4x4
+      Gauss), 32^3 cells, per-cell Lame coefficients, FP64 / FP32 / BF16X3:
+      the matrix-core-bound case, reported against the matrix-core peak.
 Every configuration prints one JSON line.
 """
 from __future__ import annotations
@@ -35,14 +38,20 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+# dense matrix-core peaks (TFLOP/s); BF16X3 does three bf16 products per
+# product of the contraction, so its contraction rate peaks at a third of bf16
+MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3}
 # HBM bytes per launch of a kernel, from two rocprofv3 --pmc passes
 # (FETCH_SIZE, WRITE_SIZE) scaled by what the same counters read for a 1 GiB
 # copy (fetch x2.0, write x1.0).  A figure holds only for the sources it was
 # measured on: when their hash differs the field is reported as null.
 MEASURED_TRAFFIC = {
-    "k_elast_q2<0>": dict(bytes=5981360949, sha256="25849177847381e8",
+    "k_elast_q2<0>": dict(bytes=5980620800, sha256="14f4c9ab9066dfda",
                           sources=["k_mfma.hip", "q2_device.h",
                                    "fe_device.h"]),
+    "k_elast_q3ws<0>": dict(bytes=9696710656, sha256="ef13c1bdbbb9c53e",
+                            sources=["k_hexmm.hip", "q2_device.h",
+                                     "fe_device.h"]),
     "k_cw_scalar<hex,1,laplace,double>@128^3": dict(
         bytes=1195318954, sha256="8f5712b5093a62b8",
         sources=["k_cellwise.hip", "cw_device.h", "fe_device.h"]),
@@ -72,7 +81,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c2",
-                    choices=["c1", "c2", "c3", "c4", "c5"])
+                    choices=["c1", "c2", "c3", "c4", "c5", "c6"])
     ap.add_argument("--n", type=int, default=0, help="cells per axis")
     ap.add_argument("--precision", default="fp64",
                     choices=["fp64", "fp32", "bf16x3"])
@@ -621,6 +630,90 @@ def run_c5(args, orc):
                       f"{tot:.1f} s"}
     return line
 
+# ------------------------------------------------------------------- c6 ---
+
+# matrix-core work per Q3 elasticity cell: the 78 upper 16x16 tiles of
+# P = g^T g (192 x 192, depth 64 points), 2 flops per multiply-add
+C6_MFMA_FLOPS = 78 * 16 * 16 * 64 * 2
+
+
+def run_c6(args, orc):
+    import torch
+    import meshgen
+    import paper_2107_04121_amd as fe
+    dev = torch.device("cuda:0")
+    n = args.n or 32
+    mesh = meshgen.hex_mesh(n, 3, alpha=0.15, seed=0)
+    lm = meshgen.lame_cell(mesh.n_cells, seed=0)
+    X = torch.from_numpy(mesh.coords).to(dev)
+    C = torch.from_numpy(mesh.conn).to(dev)
+    idx = sample_cells(mesh.n_cells, 24)
+    ref = orc.matrix(submesh(mesh, idx), "elasticity", lm[idx], "iso_cell")
+    results = {}
+    precs = [args.precision] + ([] if args.no_extra else
+                                [p for p in ("fp64", "fp32", "bf16x3")
+                                 if p != args.precision])
+    for prec in precs:
+        plan = fe.Plan("hex", 3, "elasticity", "matrix", prec,
+                       material="iso_cell", variant=args.variant)
+        M = torch.from_numpy(lm).to(dev).to(plan.dtype)
+        out = torch.empty(plan.out_shape(mesh.n_cells), dtype=plan.dtype,
+                          device=dev)
+        wall, per = time_calls(lambda: plan(X, C, material=M, out=out),
+                               args.steps, args.warmup)
+        plan.check()
+        ms = wall * 1e3 / args.steps
+        kern_ms = mean(per)
+        bpc = alg_bytes_per_cell(mesh, 192, out.element_size(),
+                                 M.element_size())
+        tflops = C6_MFMA_FLOPS * mesh.n_cells / (kern_ms * 1e-3) / 1e12
+        err = rel_err(out[torch.as_tensor(idx, device=dev)].cpu().numpy(),
+                      ref)
+        results[prec] = dict(ms_per_step=ms, kernel_ms=kern_ms,
+                             kernel_ms_min=float(min(per)),
+                             gelem_s=mesh.n_cells / (ms * 1e-3) / 1e9,
+                             mfma_tflops=tflops,
+                             mfma_frac=tflops / MFMA_PEAK_TFLOPS[prec],
+                             hbm_gbs=bpc * mesh.n_cells / (kern_ms * 1e-3)
+                             / 1e9,
+                             variant=plan.variant, max_rel_err=err)
+        del out
+        torch.cuda.empty_cache()
+    prim = results[args.precision]
+    line = base_line(args, prim["gelem_s"], prim["ms_per_step"],
+                     {"fp64": "f64", "fp32": "f32",
+                      "bf16x3": "bf16x3"}[args.precision],
+                     dict(workload="linear elasticity element matrices, Q3 "
+                          f"hex, {n}^3 cells, 4x4x4 Gauss",
+                          cells=mesh.n_cells, order=3, n_basis=64, n_qp=64,
+                          alpha=0.15, seed=0,
+                          material="per-cell lambda,mu lognormal(0,0.5)"))
+    line["max_rel_err_vs_fp64_oracle"] = prim["max_rel_err"]
+    line["roofline"] = {"bound": "mfma", "achieved": prim["mfma_tflops"],
+                        "peak": MFMA_PEAK_TFLOPS[args.precision],
+                        "unit": "TFLOP/s", "frac": prim["mfma_frac"],
+                        "traffic": (traffic("k_elast_q3ws<0>")
+                                    if args.precision == "fp64" else None),
+                        "kernel": "k_elast_q3ws",
+                        "kernel_ms": prim["kernel_ms"],
+                        "flops_per_cell": C6_MFMA_FLOPS,
+                        "hbm_frac": prim["hbm_gbs"] / HBM_PEAK_GBS}
+    line["precisions"] = results
+    if not args.no_cpu:
+        def call(k):
+            t = time.perf_counter()
+            orc.matrix(submesh(mesh, slice(0, k)), "elasticity", lm[:k],
+                       "iso_cell")
+            return time.perf_counter() - t
+        rate, k2, reps, tot = oracle_rate(call, mesh.n_cells,
+                                          args.cpu_seconds)
+        line["cpu_baseline"] = {
+            "value": rate / 1e9, "unit": "GElem/s",
+            "cores": orc.num_threads(), "kind": "oracle",
+            "sample": f"first {k2} cells of the {n}^3 Q3 mesh x {reps} "
+                      f"passes, FP64 element matrices, {tot:.1f} s"}
+    return line
+
 
 def main():
     args = parse()
@@ -633,7 +726,7 @@ def main():
     oracle.build()
     copy_calibration(args.copy_calibration)
     fn = {"c1": run_c1, "c2": run_c2, "c3": run_c3, "c4": run_c4,
-          "c5": run_c5}[args.config]
+          "c5": run_c5, "c6": run_c6}[args.config]
     line = fn(args, oracle)
     print(json.dumps(line))
     if "error" in line:
