@@ -268,6 +268,14 @@ def voigt_random_spd(shape, seed: int = 0) -> np.ndarray:
     return np.ascontiguousarray(D)
 
 
+def tensor_qp(n_cells: int, n_qp: int, seed: int = 0) -> np.ndarray:
+    """(n_cells, n_qp, 3, 3) float64 coefficients M of the weighted vector dot
+    product: I + 0.3 N with N ~ N(0, 1) entrywise (not symmetric)."""
+    _, m_rng, _ = streams(seed)
+    A = m_rng.standard_normal((n_cells, n_qp, 3, 3))
+    return np.ascontiguousarray(np.eye(3) + 0.3 * A)
+
+
 def dofs(n_nodes: int, n_comp: int, seed: int = 0) -> np.ndarray:
     """(n_nodes, n_comp) float64 DOF values ~ N(0, 1)."""
     _, _, d_rng = streams(seed)

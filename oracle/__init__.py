@@ -25,8 +25,10 @@ _SRC = os.path.join(_HERE, "fe_oracle.c")
 _LIB = os.path.join(_HERE, "liborc_fe.so")
 
 CELLS = {"hex": 0, "tet": 1}
-FORMS = {"mass": 0, "vmass": 1, "laplace": 2, "elasticity": 3}
-MATS = {None: 0, "none": 0, "iso_cell": 1, "iso_qp": 2, "voigt_qp": 3}
+FORMS = {"mass": 0, "vmass": 1, "laplace": 2, "elasticity": 3, "wdot": 4,
+         "convect": 5}
+MATS = {None: 0, "none": 0, "iso_cell": 1, "iso_qp": 2, "voigt_qp": 3,
+        "tensor_qp": 4}
 _ERR = {-1: "bad argument", -2: "non-positive Jacobian determinant",
         -3: "node index out of range"}
 
@@ -64,6 +66,8 @@ def lib():
         L.orc_gauss_jacobi01.argtypes = [i32, i32, dp, dp]
         L.orc_tables.argtypes = [i32, i32, dp, dp, dp, dp]
         L.orc_matrix.argtypes = [i32, i32, i32, i64, i64, dp, ip, i32, dp, dp]
+        L.orc_matrix_u.argtypes = [i32, i32, i32, i64, i64, dp, ip, i32, dp,
+                                   dp, dp]
         L.orc_residual.argtypes = [i32, i32, i32, i64, i64, dp, ip, i32, dp,
                                    dp, i32, dp]
         L.orc_energy.argtypes = [i32, i32, i32, i64, i64, dp, ip, i32, dp, dp,
@@ -102,7 +106,7 @@ def sizes(cell: str, order: int):
 
 
 def n_comp(form: str) -> int:
-    return 3 if form in ("vmass", "elasticity") else 1
+    return 1 if form in ("mass", "laplace") else 3
 
 
 def gauss_jacobi01(n: int, alpha: int = 0):
@@ -128,16 +132,20 @@ def _mesh_args(mesh):
     return coords, conn
 
 
-def matrix(mesh, form: str, material=None, mat_kind: str | None = None):
-    """Element matrices (n_cells, nc*nb, nc*nb), FP64."""
+def matrix(mesh, form: str, material=None, mat_kind: str | None = None,
+           u=None):
+    """Element matrices (n_cells, nc*nb, nc*nb), FP64.  For "convect" the
+    matrix is the derivative of the residual at the state u (n_nodes, 3)."""
     coords, conn = _mesh_args(mesh)
     nb = mesh.n_basis
     nd = n_comp(form) * nb
     out = np.empty((mesh.n_cells, nd, nd))
     mat = _f64(material)
-    _check(lib().orc_matrix(CELLS[mesh.cell], mesh.order, FORMS[form],
-                            mesh.n_cells, mesh.n_nodes, _dp(coords),
-                            _ip(conn), MATS[mat_kind], _dp(mat), _dp(out)))
+    U = None if u is None else _f64(np.asarray(u).reshape(mesh.n_nodes, 3))
+    _check(lib().orc_matrix_u(CELLS[mesh.cell], mesh.order, FORMS[form],
+                              mesh.n_cells, mesh.n_nodes, _dp(coords),
+                              _ip(conn), MATS[mat_kind], _dp(mat), _dp(U),
+                              _dp(out)))
     return out
 
 

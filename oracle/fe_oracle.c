@@ -10,8 +10,9 @@
  * Algorithm "feloopv" and the matrix loop of Algorithm "feloopm"): for every
  * cell, for every quadrature point, add  (quadrature weight * |J|) * integrand.
  * The integrands are the weak forms of the table of example weak forms
- * (vector dot product / mass, weak Laplacian, linear elasticity) written out
- * element by element, in FP64, with no blocking or reordering.
+ * (vector dot product / mass, weak Laplacian, linear elasticity, weighted
+ * vector dot product, Navier-Stokes convection) written out element by
+ * element, in FP64, with no blocking or reordering.
  *
  * Readings of the paper used here (the paper does not fix them):
  *   - reference hexahedron [0,1]^3; tensor Gauss-Legendre rule with p+1
@@ -43,11 +44,14 @@
 #define ORC_VMASS 1
 #define ORC_LAPLACE 2
 #define ORC_ELASTICITY 3
+#define ORC_WDOT 4
+#define ORC_CONVECT 5
 
 #define ORC_MAT_NONE 0
 #define ORC_MAT_ISO_CELL 1
 #define ORC_MAT_ISO_QP 2
 #define ORC_MAT_VOIGT_QP 3
+#define ORC_MAT_TENSOR_QP 4
 
 #define NB_MAX 216
 #define NQ_MAX 216
@@ -410,29 +414,62 @@ static double B_entry(int I, int r, int a, double (*G)[NB_MAX])
 
 static int n_comp_of(int form)
 {
-    return (form == ORC_VMASS || form == ORC_ELASTICITY) ? 3 : 1;
+    return (form == ORC_MASS || form == ORC_LAPLACE) ? 1 : 3;
 }
 
 static int check_common(int cell, int p, int form, int mat_kind)
 {
     int nb, nq;
     if (orc_sizes(cell, p, &nb, &nq)) return ERR_ARG;
-    if (form < ORC_MASS || form > ORC_ELASTICITY) return ERR_ARG;
+    if (form < ORC_MASS || form > ORC_CONVECT) return ERR_ARG;
     if (form == ORC_ELASTICITY && (mat_kind < ORC_MAT_ISO_CELL || mat_kind > ORC_MAT_VOIGT_QP))
         return ERR_ARG;
+    if (form == ORC_WDOT && mat_kind != ORC_MAT_TENSOR_QP) return ERR_ARG;
     return 0;
+}
+
+/* Weighted vector dot coefficient M_ij of cell e at quadrature point q
+ * ('ij,i,j': a 3 x 3 matrix per point, row-major). */
+static double wdot_M(const double *mat, int64_t e, int q, int nq, int i, int j)
+{
+    return mat[((size_t)e * nq + q) * 9 + i * 3 + j];
+}
+
+/* Values u_c(q) and physical gradients du_c/dx_j (q) of a vector field with
+ * element DOFs ue[c][b] (component-major). */
+static void field_at(const ref_t *r, int q, double (*G)[NB_MAX], const double *ue,
+                     double uq[3], double gu[3][3])
+{
+    const int nb = r->nb;
+    const double *phi = r->bf + (size_t)q * nb;
+    for (int c = 0; c < 3; c++) {
+        double v = 0.0;
+        for (int b = 0; b < nb; b++) v += phi[b] * ue[c * nb + b];
+        uq[c] = v;
+        for (int j = 0; j < 3; j++) {
+            double g = 0.0;
+            for (int b = 0; b < nb; b++) g += G[j][b] * ue[c * nb + b];
+            gu[c][j] = g;
+        }
+    }
 }
 
 /* ------------------------------------------------------------------------ */
 /* Matrix mode: element matrices (Algorithm "feloopm")                      */
 /* ------------------------------------------------------------------------ */
 
-/* out: (n_cells, nc*nb, nc*nb) row-major, rows/cols component-major. */
-int orc_matrix(int cell, int p, int form, int64_t n_cells, int64_t n_nodes,
-               const double *coords, const int32_t *conn, int mat_kind,
-               const double *mat, double *out)
+static int gather_dofs(const ref_t *r, int nc, int64_t e, const int32_t *conn,
+                       const double *U, double *ue);
+
+/* out: (n_cells, nc*nb, nc*nb) row-major, rows/cols component-major.
+ * U (n_nodes, 3): the state the Navier-Stokes convection matrix is the
+ * derivative at (eq. fe4); ignored by the linear forms. */
+int orc_matrix_u(int cell, int p, int form, int64_t n_cells, int64_t n_nodes,
+                 const double *coords, const int32_t *conn, int mat_kind,
+                 const double *mat, const double *U, double *out)
 {
     if (check_common(cell, p, form, mat_kind)) return ERR_ARG;
+    if (form == ORC_CONVECT && !U) return ERR_ARG;
     ref_t r;
     if (ref_init(&r, cell, p)) { ref_free(&r); return ERR_ARG; }
     const int nb = r.nb, nq = r.nq, nc = n_comp_of(form), nd = nc * nb;
@@ -441,9 +478,11 @@ int orc_matrix(int cell, int p, int form, int64_t n_cells, int64_t n_nodes,
     for (int64_t e = 0; e < n_cells; e++) {
         double x[NB_MAX][3];
         double G[3][NB_MAX];
+        double ue[3 * NB_MAX];
         double *M = out + (size_t)e * nd * nd;
         for (int k = 0; k < nd * nd; k++) M[k] = 0.0;
         int st = gather_coords(&r, e, n_nodes, coords, conn, x);
+        if (!st && form == ORC_CONVECT) gather_dofs(&r, 3, e, conn, U, ue);
         for (int q = 0; q < nq && !st; q++) {
             double wdet;
             st = geometry(&r, q, x, &wdet, G);
@@ -455,6 +494,29 @@ int orc_matrix(int cell, int p, int form, int64_t n_cells, int64_t n_nodes,
                     for (int a = 0; a < nb; a++)
                         for (int b = 0; b < nb; b++)
                             M[(c * nb + a) * nd + c * nb + b] += wdet * phi[a] * phi[b];
+            } else if (form == ORC_WDOT) {
+                /* int v_i M_ij u_j |J|: K[(i,a),(j,b)] = M_ij phi_a phi_b */
+                for (int i = 0; i < 3; i++)
+                    for (int j = 0; j < 3; j++) {
+                        const double m = wdot_M(mat, e, q, nq, i, j);
+                        for (int a = 0; a < nb; a++)
+                            for (int b = 0; b < nb; b++)
+                                M[(i * nb + a) * nd + j * nb + b] += wdet * m * phi[a] * phi[b];
+                    }
+            } else if (form == ORC_CONVECT) {
+                /* derivative of int v_i (du_i/dx_j) u_j |J| w.r.t. u (eq. fe4):
+                 * the two terms obtained by leaving out either u,
+                 * K[(i,a),(c,m)] = phi_a (delta_ic u_j dphi_m/dx_j + du_i/dx_c phi_m) */
+                double uq[3], gu[3][3];
+                field_at(&r, q, G, ue, uq, gu);
+                for (int i = 0; i < 3; i++)
+                    for (int a = 0; a < nb; a++)
+                        for (int c = 0; c < 3; c++)
+                            for (int m = 0; m < nb; m++) {
+                                double t = gu[i][c] * phi[m];
+                                if (i == c) t += uq[0] * G[0][m] + uq[1] * G[1][m] + uq[2] * G[2][m];
+                                M[(i * nb + a) * nd + c * nb + m] += wdet * phi[a] * t;
+                            }
             } else if (form == ORC_LAPLACE) {
                 /* int grad phi_a . grad phi_b |J|  ('cq,cqjd,cqje->cde') */
                 for (int a = 0; a < nb; a++)
@@ -495,6 +557,13 @@ int orc_matrix(int cell, int p, int form, int64_t n_cells, int64_t n_nodes,
     return status;
 }
 
+int orc_matrix(int cell, int p, int form, int64_t n_cells, int64_t n_nodes,
+               const double *coords, const int32_t *conn, int mat_kind,
+               const double *mat, double *out)
+{
+    return orc_matrix_u(cell, p, form, n_cells, n_nodes, coords, conn, mat_kind, mat, NULL, out);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Residual mode: action on gathered DOFs (Algorithm "feloopv")             */
 /* ------------------------------------------------------------------------ */
@@ -516,6 +585,33 @@ static int residual_qp(const ref_t *r, int form, int q, double wdet,
             for (int b = 0; b < nb; b++) uq += phi[b] * ue[c * nb + b];
             for (int a = 0; a < nb; a++) re[c * nb + a] += wdet * phi[a] * uq;
             *energy += wdet * uq * uq;
+        }
+        return 0;
+    }
+    if (form == ORC_WDOT) {
+        /* test side phi_a, flux M u(q) */
+        double uq[3];
+        for (int c = 0; c < 3; c++) {
+            double v = 0.0;
+            for (int b = 0; b < nb; b++) v += phi[b] * ue[c * nb + b];
+            uq[c] = v;
+        }
+        for (int i = 0; i < 3; i++) {
+            double f = 0.0;
+            for (int j = 0; j < 3; j++) f += wdot_M(mat, e, q, r->nq, i, j) * uq[j];
+            for (int a = 0; a < nb; a++) re[i * nb + a] += wdet * phi[a] * f;
+            *energy += wdet * uq[i] * f;
+        }
+        return 0;
+    }
+    if (form == ORC_CONVECT) {
+        /* test side phi_a, flux (u . grad) u_i at the point */
+        double uq[3], gu[3][3];
+        field_at(r, q, G, ue, uq, gu);
+        for (int i = 0; i < 3; i++) {
+            const double f = gu[i][0] * uq[0] + gu[i][1] * uq[1] + gu[i][2] * uq[2];
+            for (int a = 0; a < nb; a++) re[i * nb + a] += wdet * phi[a] * f;
+            *energy += wdet * uq[i] * f;
         }
         return 0;
     }
@@ -570,13 +666,15 @@ static int gather_dofs(const ref_t *r, int nc, int64_t e, const int32_t *conn,
 }
 
 /* path 0: gradient-first (quadrature-point values first);
- * path 1: matrix-first (element matrix, then its product with u_e).
+ * path 1: matrix-first (element matrix, then its product with u_e; linear
+ * forms only: the convection matrix is a derivative, K(u) u = 2 r(u)).
  * out: (n_cells, nc, nb). */
 int orc_residual(int cell, int p, int form, int64_t n_cells, int64_t n_nodes,
                  const double *coords, const int32_t *conn, int mat_kind,
                  const double *mat, const double *U, int path, double *out)
 {
     if (check_common(cell, p, form, mat_kind) || (path != 0 && path != 1)) return ERR_ARG;
+    if (form == ORC_CONVECT && path == 1) return ERR_ARG;
     ref_t r;
     if (ref_init(&r, cell, p)) { ref_free(&r); return ERR_ARG; }
     const int nb = r.nb, nq = r.nq, nc = n_comp_of(form), nd = nc * nb;
