@@ -67,12 +67,21 @@ typedef enum { FE_CELL_HEX = 0, FE_CELL_TET = 1 } fe_cell;
 /* Forms of the table of example weak forms.  MASS: scalar 'i,i' with one
  * component; VMASS: 'i,i' with three components (its matrix is D diagonal
  * blocks of the scalar one, eq. fe3c); LAPLACE: '0.i,0.i';
- * ELASTICITY: 'IK,s(i:j)->I,s(k:l)->K' with three components. */
+ * ELASTICITY: 'IK,s(i:j)->I,s(k:l)->K' with three components;
+ * WDOT: the weighted vector dot product 'ij,i,j' (int v_i M_ij u_j, M a
+ * 3 x 3 matrix per quadrature point, material kind TENSOR_QP);
+ * CONVECT: the Navier-Stokes convection 'i,i.j,j' (int v_i du_i/dx_j u_j,
+ * eq. fe2), non-linear: its residual is the action on the DOFs and its
+ * matrix the derivative with respect to u at the DOFs passed (eq. fe4),
+ *   K[(i,a),(c,m)] = int phi_a (delta_ic u . grad phi_m + du_i/dx_c phi_m),
+ * so K(u) u = 2 r(u). */
 typedef enum {
     FE_FORM_MASS = 0,
     FE_FORM_VMASS = 1,
     FE_FORM_LAPLACE = 2,
-    FE_FORM_ELASTICITY = 3
+    FE_FORM_ELASTICITY = 3,
+    FE_FORM_WDOT = 4,
+    FE_FORM_CONVECT = 5
 } fe_form;
 
 /* MATRIX: element matrices (Algorithm "feloopm").  RESIDUAL: per-element
@@ -89,15 +98,18 @@ typedef enum { FE_MODE_MATRIX = 0, FE_MODE_RESIDUAL = 1, FE_MODE_EVAL = 2 } fe_m
  *         kernels only). */
 typedef enum { FE_PREC_FP64 = 0, FE_PREC_FP32 = 1, FE_PREC_BF16X3 = 2 } fe_precision;
 
-/* Material data layout (elasticity only; NONE for mass and Laplace):
- * ISO_CELL [n_cells][2] (lambda, mu); ISO_QP [n_cells][n_qp][2];
+/* Material data layout (NONE for mass, Laplace and convection):
+ * elasticity: ISO_CELL [n_cells][2] (lambda, mu); ISO_QP [n_cells][n_qp][2];
  * VOIGT_QP [n_cells][n_qp][6][6] (the per-quadrature-point D of the paper's
- * elasticity einsum, 'cqIK').  FP64 in FP64 mode, FP32 otherwise. */
+ * elasticity einsum, 'cqIK');
+ * weighted dot product: TENSOR_QP [n_cells][n_qp][3][3] (M_ij, row-major).
+ * FP64 in FP64 mode, FP32 otherwise. */
 typedef enum {
     FE_MAT_NONE = 0,
     FE_MAT_ISO_CELL = 1,
     FE_MAT_ISO_QP = 2,
-    FE_MAT_VOIGT_QP = 3
+    FE_MAT_VOIGT_QP = 3,
+    FE_MAT_TENSOR_QP = 4
 } fe_material_kind;
 
 /* Kernel variant (0 = automatic choice). */
@@ -168,7 +180,8 @@ int fe_plan_workspace_size(fe_plan plan, int64_t n_cells, size_t *bytes);
  *   coords [n_nodes][3] FP64        node coordinates
  *   conn   [n_cells][n_basis] int32 local-to-global node numbers
  *   material                        layout by the plan's material kind, or NULL
- *   dofs   [n_nodes][n_comp]        RESIDUAL/EVAL only (NULL in MATRIX mode)
+ *   dofs   [n_nodes][n_comp]        RESIDUAL/EVAL, and MATRIX of CONVECT (the
+ *                                    state of the derivative); NULL otherwise
  *   out    MATRIX   [n_cells][n_dof][n_dof]
  *          RESIDUAL [n_cells][n_comp][n_basis]
  *          EVAL     [n_cells]

@@ -11,10 +11,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfe_forms.so")
 
 CELLS = {"hex": 0, "tet": 1}
-FORMS = {"mass": 0, "vmass": 1, "laplace": 2, "elasticity": 3}
+FORMS = {"mass": 0, "vmass": 1, "laplace": 2, "elasticity": 3, "wdot": 4,
+         "convect": 5}
 MODES = {"matrix": 0, "residual": 1, "eval": 2}
 PRECS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
-MATS = {None: 0, "none": 0, "iso_cell": 1, "iso_qp": 2, "voigt_qp": 3}
+MATS = {None: 0, "none": 0, "iso_cell": 1, "iso_qp": 2, "voigt_qp": 3,
+        "tensor_qp": 4}
 VARIANTS = {"auto": 0, "generic": 1, "mfma": 2, "sumfact": 3,
             "matrix_first": 4, "cellwise": 5}
 VARIANT_NAMES = {v: k for k, v in VARIANTS.items()}

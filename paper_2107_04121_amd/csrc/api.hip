@@ -17,7 +17,7 @@ static thread_local std::string g_last_error;
 
 void set_error(const std::string &msg) { g_last_error = msg; }
 
-int n_comp_of(int form) { return (form == FE_FORM_VMASS || form == FE_FORM_ELASTICITY) ? 3 : 1; }
+int n_comp_of(int form) { return (form == FE_FORM_MASS || form == FE_FORM_LAPLACE) ? 1 : 3; }
 
 size_t grad_part_bytes(const Plan &p, int64_t n_cells);
 int energy_grad_impl(const Plan &p, const fe_incidence_s *inc, const ExecArgs &A, double scale, void *gmat,
@@ -103,14 +103,17 @@ int fe_plan_create(int cell, int order, int form, int mode, int precision, int m
     if (!out) return fail(FE_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (cell != FE_CELL_HEX && cell != FE_CELL_TET) return fail(FE_ERR_INVALID_ARG, "bad cell");
-    if (form < FE_FORM_MASS || form > FE_FORM_ELASTICITY) return fail(FE_ERR_INVALID_ARG, "bad form");
+    if (form < FE_FORM_MASS || form > FE_FORM_CONVECT) return fail(FE_ERR_INVALID_ARG, "bad form");
     if (mode < FE_MODE_MATRIX || mode > FE_MODE_EVAL) return fail(FE_ERR_INVALID_ARG, "bad mode");
     if (precision < FE_PREC_FP64 || precision > FE_PREC_BF16X3) return fail(FE_ERR_INVALID_ARG, "bad precision");
     if (form == FE_FORM_ELASTICITY) {
         if (material_kind < FE_MAT_ISO_CELL || material_kind > FE_MAT_VOIGT_QP)
             return fail(FE_ERR_INVALID_ARG, "elasticity needs a material kind");
+    } else if (form == FE_FORM_WDOT) {
+        if (material_kind != FE_MAT_TENSOR_QP)
+            return fail(FE_ERR_INVALID_ARG, "the weighted dot product needs material kind TENSOR_QP");
     } else if (material_kind != FE_MAT_NONE) {
-        return fail(FE_ERR_INVALID_ARG, "only elasticity takes a material");
+        return fail(FE_ERR_INVALID_ARG, "only elasticity and the weighted dot product take a material");
     }
     int nb, nq;
     if (reference_sizes(cell, order, &nb, &nq)) return fail(FE_ERR_UNSUPPORTED, "unsupported cell/order");
@@ -152,6 +155,10 @@ int fe_plan_create(int cell, int order, int form, int mode, int precision, int m
         if (mode != FE_MODE_RESIDUAL || p->opts.layout != FE_LAYOUT_CELL_MAJOR) {
             delete p;
             return fail(FE_ERR_UNSUPPORTED, "matrix-first is a cell-major residual variant");
+        }
+        if (form == FE_FORM_CONVECT) {
+            delete p;
+            return fail(FE_ERR_UNSUPPORTED, "the convection matrix is a derivative: K(u) u = 2 r(u)");
         }
         Plan pm = *p;
         pm.mode = FE_MODE_MATRIX;
@@ -252,8 +259,10 @@ int fe_execute(fe_plan p, int64_t n_cells, int64_t n_nodes, const double *coords
     if (n_cells == 0) return FE_OK;
     if (n_nodes == 0) return fail(FE_ERR_INVALID_ARG, "cells without nodes");
     if (!coords || !conn || !out) return fail(FE_ERR_INVALID_ARG, "coords/conn/out is NULL");
-    if (p->form == FE_FORM_ELASTICITY && !material) return fail(FE_ERR_INVALID_ARG, "material is NULL");
-    if (p->mode != FE_MODE_MATRIX && !dofs) return fail(FE_ERR_INVALID_ARG, "dofs is NULL");
+    if ((p->form == FE_FORM_ELASTICITY || p->form == FE_FORM_WDOT) && !material)
+        return fail(FE_ERR_INVALID_ARG, "material is NULL");
+    if ((p->mode != FE_MODE_MATRIX || p->form == FE_FORM_CONVECT) && !dofs)
+        return fail(FE_ERR_INVALID_ARG, "dofs is NULL");
     size_t need;
     fe_plan_workspace_size(p, n_cells, &need);
     if (!workspace || workspace_bytes < need) return fail(FE_ERR_INVALID_ARG, "workspace too small");

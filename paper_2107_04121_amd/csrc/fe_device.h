@@ -12,7 +12,7 @@ namespace fe {
 constexpr int hex_nb(int p) { return (p + 1) * (p + 1) * (p + 1); }
 constexpr int cell_nb(int cell, int p) { return cell == FE_CELL_HEX ? hex_nb(p) : (p == 1 ? 4 : 10); }
 constexpr int cell_nq(int cell, int p) { return (p + 1) * (p + 1) * (p + 1); }
-constexpr int form_nc(int form) { return (form == FE_FORM_VMASS || form == FE_FORM_ELASTICITY) ? 3 : 1; }
+constexpr int form_nc(int form) { return (form == FE_FORM_MASS || form == FE_FORM_LAPLACE) ? 1 : 3; }
 
 // MI355X dispatches consecutive workgroups round-robin over its 8 XCDs, each
 // with a private L2.  Remapping the hardware block id so that every XCD works

@@ -12,6 +12,10 @@
 //   residual/eval -- gradient-first: values/gradients of u and the flux per
 //                    quadrature point, then one lane per (cell, row) contracts
 //                    with the test functions (Algorithm "feloopv").
+// The weighted vector dot product and the Navier-Stokes convection test with
+// basis values, like the mass forms; the convection matrix is the derivative
+// at the given DOFs (eq. fe4), so its matrix kernel also gathers u and keeps
+// u and grad u at every point in LDS.
 #include "fe_device.h"
 
 namespace fe {
@@ -35,15 +39,21 @@ struct Gen {
     static constexpr int NQ = cell_nq(CELL, P);
     static constexpr int NC = form_nc(FORM);
     static constexpr int ND = NC * NB;
-    static constexpr bool NEED_G = FORM == FE_FORM_LAPLACE || FORM == FE_FORM_ELASTICITY;
-    static constexpr int MATW = FORM == FE_FORM_ELASTICITY ? 36 : 0;
+    static constexpr bool NEED_G = FORM == FE_FORM_LAPLACE || FORM == FE_FORM_ELASTICITY || FORM == FE_FORM_CONVECT;
+    static constexpr int MATW = FORM == FE_FORM_ELASTICITY ? 36 : (FORM == FE_FORM_WDOT ? 9 : 0);
+    // forms whose test side is the basis value (flux width NC), not its gradient
+    static constexpr bool TESTVAL = FORM == FE_FORM_MASS || FORM == FE_FORM_VMASS || FORM == FE_FORM_WDOT ||
+                                    FORM == FE_FORM_CONVECT;
+    // convection matrix: u gathered per cell, u and grad u per point
+    static constexpr int UW = FORM == FE_FORM_CONVECT ? 12 : 0;
     static constexpr int CB = pick_cb(NB);
     static constexpr int NCH = ND / CB;
     // matrix kernel LDS per cell
     static constexpr int M_BYTES = NB * 3 * 8 + (NEED_G ? NQ * 3 * NB * (int)sizeof(T) : 0) +
-                                   NQ * (int)sizeof(T) + NQ * MATW * (int)sizeof(T);
+                                   NQ * (int)sizeof(T) + NQ * MATW * (int)sizeof(T) +
+                                   (UW ? (3 * NB + NQ * UW) * (int)sizeof(T) : 0);
     // residual kernel LDS per cell: coords, u, flux, energy, material
-    static constexpr int FW = (FORM == FE_FORM_MASS || FORM == FE_FORM_VMASS) ? NC : 3 * NC;
+    static constexpr int FW = TESTVAL ? NC : 3 * NC;
     static constexpr int R_BYTES = NB * 3 * 8 + NC * NB * (int)sizeof(T) + NQ * FW * (int)sizeof(T) +
                                    NQ * (int)sizeof(T) + NQ * MATW * (int)sizeof(T);
     static constexpr int work_m = (NQ > ND ? NQ : ND);
@@ -58,12 +68,16 @@ struct Gen {
     static constexpr int ER = choose(R_BYTES, (NQ > NB ? NQ : NB));
 };
 
-// Material coefficients of cell e at quadrature point q into LDS slot m[36]:
-// ISO kinds store (lambda, mu) in m[0], m[1]; VOIGT stores D row-major.
+// Material coefficients of cell e at quadrature point q into its LDS slot:
+// ISO kinds store (lambda, mu) in m[0], m[1]; VOIGT stores D row-major
+// (36); TENSOR stores the weighted dot product's M row-major (9).
 __device__ __forceinline__ void load_material(const ExecArgs &A, int64_t e, int q, int NQ, T *m)
 {
     const T *mat = static_cast<const T *>(A.mat);
-    if (A.mat_kind == FE_MAT_ISO_CELL) {
+    if (A.mat_kind == FE_MAT_TENSOR_QP) {
+        const T *d = mat + (e * NQ + q) * 9;
+        for (int k = 0; k < 9; k++) m[k] = d[k];
+    } else if (A.mat_kind == FE_MAT_ISO_CELL) {
         m[0] = mat[2 * e];
         m[1] = mat[2 * e + 1];
     } else if (A.mat_kind == FE_MAT_ISO_QP) {
@@ -97,6 +111,8 @@ __global__ __launch_bounds__(256) void k_matrix(ExecArgs A)
     T *Gs = reinterpret_cast<T *>(xs + E * NB * 3);
     T *wd = Gs + (C::NEED_G ? E * NQ * 3 * NB : 0);
     T *ms = wd + E * NQ;
+    T *ug = ms + E * NQ * C::MATW;  // CONVECT: u [E][3][NB], then u, grad u [E][NQ][12]
+    T *uh = ug + (C::UW ? E * 3 * NB : 0);
 
     const int64_t e0 = logical_block(A.xcd_remap) * E;
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -105,21 +121,31 @@ __global__ __launch_bounds__(256) void k_matrix(ExecArgs A)
         const int el = i / NB, a = i - el * NB;
         const int64_t e = e0 + el;
         double x0 = 0.0, x1 = 0.0, x2 = 0.0;
+        T u[3] = {T(0), T(0), T(0)};
         if (e < A.n_cells) {
             const int64_t n = checked_node(A.conn, e * NB + a, A.n_nodes, A.flags);
             x0 = A.coords[3 * n];
             x1 = A.coords[3 * n + 1];
             x2 = A.coords[3 * n + 2];
+            if constexpr (C::UW != 0) {
+                const T *U = static_cast<const T *>(A.dofs);
+#pragma unroll
+                for (int c = 0; c < 3; c++) u[c] = U[n * 3 + c];
+            }
         }
         xs[i * 3 + 0] = x0;
         xs[i * 3 + 1] = x1;
         xs[i * 3 + 2] = x2;
+        if constexpr (C::UW != 0) {
+#pragma unroll
+            for (int c = 0; c < 3; c++) ug[(el * 3 + c) * NB + a] = u[c];
+        }
     }
-    if constexpr (FORM == FE_FORM_ELASTICITY) {
+    if constexpr (C::MATW != 0) {
         for (int i = tid; i < E * NQ; i += nt) {
             const int el = i / NQ, q = i - el * NQ;
             const int64_t e = e0 + el;
-            if (e < A.n_cells) load_material(A, e, q, NQ, ms + i * 36);
+            if (e < A.n_cells) load_material(A, e, q, NQ, ms + i * C::MATW);
         }
     }
     __syncthreads();
@@ -141,6 +167,29 @@ __global__ __launch_bounds__(256) void k_matrix(ExecArgs A)
 #pragma unroll
                 for (int d = 0; d < 3; d++)
                     g[d * NB + a] = static_cast<T>(r0 * Ji[0][d] + r1 * Ji[1][d] + r2 * Ji[2][d]);
+            }
+            if constexpr (C::UW != 0) {
+                // u and grad u at the point (the state of the derivative)
+                const T *u = ug + el * 3 * NB;
+                T v[3] = {T(0), T(0), T(0)}, h[3][3] = {};
+                for (int b = 0; b < NB; b++) {
+                    const T ph = static_cast<T>(A.tab.bf[q * NB + b]);
+                    const T gb[3] = {g[b], g[NB + b], g[2 * NB + b]};
+#pragma unroll
+                    for (int c = 0; c < 3; c++) {
+                        const T uc = u[c * NB + b];
+                        v[c] += ph * uc;
+#pragma unroll
+                        for (int d = 0; d < 3; d++) h[c][d] += gb[d] * uc;
+                    }
+                }
+                T *o = uh + i * C::UW;
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    o[c] = v[c];
+#pragma unroll
+                    for (int d = 0; d < 3; d++) o[3 + c * 3 + d] = h[c][d];
+                }
             }
         }
     }
@@ -167,6 +216,23 @@ __global__ __launch_bounds__(256) void k_matrix(ExecArgs A)
                     const T wa = w * static_cast<T>(phi[a]);
 #pragma unroll
                     for (int c = 0; c < CB; c++) acc[c] += wa * static_cast<T>(phi[b0 + c]);
+                } else if constexpr (FORM == FE_FORM_WDOT) {
+                    // w M_rs phi_a phi_b
+                    const double *phi = A.tab.bf + q * NB;
+                    const T wa = w * ms[(el * NQ + q) * 9 + r * 3 + s] * static_cast<T>(phi[a]);
+#pragma unroll
+                    for (int c = 0; c < CB; c++) acc[c] += wa * static_cast<T>(phi[b0 + c]);
+                } else if constexpr (FORM == FE_FORM_CONVECT) {
+                    // w phi_a (delta_rs u . grad phi_b + du_r/dx_s phi_b)
+                    const double *phi = A.tab.bf + q * NB;
+                    const T *g = Gs + (el * NQ + q) * 3 * NB;
+                    const T *o = uh + (el * NQ + q) * C::UW;
+                    const T wa = w * static_cast<T>(phi[a]), hrs = o[3 + r * 3 + s];
+                    const T u0 = r == s ? o[0] : T(0), u1 = r == s ? o[1] : T(0), u2 = r == s ? o[2] : T(0);
+#pragma unroll
+                    for (int c = 0; c < CB; c++)
+                        acc[c] += wa * (hrs * static_cast<T>(phi[b0 + c]) + u0 * g[b0 + c] + u1 * g[NB + b0 + c] +
+                                        u2 * g[2 * NB + b0 + c]);
                 } else {
                     const T *g = Gs + (el * NQ + q) * 3 * NB;
                     const T ga[3] = {g[a], g[NB + a], g[2 * NB + a]};
@@ -225,12 +291,13 @@ __global__ __launch_bounds__(256) void k_residual(ExecArgs A)
     using C = Gen<CELL, P, FORM>;
     constexpr int NB = C::NB, NQ = C::NQ, NC = C::NC, E = C::ER, FW = C::FW;
     constexpr bool MASSLIKE = FORM == FE_FORM_MASS || FORM == FE_FORM_VMASS;
+    constexpr bool TESTVAL = C::TESTVAL;
     extern __shared__ __align__(16) unsigned char smem[];
     double *xs = reinterpret_cast<double *>(smem);
     T *us = reinterpret_cast<T *>(xs + E * NB * 3);  // [E][NC][NB]
     T *F = us + E * NC * NB;                           // [E][NQ][FW]
     T *en = F + E * NQ * FW;                           // [E][NQ]
-    T *ms = en + E * NQ;                               // [E][NQ][36]
+    T *ms = en + E * NQ;                               // [E][NQ][MATW]
 
     const int64_t e0 = logical_block(A.xcd_remap) * E;
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -257,11 +324,11 @@ __global__ __launch_bounds__(256) void k_residual(ExecArgs A)
 #pragma unroll
         for (int c = 0; c < NC; c++) us[(el * NC + c) * NB + a] = u[c];
     }
-    if constexpr (FORM == FE_FORM_ELASTICITY) {
+    if constexpr (C::MATW != 0) {
         for (int i = tid; i < E * NQ; i += nt) {
             const int el = i / NQ, q = i - el * NQ;
             const int64_t e = e0 + el;
-            if (e < A.n_cells) load_material(A, e, q, NQ, ms + i * 36);
+            if (e < A.n_cells) load_material(A, e, q, NQ, ms + i * C::MATW);
         }
     }
     __syncthreads();
@@ -284,6 +351,23 @@ __global__ __launch_bounds__(256) void k_residual(ExecArgs A)
                 for (int a = 0; a < NB; a++) v += static_cast<T>(A.tab.bf[q * NB + a]) * u[c * NB + a];
                 f[c] = w * v;
                 energy += w * v * v;
+            }
+            en[i] = energy;
+        } else if constexpr (FORM == FE_FORM_WDOT) {
+            // flux M u(q); energy u . M u
+            T v[3] = {T(0), T(0), T(0)};
+            for (int a = 0; a < NB; a++) {
+                const T ph = static_cast<T>(A.tab.bf[q * NB + a]);
+#pragma unroll
+                for (int c = 0; c < 3; c++) v[c] += ph * u[c * NB + a];
+            }
+            const T *m = ms + i * 9;
+            T energy = T(0);
+#pragma unroll
+            for (int r = 0; r < 3; r++) {
+                const T fr = m[r * 3] * v[0] + m[r * 3 + 1] * v[1] + m[r * 3 + 2] * v[2];
+                f[r] = w * fr;
+                energy += w * v[r] * fr;
             }
             en[i] = energy;
         } else {
@@ -315,7 +399,23 @@ __global__ __launch_bounds__(256) void k_residual(ExecArgs A)
                 for (int d = 0; d < 3; d++) H[c][d] = Hx[c][0] * Jt[0][d] + Hx[c][1] * Jt[1][d] + Hx[c][2] * Jt[2][d];
             T S[NC][3];  // physical flux
             T energy = T(0);
-            if constexpr (FORM == FE_FORM_LAPLACE) {
+            if constexpr (FORM == FE_FORM_CONVECT) {
+                // flux (u . grad) u at the point, tested with basis values
+                T v[3] = {T(0), T(0), T(0)};
+                for (int a = 0; a < NB; a++) {
+                    const T ph = static_cast<T>(A.tab.bf[q * NB + a]);
+#pragma unroll
+                    for (int c = 0; c < 3; c++) v[c] += ph * u[c * NB + a];
+                }
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    const T fc = H[c][0] * v[0] + H[c][1] * v[1] + H[c][2] * v[2];
+                    f[c] = w * fc;
+                    energy += w * v[c] * fc;
+                }
+                en[i] = energy;
+                continue;
+            } else if constexpr (FORM == FE_FORM_LAPLACE) {
 #pragma unroll
                 for (int d = 0; d < 3; d++) S[0][d] = H[0][d];
                 energy = w * (H[0][0] * H[0][0] + H[0][1] * H[0][1] + H[0][2] * H[0][2]);
@@ -382,7 +482,7 @@ __global__ __launch_bounds__(256) void k_residual(ExecArgs A)
         T acc = T(0);
         for (int q = 0; q < NQ; q++) {
             const T *f = F + (el * NQ + q) * FW;
-            if constexpr (MASSLIKE) {
+            if constexpr (TESTVAL) {
                 acc += static_cast<T>(A.tab.bf[q * NB + a]) * f[c];
             } else {
                 acc += static_cast<T>(A.tab.bfgT[(a * 3 + 0) * NQ + q]) * f[c * 3 + 0] +
@@ -435,6 +535,9 @@ LaunchFn pick_form(int form, int mode)
         return m ? launch_matrix<CELL, P, FE_FORM_LAPLACE> : launch_residual<CELL, P, FE_FORM_LAPLACE>;
     case FE_FORM_ELASTICITY:
         return m ? launch_matrix<CELL, P, FE_FORM_ELASTICITY> : launch_residual<CELL, P, FE_FORM_ELASTICITY>;
+    case FE_FORM_WDOT: return m ? launch_matrix<CELL, P, FE_FORM_WDOT> : launch_residual<CELL, P, FE_FORM_WDOT>;
+    case FE_FORM_CONVECT:
+        return m ? launch_matrix<CELL, P, FE_FORM_CONVECT> : launch_residual<CELL, P, FE_FORM_CONVECT>;
     }
     return nullptr;
 }

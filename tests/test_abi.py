@@ -77,6 +77,12 @@ def test_argument_validation_without_device(L):
                             ctypes.byref(h)) == 1   # laplace with material
     assert L.fe_plan_create(0, 9, 2, 0, 0, 0, ctypes.byref(opts),
                             ctypes.byref(h)) == 2   # unsupported order
+    assert L.fe_plan_create(0, 1, 4, 0, 0, 1, ctypes.byref(opts),
+                            ctypes.byref(h)) == 1   # weighted dot w/o TENSOR_QP
+    assert L.fe_plan_create(0, 1, 5, 0, 0, 4, ctypes.byref(opts),
+                            ctypes.byref(h)) == 1   # convection with material
+    assert L.fe_plan_create(0, 1, 6, 0, 0, 0, ctypes.byref(opts),
+                            ctypes.byref(h)) == 1   # no such form
     assert L.fe_execute(None, 1, 1, None, None, None, None, None, None, 0,
                         None) == 1
     assert L.fe_plan_destroy(None) == 0

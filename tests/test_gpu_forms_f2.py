@@ -1,0 +1,94 @@
+"""GPU parity of the weighted vector dot product ('ij,i,j', M, v, u) and the
+Navier-Stokes convection ('i,i.j,j', v, u, u) against the FP64 oracle, in
+matrix, residual and eval modes, through the C ABI, for every cell kind and
+order the generic kernels cover, on meshes that span several workgroups and
+end in a ragged tail.  The convection matrix is the derivative at the DOFs
+passed (eq. fe4).
+
+Gates: FP64 1e-12, FP32 1e-5 of each element's max-norm (eval: of the
+largest element value).
+"""
+import numpy as np
+import pytest
+
+import meshgen
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+CELLS = [("hex", 1, False), ("hex", 2, True), ("hex", 3, True), ("tet", 1, False), ("tet", 2, False)]
+
+
+def _t(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    return t if dtype is None else t.to(dtype)
+
+
+def _mesh(cell, p, curved):
+    if cell == "hex":
+        dims = {1: (7, 5, 3), 2: (5, 3, 3), 3: (3, 3, 2)}[p]
+        return meshgen.hex_mesh(dims, p, alpha=0.15, seed=40 + p, curved=0.04 if curved else 0.0)
+    return meshgen.tet_mesh((4, 3, 2), p, alpha=0.15, seed=40 + p)
+
+
+def _err(got, ref):
+    n = ref.shape[0]
+    g = np.asarray(got, dtype=np.float64).reshape(n, -1)
+    r = ref.reshape(n, -1)
+    return float((np.abs(g - r).max(1) / np.maximum(np.abs(r).max(1), 1e-300)).max())
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("form", ["wdot", "convect"])
+@pytest.mark.parametrize("cell,p,curved", CELLS)
+def test_forms_f2_parity(orc, cell, p, curved, form, prec):
+    import paper_2107_04121_amd as fe
+    mesh = _mesh(cell, p, curved)
+    nb, nq = orc.sizes(cell, p)
+    kind = "tensor_qp" if form == "wdot" else None
+    M = meshgen.tensor_qp(mesh.n_cells, nq, seed=41) if kind else None
+    U = meshgen.dofs(mesh.n_nodes, 3, seed=42)
+    X, C = _t(mesh.coords), _t(mesh.conn)
+    refs = {"matrix": orc.matrix(mesh, form, M, kind, u=U),
+            "residual": orc.residual(mesh, form, U, M, kind),
+            "eval": orc.energy(mesh, form, U, M, kind)}
+    for mode, ref in refs.items():
+        plan = fe.Plan(cell, p, form, mode, prec, material=kind)
+        print(f"[f2] {cell}{p} {form} {mode} {prec} variant={plan.variant} cells={mesh.n_cells}", flush=True)
+        dt = plan.dtype
+        out = plan(X, C, material=None if M is None else _t(M, dt), dofs=_t(U, dt))
+        plan.check()
+        got = out.cpu().numpy()
+        if mode == "eval":
+            err = float(np.abs(got - ref).max() / np.abs(ref).max())
+        else:
+            err = _err(got, ref)
+        assert err < TOL[prec], (mode, err)
+
+
+def test_convect_matrix_times_state_is_twice_residual():
+    """K(u) u = 2 r(u) between the GPU matrix and residual kernels (FP64)."""
+    import torch
+    import paper_2107_04121_amd as fe
+    mesh = _mesh("hex", 2, True)
+    U = meshgen.dofs(mesh.n_nodes, 3, seed=43)
+    X, C, Ud = _t(mesh.coords), _t(mesh.conn), _t(U)
+    K = fe.Plan("hex", 2, "convect", "matrix", "fp64")(X, C, dofs=Ud)
+    r = fe.Plan("hex", 2, "convect", "residual", "fp64")(X, C, dofs=Ud)
+    ue = Ud[C.long()].transpose(1, 2).reshape(mesh.n_cells, -1)
+    Ku = torch.bmm(K, ue.unsqueeze(2)).squeeze(2)
+    rr = r.reshape(mesh.n_cells, -1)
+    assert float(((Ku - 2 * rr).abs().amax(1) / rr.abs().amax(1)).max()) < 1e-12
+
+
+def test_f2_argument_rules():
+    import paper_2107_04121_amd as fe
+    with pytest.raises(fe.FeError):
+        fe.Plan("hex", 1, "convect", "residual", "fp64", variant="matrix_first")
+    with pytest.raises(fe.FeError):
+        fe.Plan("hex", 1, "wdot", "matrix", "fp64")              # no TENSOR_QP
+    mesh = _mesh("hex", 1, False)
+    plan = fe.Plan("hex", 1, "convect", "matrix", "fp64")
+    with pytest.raises(fe.FeError):
+        plan(_t(mesh.coords), _t(mesh.conn))                     # no state u
