@@ -22,7 +22,11 @@ Other configurations of the same hot path (--config):
       per-point coefficients: forward + adjoint (dJ/dc, dJ/dx, dJ/du);
   c6  Q3 linear-elasticity element matrices (64 nodes, 192 DOFs, 4x4x4
       Gauss), 32^3 cells, per-cell Lame coefficients, FP64 / FP32 / BF16X3:
-      the matrix-core-bound case, reported against the matrix-core peak.
+      the matrix-core-bound case, reported against the matrix-core peak;
+  c7  the paper's two other benchmark forms on Q2 hexahedra, 32^3 cells,
+      FP64 and FP32: weighted vector dot product (per-point 3x3 M) and
+      Navier-Stokes convection (matrix = derivative at u ~ N(0,1)), matrix
+      and residual modes.
 Every configuration prints one JSON line.
 """
 from __future__ import annotations
@@ -81,7 +85,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c2",
-                    choices=["c1", "c2", "c3", "c4", "c5", "c6"])
+                    choices=["c1", "c2", "c3", "c4", "c5", "c6", "c7"])
     ap.add_argument("--n", type=int, default=0, help="cells per axis")
     ap.add_argument("--precision", default="fp64",
                     choices=["fp64", "fp32", "bf16x3"])
@@ -715,6 +719,87 @@ def run_c6(args, orc):
     return line
 
 
+# ------------------------------------------------------------------- c7 ---
+
+def run_c7(args, orc):
+    import torch
+    import meshgen
+    import paper_2107_04121_amd as fe
+    dev = torch.device("cuda:0")
+    n = args.n or 32
+    mesh = meshgen.hex_mesh(n, 2, alpha=0.15, seed=0)
+    nb, nq = mesh.n_basis, 27
+    Mt = meshgen.tensor_qp(mesh.n_cells, nq, seed=0)
+    U = meshgen.dofs(mesh.n_nodes, 3, seed=0)
+    X = torch.from_numpy(mesh.coords).to(dev)
+    C = torch.from_numpy(mesh.conn).to(dev)
+    idx = sample_cells(mesh.n_cells, 24)
+    sub = submesh(mesh, idx)
+    paths = {}
+    for form in ("wdot", "convect"):
+        kind = "tensor_qp" if form == "wdot" else None
+        mat = Mt[idx] if kind else None
+        refs = {"matrix": orc.matrix(sub, form, mat, kind, u=U),
+                "residual": orc.residual(sub, form, U, mat, kind)}
+        for mode in ("matrix", "residual"):
+            for prec in ("fp64", "fp32"):
+                if args.no_extra and prec != "fp64":
+                    continue
+                plan = fe.Plan("hex", 2, form, mode, prec, material=kind)
+                dt = plan.dtype
+                Md = torch.from_numpy(Mt).to(dev).to(dt) if kind else None
+                Ud = torch.from_numpy(U).to(dev).to(dt)
+                out = torch.empty(plan.out_shape(mesh.n_cells), dtype=dt,
+                                  device=dev)
+                wall, per = time_calls(
+                    lambda: plan(X, C, material=Md, dofs=Ud, out=out),
+                    args.steps, args.warmup)
+                plan.check()
+                kms = mean(per)
+                esz = out.element_size()
+                nd = 3 * nb
+                outb = nd * nd * esz if mode == "matrix" else nd * esz
+                bpc = (outb + nb * 4 + mesh.n_nodes * (24 + 3 * esz)
+                       / mesh.n_cells + (nq * 9 * esz if kind else 0))
+                err = rel_err(out[torch.as_tensor(idx, device=dev)].cpu()
+                              .numpy(), refs[mode])
+                paths[f"{form}/{mode}/{prec}"] = dict(
+                    kernel_ms=kms, ms_per_step=wall * 1e3 / args.steps,
+                    gelem_s=mesh.n_cells / (kms * 1e-3) / 1e9,
+                    alg_bytes_per_cell=bpc,
+                    hbm_gbs=bpc * mesh.n_cells / (kms * 1e-3) / 1e9,
+                    variant=plan.variant, max_rel_err=err)
+                del out
+                torch.cuda.empty_cache()
+    prim = paths["convect/matrix/fp64"]
+    line = base_line(args, prim["gelem_s"], prim["ms_per_step"], "f64",
+                     dict(workload="weighted vector dot product and "
+                          "Navier-Stokes convection, Q2 hex, "
+                          f"{n}^3 cells, 3x3x3 Gauss, matrix and residual",
+                          cells=mesh.n_cells, order=2, alpha=0.15, seed=0))
+    line["max_rel_err_vs_fp64_oracle"] = prim["max_rel_err"]
+    line["roofline"] = {"bound": "hbm", "achieved": prim["hbm_gbs"],
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": prim["hbm_gbs"] / HBM_PEAK_GBS,
+                        "traffic": None,
+                        "kernel": "k_matrix<hex,2,convect> (generic)",
+                        "kernel_ms": prim["kernel_ms"]}
+    line["paths"] = paths
+    if not args.no_cpu:
+        def call(k):
+            t = time.perf_counter()
+            orc.matrix(submesh(mesh, slice(0, k)), "convect", u=U)
+            return time.perf_counter() - t
+        rate, k2, reps, tot = oracle_rate(call, mesh.n_cells,
+                                          args.cpu_seconds)
+        line["cpu_baseline"] = {
+            "value": rate / 1e9, "unit": "GElem/s",
+            "cores": orc.num_threads(), "kind": "oracle",
+            "sample": f"first {k2} cells of the {n}^3 Q2 mesh x {reps} "
+                      f"passes, FP64 convection matrices, {tot:.1f} s"}
+    return line
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -726,7 +811,7 @@ def main():
     oracle.build()
     copy_calibration(args.copy_calibration)
     fn = {"c1": run_c1, "c2": run_c2, "c3": run_c3, "c4": run_c4,
-          "c5": run_c5, "c6": run_c6}[args.config]
+          "c5": run_c5, "c6": run_c6, "c7": run_c7}[args.config]
     line = fn(args, oracle)
     print(json.dumps(line))
     if "error" in line:
