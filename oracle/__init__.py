@@ -197,3 +197,24 @@ def energy_grad(mesh, lam_mu_qp, u, want_mat=True, want_coords=True):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def assemble_matrix(mesh, cell_mats, n_comp: int):
+    """Global matrix (scipy CSR, FP64) of element matrices (n_cells, nc*nb,
+    nc*nb): every entry K_e[(c,a),(d,b)] added at global row
+    conn[e][a]*nc + c, column conn[e][b]*nc + d (the assembly that follows
+    the element loops; duplicates summed by scipy's COO-to-CSR
+    conversion)."""
+    import scipy.sparse as sp
+    nb, nc = mesh.n_basis, n_comp
+    K = np.asarray(cell_mats, dtype=np.float64).reshape(mesh.n_cells, nc, nb,
+                                                        nc, nb)
+    conn = np.asarray(mesh.conn, dtype=np.int64)
+    rows = (conn[:, None, :, None, None] * nc
+            + np.arange(nc)[None, :, None, None, None])
+    cols = (conn[:, None, None, None, :] * nc
+            + np.arange(nc)[None, None, None, :, None])
+    rows = np.broadcast_to(rows, K.shape).ravel()
+    cols = np.broadcast_to(cols, K.shape).ravel()
+    n = mesh.n_nodes * nc
+    return sp.coo_matrix((K.ravel(), (rows, cols)), shape=(n, n)).tocsr()
