@@ -225,6 +225,39 @@ int fe_incidence_destroy(fe_incidence inc);
 int fe_assemble(fe_incidence inc, int n_comp, int precision, const void *cell_vec, double scale,
                 void *out, void *stream);
 
+/* Sparsity pattern of the global matrix of a connectivity (the matrix
+ * assembly that follows the element loops): row node n couples to every node
+ * m that shares a cell with n.  CSR over nodes with sorted column node
+ * numbers, built on the current device from the cells' (n, m) node pairs by
+ * a radix sort.
+ *   conn [n_cells][n_basis] int32, device, entries in [0, n_nodes)
+ *   (FE_ERR_INDEX_OUT_OF_RANGE otherwise); n_cells * n_basis^2 pairs and the
+ *   number of distinct pairs must stay below 2^31 (FE_ERR_INVALID_ARG).
+ * Synchronises `stream`; the handle owns its device arrays. */
+typedef struct fe_pattern_s *fe_pattern;
+int fe_pattern_create(int64_t n_cells, int64_t n_nodes, int n_basis, const int32_t *conn, void *stream,
+                      fe_pattern *out);
+/* n_nodes and the number of stored node pairs nnz; either may be NULL. */
+int fe_pattern_info(fe_pattern pat, int64_t *n_nodes, int64_t *nnz);
+/* Copy the pattern into caller-owned device arrays row_ptr [n_nodes + 1] and
+ * cols [nnz] (int32).  Asynchronous on `stream`. */
+int fe_pattern_copy(fe_pattern pat, int32_t *row_ptr, int32_t *cols, void *stream);
+int fe_pattern_destroy(fe_pattern pat);
+
+/* Assembly of element matrices into the block-CSR global matrix of a pattern
+ * (blocks n_comp x n_comp, global unknown (n, c) = node n, component c, as
+ * the DOF array [n_nodes][n_comp]):
+ *   values[k][c][d] = scale * sum over (e, a, b) with conn[e][a] = n,
+ *                     conn[e][b] = m of K_e[c*n_basis + a][d*n_basis + b]
+ * for the pattern entry k of (n, m).  cell_mats [n_cells][n_comp n_basis]^2
+ * (component-major rows, the layout of the matrix mode) and values [nnz]
+ * [n_comp][n_comp] are device arrays, FP64 when precision == FE_PREC_FP64,
+ * FP32 otherwise; values is overwritten.  inc must be the incidence of the
+ * same connectivity.  One thread sums each row node over its incidence list
+ * in order, so results are bitwise repeatable.  Asynchronous. */
+int fe_assemble_matrix(fe_pattern pat, fe_incidence inc, const int32_t *conn, int n_comp, int precision,
+                       const void *cell_mats, double scale, void *values, void *stream);
+
 /* Gradient of the eval-mode value of linear elasticity,
  *   J(c, x) = sum_e u_e^T K_e(c, x) u_e
  * (eval mode of the elasticity form; the derivative rules below follow from

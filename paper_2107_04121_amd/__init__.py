@@ -18,7 +18,8 @@ import numpy as np
 from . import _lib
 from ._lib import FeError
 
-__all__ = ["Plan", "FeError", "Incidence", "assemble", "reference_sizes",
+__all__ = ["Plan", "FeError", "Incidence", "assemble", "Pattern",
+           "assemble_matrix", "reference_sizes",
            "reference_tables", "n_comp", "ElasticEnergy", "Batch"]
 
 _TORCH_DT = {"fp64": "float64", "fp32": "float32", "bf16x3": "float32"}
@@ -220,6 +221,70 @@ def assemble(inc: Incidence, cell_vec, scale: float = 1.0, out=None,
     _lib.check(_lib.lib().fe_assemble(inc._h, nc, prec, _ptr(cell_vec),
                                       float(scale), _ptr(out),
                                       _stream_handle(stream)), "fe_assemble")
+    return out
+
+
+class Pattern:
+    """Sparsity pattern of the global matrix of a connectivity: CSR over
+    nodes (row node n couples to every node sharing a cell with n), built on
+    the device; row_ptr (n_nodes + 1) and cols (nnz) as int32 cuda
+    tensors."""
+
+    def __init__(self, conn, n_nodes: int, stream=None):
+        import torch
+        if conn.dtype != torch.int32 or not conn.is_cuda or \
+                not conn.is_contiguous():
+            raise ValueError("conn must be a contiguous int32 cuda tensor")
+        self.n_cells, self.n_basis = conn.shape
+        self.n_nodes = int(n_nodes)
+        h = ctypes.c_void_p()
+        L = _lib.lib()
+        _lib.check(L.fe_pattern_create(
+            self.n_cells, self.n_nodes, self.n_basis, _ptr(conn),
+            _stream_handle(stream), ctypes.byref(h)), "fe_pattern_create")
+        self._h = h
+        nn, nnz = ctypes.c_int64(), ctypes.c_int64()
+        _lib.check(L.fe_pattern_info(h, ctypes.byref(nn), ctypes.byref(nnz)),
+                   "fe_pattern_info")
+        self.nnz = nnz.value
+        self.row_ptr = torch.empty(self.n_nodes + 1, dtype=torch.int32,
+                                   device=conn.device)
+        self.cols = torch.empty(max(self.nnz, 1), dtype=torch.int32,
+                                device=conn.device)[:self.nnz]
+        _lib.check(L.fe_pattern_copy(h, _ptr(self.row_ptr), _ptr(self.cols),
+                                     _stream_handle(stream)),
+                   "fe_pattern_copy")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        lib = getattr(_lib, "_lib", None) if _lib is not None else None
+        if h is not None and h.value and lib is not None:
+            lib.fe_pattern_destroy(h)
+            self._h = None
+
+
+def assemble_matrix(pattern: Pattern, inc: Incidence, conn, cell_mats,
+                    scale: float = 1.0, out=None, stream=None):
+    """Sum element matrices (n_cells, n_comp n_basis, n_comp n_basis) into
+    the block-CSR global matrix of the pattern: values (nnz, n_comp,
+    n_comp), block k of row node n holding the coupling to node cols[k]."""
+    import torch
+    n_cells, nd, nd2 = cell_mats.shape
+    nc = nd // pattern.n_basis
+    if nd != nd2 or nc * pattern.n_basis != nd or nc not in (1, 3) or \
+            n_cells != pattern.n_cells:
+        raise ValueError("cell_mats does not match the pattern")
+    if not cell_mats.is_contiguous():
+        raise ValueError("cell_mats must be contiguous")
+    prec = {torch.float64: 0, torch.float32: 1}[cell_mats.dtype]
+    if out is None:
+        out = torch.empty((max(pattern.nnz, 1), nc, nc),
+                          dtype=cell_mats.dtype,
+                          device=cell_mats.device)[:pattern.nnz]
+    _lib.check(_lib.lib().fe_assemble_matrix(
+        pattern._h, inc._h, _ptr(conn), nc, prec, _ptr(cell_mats),
+        float(scale), _ptr(out), _stream_handle(stream)),
+        "fe_assemble_matrix")
     return out
 
 

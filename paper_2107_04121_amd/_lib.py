@@ -31,7 +31,9 @@ EXPORTS = ["fe_status_string", "fe_last_error", "fe_version",
            "fe_reference_sizes", "fe_reference_tables", "fe_plan_create",
            "fe_plan_info", "fe_plan_workspace_size", "fe_execute",
            "fe_plan_check", "fe_plan_destroy", "fe_incidence_create",
-           "fe_incidence_destroy", "fe_assemble",
+           "fe_incidence_destroy", "fe_assemble", "fe_pattern_create",
+           "fe_pattern_info", "fe_pattern_copy", "fe_pattern_destroy",
+           "fe_assemble_matrix",
            "fe_energy_grad_workspace_size", "fe_energy_grad",
            "fe_batch_create", "fe_batch_execute", "fe_batch_check",
            "fe_batch_tiles", "fe_batch_destroy"]
@@ -106,6 +108,11 @@ def lib():
                                       ctypes.POINTER(vp)]
     L.fe_incidence_destroy.argtypes = [vp]
     L.fe_assemble.argtypes = [vp, i32, i32, vp, dbl, vp, vp]
+    L.fe_pattern_create.argtypes = [i64, i64, i32, vp, vp, ctypes.POINTER(vp)]
+    L.fe_pattern_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.fe_pattern_copy.argtypes = [vp, vp, vp, vp]
+    L.fe_pattern_destroy.argtypes = [vp]
+    L.fe_assemble_matrix.argtypes = [vp, vp, vp, i32, i32, vp, dbl, vp, vp]
     L.fe_energy_grad_workspace_size.argtypes = [vp, i64, ctypes.POINTER(sz)]
     L.fe_energy_grad.argtypes = [vp, vp, i64, i64, vp, vp, vp, vp, dbl, vp,
                                  vp, vp, sz, vp]

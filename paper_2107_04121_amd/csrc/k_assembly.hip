@@ -1,0 +1,298 @@
+// Global matrix assembly: the sparsity pattern of a connectivity and the
+// block-CSR sum of element matrices (the assembly that follows the paper's
+// element loops, which return per-cell matrices).
+//
+// Pattern: every cell contributes the node pairs (conn[e][a], conn[e][b]);
+// the pairs are encoded as 64-bit keys n * n_nodes + m, radix-sorted and
+// made unique on the device, so each row's column nodes come out sorted and
+// the rows contiguous.
+//
+// Values: one thread per row node n walks the node's incidence list (cells
+// and local numbers, sorted) and, for every local node b of each incident
+// cell, adds the n_comp x n_comp block K_e[(., a), (., b)] into the slot of
+// conn[e][b] found by binary search in the row.  A row is written by its own
+// thread only, in a fixed order: no atomics, bitwise repeatable.
+#include <hipcub/hipcub.hpp>
+
+#include "fe_device.h"
+
+struct fe_pattern_s {
+    int64_t n_nodes = 0, nnz = 0;
+    int nb = 0, device = -1;
+    int32_t *row_ptr = nullptr;  // [n_nodes + 1]
+    int32_t *cols = nullptr;     // [nnz]
+};
+
+namespace fe {
+namespace {
+
+__global__ void k_pair_keys(const int32_t *conn, int64_t n_cells, int nb, int64_t n_nodes, uint64_t *keys,
+                            unsigned *flags)
+{
+    const int64_t nb2 = (int64_t)nb * nb;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_cells * nb2) return;
+    const int64_t e = i / nb2;
+    const int ab = static_cast<int>(i - e * nb2), a = ab / nb, b = ab - a * nb;
+    int64_t n = conn[e * nb + a], m = conn[e * nb + b];
+    if (n < 0 || n >= n_nodes || m < 0 || m >= n_nodes) {
+        raise_fault(flags, FAULT_INDEX);
+        n = m = 0;
+    }
+    keys[i] = static_cast<uint64_t>(n) * static_cast<uint64_t>(n_nodes) + static_cast<uint64_t>(m);
+}
+
+__global__ void k_pair_split(const uint64_t *keys, int64_t nnz, int64_t n_nodes, int32_t *cnt, int32_t *cols)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nnz) return;
+    const uint64_t k = keys[i];
+    const int64_t row = static_cast<int64_t>(k / static_cast<uint64_t>(n_nodes));
+    cols[i] = static_cast<int32_t>(k - static_cast<uint64_t>(row) * static_cast<uint64_t>(n_nodes));
+    atomicAdd(&cnt[row], 1);  // integer counts: the result does not depend on the order
+}
+
+template <typename T, int NC>
+__global__ void k_asm_matrix(const int32_t *row_ptr, const int32_t *cols, const int32_t *inc_off,
+                             const int32_t *inc_items, const int32_t *conn, int64_t n_nodes, int nb, const T *K,
+                             double scale, T *values)
+{
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= n_nodes) return;
+    constexpr int B = NC * NC;
+    const int r0 = row_ptr[n], r1 = row_ptr[n + 1];
+    for (int64_t k = (int64_t)r0 * B; k < (int64_t)r1 * B; k++) values[k] = T(0);
+    const int nd = NC * nb;
+    const T s = static_cast<T>(scale);
+    for (int it = inc_off[n]; it < inc_off[n + 1]; it++) {
+        const int32_t item = inc_items[it];
+        const int64_t e = item / nb;
+        const int a = item - static_cast<int>(e) * nb;
+        const T *Ke = K + e * (int64_t)nd * nd;
+        for (int b = 0; b < nb; b++) {
+            const int32_t m = conn[e * nb + b];
+            int lo = r0, hi = r1 - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (cols[mid] < m) lo = mid + 1;
+                else hi = mid;
+            }
+            T *v = values + (int64_t)lo * B;
+#pragma unroll
+            for (int c = 0; c < NC; c++)
+#pragma unroll
+                for (int d = 0; d < NC; d++) v[c * NC + d] += s * Ke[(c * nb + a) * nd + d * nb + b];
+        }
+    }
+}
+
+int bits_for(uint64_t x)
+{
+    int b = 1;
+    while (b < 64 && (x >> b) != 0) b++;
+    return b;
+}
+
+}  // namespace
+}  // namespace fe
+
+using namespace fe;
+
+extern "C" {
+
+int fe_pattern_create(int64_t n_cells, int64_t n_nodes, int n_basis, const int32_t *conn, void *stream,
+                      fe_pattern *out)
+{
+    if (!out) {
+        set_error("out is NULL");
+        return FE_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    if (n_cells < 0 || n_nodes <= 0 || n_basis <= 0 || (n_cells > 0 && !conn)) {
+        set_error("bad pattern arguments");
+        return FE_ERR_INVALID_ARG;
+    }
+    const int64_t n_pairs = n_cells * (int64_t)n_basis * n_basis;
+    if (n_pairs >= 0x7fffffffLL || n_nodes >= 0x7fffffffLL) {
+        set_error("too many node pairs for one pattern (n_cells * n_basis^2 must stay below 2^31)");
+        return FE_ERR_INVALID_ARG;
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) {
+        (void)hipGetLastError();
+        set_error("no HIP device");
+        return FE_ERR_NO_DEVICE;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    fe_pattern_s *p = new (std::nothrow) fe_pattern_s();
+    if (!p) {
+        set_error("host allocation failed");
+        return FE_ERR_OUT_OF_MEMORY;
+    }
+    p->n_nodes = n_nodes;
+    p->nb = n_basis;
+    p->device = dev;
+    uint64_t *k0 = nullptr, *k1 = nullptr;
+    int32_t *cnt = nullptr, *nsel = nullptr;
+    unsigned *flags = nullptr;
+    void *tmp = nullptr;
+    auto cleanup = [&]() {
+        for (void *q : {(void *)k0, (void *)k1, (void *)cnt, (void *)nsel, (void *)flags, tmp})
+            if (q) (void)hipFree(q);
+    };
+    auto fail_hip = [&](const char *what) {
+        (void)hipGetLastError();
+        cleanup();
+        fe_pattern_destroy(p);
+        set_error(what);
+        return FE_ERR_HIP;
+    };
+    const int64_t np = n_pairs > 0 ? n_pairs : 1;
+    if (hipMalloc(&k0, np * sizeof(uint64_t)) != hipSuccess || hipMalloc(&k1, np * sizeof(uint64_t)) != hipSuccess ||
+        hipMalloc(&cnt, (n_nodes + 1) * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&nsel, sizeof(int32_t)) != hipSuccess || hipMalloc(&flags, sizeof(unsigned)) != hipSuccess ||
+        hipMalloc(&p->row_ptr, (n_nodes + 1) * sizeof(int32_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        cleanup();
+        fe_pattern_destroy(p);
+        set_error("pattern allocation failed");
+        return FE_ERR_OUT_OF_MEMORY;
+    }
+    if (hipMemsetAsync(cnt, 0, (n_nodes + 1) * sizeof(int32_t), st) != hipSuccess ||
+        hipMemsetAsync(flags, 0, sizeof(unsigned), st) != hipSuccess ||
+        hipMemsetAsync(nsel, 0, sizeof(int32_t), st) != hipSuccess)
+        return fail_hip("hipMemsetAsync failed");
+    const int items = static_cast<int>(n_pairs);
+    if (items > 0) {
+        hipLaunchKernelGGL(k_pair_keys, dim3((unsigned)((n_pairs + 255) / 256)), dim3(256), 0, st, conn, n_cells,
+                           n_basis, n_nodes, k0, flags);
+        const int end_bit = bits_for(static_cast<uint64_t>(n_nodes) * static_cast<uint64_t>(n_nodes));
+        size_t b_sort = 0, b_uniq = 0;
+        if (hipcub::DeviceRadixSort::SortKeys(nullptr, b_sort, k0, k1, items, 0, end_bit, st) != hipSuccess ||
+            hipcub::DeviceSelect::Unique(nullptr, b_uniq, k1, k0, nsel, items, st) != hipSuccess)
+            return fail_hip("radix sort sizing failed");
+        const size_t b_tmp = b_sort > b_uniq ? b_sort : b_uniq;
+        if (hipMalloc(&tmp, b_tmp ? b_tmp : 1) != hipSuccess) return fail_hip("temporary allocation failed");
+        size_t bs = b_tmp;
+        if (hipcub::DeviceRadixSort::SortKeys(tmp, bs, k0, k1, items, 0, end_bit, st) != hipSuccess)
+            return fail_hip("radix sort failed");
+        bs = b_tmp;
+        if (hipcub::DeviceSelect::Unique(tmp, bs, k1, k0, nsel, items, st) != hipSuccess)
+            return fail_hip("unique failed");
+    }
+    int32_t h_nsel = 0;
+    unsigned h_flags = 0;
+    if (hipMemcpyAsync(&h_nsel, nsel, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(&h_flags, flags, sizeof(unsigned), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return fail_hip("pattern size read failed");
+    if (h_flags & FAULT_INDEX) {
+        cleanup();
+        fe_pattern_destroy(p);
+        set_error("a connectivity entry is out of range");
+        return FE_ERR_INDEX_OUT_OF_RANGE;
+    }
+    p->nnz = h_nsel;
+    if (hipMalloc(&p->cols, (p->nnz > 0 ? p->nnz : 1) * sizeof(int32_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        cleanup();
+        fe_pattern_destroy(p);
+        set_error("pattern allocation failed");
+        return FE_ERR_OUT_OF_MEMORY;
+    }
+    if (p->nnz > 0)
+        hipLaunchKernelGGL(k_pair_split, dim3((unsigned)((p->nnz + 255) / 256)), dim3(256), 0, st, k0, p->nnz, n_nodes,
+                           cnt, p->cols);
+    size_t b_scan = 0;
+    if (hipcub::DeviceScan::ExclusiveSum(nullptr, b_scan, cnt, p->row_ptr, (int)(n_nodes + 1), st) != hipSuccess)
+        return fail_hip("prefix sum sizing failed");
+    if (tmp) (void)hipFree(tmp);
+    tmp = nullptr;
+    if (hipMalloc(&tmp, b_scan ? b_scan : 1) != hipSuccess) return fail_hip("temporary allocation failed");
+    if (hipcub::DeviceScan::ExclusiveSum(tmp, b_scan, cnt, p->row_ptr, (int)(n_nodes + 1), st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return fail_hip("prefix sum failed");
+    cleanup();
+    *out = p;
+    return FE_OK;
+}
+
+int fe_pattern_info(fe_pattern p, int64_t *n_nodes, int64_t *nnz)
+{
+    if (!p) {
+        set_error("pattern is NULL");
+        return FE_ERR_INVALID_ARG;
+    }
+    if (n_nodes) *n_nodes = p->n_nodes;
+    if (nnz) *nnz = p->nnz;
+    return FE_OK;
+}
+
+int fe_pattern_copy(fe_pattern p, int32_t *row_ptr, int32_t *cols, void *stream)
+{
+    if (!p || (!row_ptr && !cols)) {
+        set_error("bad argument");
+        return FE_ERR_INVALID_ARG;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (row_ptr)
+        FE_HIP_CHECK(hipMemcpyAsync(row_ptr, p->row_ptr, (p->n_nodes + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    if (cols && p->nnz > 0)
+        FE_HIP_CHECK(hipMemcpyAsync(cols, p->cols, p->nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    return FE_OK;
+}
+
+int fe_pattern_destroy(fe_pattern p)
+{
+    if (!p) return FE_OK;
+    if (p->row_ptr) (void)hipFree(p->row_ptr);
+    if (p->cols) (void)hipFree(p->cols);
+    delete p;
+    return FE_OK;
+}
+
+int fe_assemble_matrix(fe_pattern pat, fe_incidence inc, const int32_t *conn, int n_comp, int precision,
+                       const void *cell_mats, double scale, void *values, void *stream)
+{
+    if (!pat || !inc || !conn || !cell_mats || !values || (n_comp != 1 && n_comp != 3) ||
+        precision < FE_PREC_FP64 || precision > FE_PREC_BF16X3) {
+        set_error("bad matrix assembly arguments");
+        return FE_ERR_INVALID_ARG;
+    }
+    if (inc->n_nodes != pat->n_nodes || inc->nb != pat->nb) {
+        set_error("incidence and pattern belong to different connectivities");
+        return FE_ERR_INVALID_ARG;
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != pat->device || dev != inc->device) {
+        set_error("pattern or incidence was created on another device");
+        return FE_ERR_INVALID_ARG;
+    }
+    if (pat->n_nodes == 0 || inc->n_cells == 0) return FE_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const dim3 grid((unsigned)((pat->n_nodes + 127) / 128)), block(128);
+    const int nb = pat->nb;
+    if (precision == FE_PREC_FP64) {
+        if (n_comp == 1)
+            hipLaunchKernelGGL((k_asm_matrix<double, 1>), grid, block, 0, st, pat->row_ptr, pat->cols, inc->offsets,
+                               inc->items, conn, pat->n_nodes, nb, static_cast<const double *>(cell_mats), scale,
+                               static_cast<double *>(values));
+        else
+            hipLaunchKernelGGL((k_asm_matrix<double, 3>), grid, block, 0, st, pat->row_ptr, pat->cols, inc->offsets,
+                               inc->items, conn, pat->n_nodes, nb, static_cast<const double *>(cell_mats), scale,
+                               static_cast<double *>(values));
+    } else {
+        if (n_comp == 1)
+            hipLaunchKernelGGL((k_asm_matrix<float, 1>), grid, block, 0, st, pat->row_ptr, pat->cols, inc->offsets,
+                               inc->items, conn, pat->n_nodes, nb, static_cast<const float *>(cell_mats), scale,
+                               static_cast<float *>(values));
+        else
+            hipLaunchKernelGGL((k_asm_matrix<float, 3>), grid, block, 0, st, pat->row_ptr, pat->cols, inc->offsets,
+                               inc->items, conn, pat->n_nodes, nb, static_cast<const float *>(cell_mats), scale,
+                               static_cast<float *>(values));
+    }
+    FE_HIP_CHECK(hipGetLastError());
+    return FE_OK;
+}
+
+}  // extern "C"

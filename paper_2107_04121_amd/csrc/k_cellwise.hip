@@ -48,7 +48,7 @@ struct CwScalar {
 };
 
 template <int CELL, int P, int FORM, typename T>
-__global__ __launch_bounds__(64) void k_cw_scalar(ExecArgs A)
+__global__ __launch_bounds__(64, CELL == FE_CELL_HEX && sizeof(T) == 4 ? 4 : 1) void k_cw_scalar(ExecArgs A)
 {
     using C = CwScalar<CELL, P, FORM, T>;
     constexpr int NB = C::NB, NQ = C::NQ, NP = C::NP, ND = C::ND, RC = C::RC, SS = C::SS;
