@@ -266,6 +266,8 @@ def run_c2(args, orc):
                         "kernel": "k_elast_q2 (" + prim["variant"] + ")",
                         "kernel_ms": prim["kernel_ms"]}
     line["precisions"] = results
+    if not args.no_extra:
+        line["assembly"] = c2_assembly(args, mesh, lm, X, C)
     if not args.no_cpu:
         def call(k):
             t = time.perf_counter()
@@ -280,6 +282,34 @@ def run_c2(args, orc):
             "sample": f"first {k2} cells of the 48^3 Q2 mesh x {reps} "
                       f"passes, FP64 element matrices, {tot:.1f} s"}
     return line
+
+
+def c2_assembly(args, mesh, lm, X, C):
+    """Global block-CSR assembly of the FP64 elasticity matrices (the step
+    after the element loop): pattern build once, then the assembly kernel
+    timed; bytes = element matrices read once + values written once."""
+    import torch
+    import paper_2107_04121_amd as fe
+    plan = fe.Plan("hex", 2, "elasticity", "matrix", "fp64",
+                   material="iso_cell")
+    K = plan(X, C, material=torch.from_numpy(lm).to(X.device))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pat = fe.Pattern(C, mesh.n_nodes)
+    inc = fe.Incidence(C, mesh.n_nodes)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    vals = torch.empty((pat.nnz, 3, 3), dtype=torch.float64, device=X.device)
+    _, per = time_calls(lambda: fe.assemble_matrix(pat, inc, C, K, out=vals),
+                        args.steps, args.warmup)
+    kms = mean(per)
+    nbytes = K.numel() * 8 + vals.numel() * 8
+    res = dict(kernel="k_asm_rows<double,3>", kernel_ms=kms,
+               pattern_and_incidence_ms=setup_ms, nnz_blocks=pat.nnz,
+               bytes=nbytes, hbm_gbs=nbytes / (kms * 1e-3) / 1e9)
+    del K, vals, pat, inc
+    torch.cuda.empty_cache()
+    return res
 
 
 # ------------------------------------------------------------------- c1 ---

@@ -7,18 +7,20 @@
 // made unique on the device, so each row's column nodes come out sorted and
 // the rows contiguous.
 //
-// Values: one thread per row node n walks the node's incidence list (cells
-// and local numbers, sorted) and, for every local node b of each incident
-// cell, adds the n_comp x n_comp block K_e[(., a), (., b)] into the slot of
-// conn[e][b] found by binary search in the row.  A row is written by its own
-// thread only, in a fixed order: no atomics, bitwise repeatable.
+// Values: one wave per row node n walks the node's incidence list (cells and
+// local numbers (e, a), sorted); at each step lane b adds the n_comp x n_comp
+// block K_e[(., a), (., b)] into the row's LDS accumulator at the slot of
+// conn[e][b] (binary search in the row's columns, staged in LDS).  Within a
+// step the lanes hit distinct slots, the steps run in incidence order, and
+// lanes b read consecutive entries of the element matrix rows; the row is
+// written once at the end.  No atomics: bitwise repeatable.
 #include <hipcub/hipcub.hpp>
 
 #include "fe_device.h"
 
 struct fe_pattern_s {
     int64_t n_nodes = 0, nnz = 0;
-    int nb = 0, device = -1;
+    int nb = 0, device = -1, max_row = 0;
     int32_t *row_ptr = nullptr;  // [n_nodes + 1]
     int32_t *cols = nullptr;     // [nnz]
 };
@@ -52,38 +54,61 @@ __global__ void k_pair_split(const uint64_t *keys, int64_t nnz, int64_t n_nodes,
     atomicAdd(&cnt[row], 1);  // integer counts: the result does not depend on the order
 }
 
-template <typename T, int NC>
-__global__ void k_asm_matrix(const int32_t *row_ptr, const int32_t *cols, const int32_t *inc_off,
-                             const int32_t *inc_items, const int32_t *conn, int64_t n_nodes, int nb, const T *K,
-                             double scale, T *values)
+__device__ __forceinline__ void wave_sync()
 {
-    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= n_nodes) return;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// LDS bytes of one row's columns and block accumulators
+template <typename T, int NC>
+constexpr size_t row_lds(int len)
+{
+    return ((size_t)len * 4 + 15) / 16 * 16 + (size_t)len * NC * NC * sizeof(T);
+}
+
+template <typename T, int NC>
+__global__ __launch_bounds__(64) void k_asm_rows(const int32_t *row_ptr, const int32_t *cols,
+                                                 const int32_t *inc_off, const int32_t *inc_items,
+                                                 const int32_t *conn, int nb, const T *K, double scale, T *values)
+{
+    extern __shared__ __align__(16) unsigned char sm[];
     constexpr int B = NC * NC;
-    const int r0 = row_ptr[n], r1 = row_ptr[n + 1];
-    for (int64_t k = (int64_t)r0 * B; k < (int64_t)r1 * B; k++) values[k] = T(0);
+    const int64_t n = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int r0 = row_ptr[n], len = row_ptr[n + 1] - r0;
+    int32_t *sc = reinterpret_cast<int32_t *>(sm);
+    T *acc = reinterpret_cast<T *>(sm + ((size_t)len * 4 + 15) / 16 * 16);
+    for (int k = lane; k < len; k += 64) sc[k] = cols[r0 + k];
+    for (int k = lane; k < len * B; k += 64) acc[k] = T(0);
+    wave_sync();
     const int nd = NC * nb;
     const T s = static_cast<T>(scale);
-    for (int it = inc_off[n]; it < inc_off[n + 1]; it++) {
+    const int i1 = inc_off[n + 1];
+    for (int it = inc_off[n]; it < i1; it++) {
         const int32_t item = inc_items[it];
         const int64_t e = item / nb;
         const int a = item - static_cast<int>(e) * nb;
-        const T *Ke = K + e * (int64_t)nd * nd;
-        for (int b = 0; b < nb; b++) {
-            const int32_t m = conn[e * nb + b];
-            int lo = r0, hi = r1 - 1;
+        if (lane < nb) {
+            const int32_t m = conn[e * nb + lane];
+            int lo = 0, hi = len - 1;
             while (lo < hi) {
                 const int mid = (lo + hi) >> 1;
-                if (cols[mid] < m) lo = mid + 1;
+                if (sc[mid] < m) lo = mid + 1;
                 else hi = mid;
             }
-            T *v = values + (int64_t)lo * B;
+            const T *Ke = K + e * (int64_t)nd * nd + a * nd + lane;
+            T *v = acc + lo * B;
 #pragma unroll
             for (int c = 0; c < NC; c++)
 #pragma unroll
-                for (int d = 0; d < NC; d++) v[c * NC + d] += s * Ke[(c * nb + a) * nd + d * nb + b];
+                for (int d = 0; d < NC; d++) v[c * NC + d] += s * Ke[(int64_t)c * nb * nd + d * nb];
         }
+        wave_sync();  // the next step may add to a slot another lane wrote
     }
+    T *out = values + (int64_t)r0 * B;
+    for (int k = lane; k < len * B; k += 64) out[k] = acc[k];
 }
 
 int bits_for(uint64_t x)
@@ -209,9 +234,21 @@ int fe_pattern_create(int64_t n_cells, int64_t n_nodes, int n_basis, const int32
     if (tmp) (void)hipFree(tmp);
     tmp = nullptr;
     if (hipMalloc(&tmp, b_scan ? b_scan : 1) != hipSuccess) return fail_hip("temporary allocation failed");
-    if (hipcub::DeviceScan::ExclusiveSum(tmp, b_scan, cnt, p->row_ptr, (int)(n_nodes + 1), st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
+    if (hipcub::DeviceScan::ExclusiveSum(tmp, b_scan, cnt, p->row_ptr, (int)(n_nodes + 1), st) != hipSuccess)
         return fail_hip("prefix sum failed");
+    // the longest row sizes the LDS of the assembly kernel
+    size_t b_max = 0;
+    if (hipcub::DeviceReduce::Max(nullptr, b_max, cnt, nsel, (int)n_nodes, st) != hipSuccess)
+        return fail_hip("row length sizing failed");
+    if (tmp) (void)hipFree(tmp);
+    tmp = nullptr;
+    if (hipMalloc(&tmp, b_max ? b_max : 1) != hipSuccess) return fail_hip("temporary allocation failed");
+    int32_t h_max = 0;
+    if (hipcub::DeviceReduce::Max(tmp, b_max, cnt, nsel, (int)n_nodes, st) != hipSuccess ||
+        hipMemcpyAsync(&h_max, nsel, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return fail_hip("row length reduction failed");
+    p->max_row = h_max;
     cleanup();
     *out = p;
     return FE_OK;
@@ -269,28 +306,40 @@ int fe_assemble_matrix(fe_pattern pat, fe_incidence inc, const int32_t *conn, in
         return FE_ERR_INVALID_ARG;
     }
     if (pat->n_nodes == 0 || inc->n_cells == 0) return FE_OK;
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    const dim3 grid((unsigned)((pat->n_nodes + 127) / 128)), block(128);
-    const int nb = pat->nb;
-    if (precision == FE_PREC_FP64) {
-        if (n_comp == 1)
-            hipLaunchKernelGGL((k_asm_matrix<double, 1>), grid, block, 0, st, pat->row_ptr, pat->cols, inc->offsets,
-                               inc->items, conn, pat->n_nodes, nb, static_cast<const double *>(cell_mats), scale,
-                               static_cast<double *>(values));
-        else
-            hipLaunchKernelGGL((k_asm_matrix<double, 3>), grid, block, 0, st, pat->row_ptr, pat->cols, inc->offsets,
-                               inc->items, conn, pat->n_nodes, nb, static_cast<const double *>(cell_mats), scale,
-                               static_cast<double *>(values));
-    } else {
-        if (n_comp == 1)
-            hipLaunchKernelGGL((k_asm_matrix<float, 1>), grid, block, 0, st, pat->row_ptr, pat->cols, inc->offsets,
-                               inc->items, conn, pat->n_nodes, nb, static_cast<const float *>(cell_mats), scale,
-                               static_cast<float *>(values));
-        else
-            hipLaunchKernelGGL((k_asm_matrix<float, 3>), grid, block, 0, st, pat->row_ptr, pat->cols, inc->offsets,
-                               inc->items, conn, pat->n_nodes, nb, static_cast<const float *>(cell_mats), scale,
-                               static_cast<float *>(values));
+    if (pat->nb > 64) {
+        set_error("matrix assembly takes at most 64 nodes per cell");
+        return FE_ERR_UNSUPPORTED;
     }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const bool f64 = precision == FE_PREC_FP64;
+    const size_t lds = f64 ? (n_comp == 1 ? row_lds<double, 1>(pat->max_row) : row_lds<double, 3>(pat->max_row))
+                           : (n_comp == 1 ? row_lds<float, 1>(pat->max_row) : row_lds<float, 3>(pat->max_row));
+    if (lds > 160 * 1024) {
+        set_error("a pattern row is too long for the LDS of the assembly kernel");
+        return FE_ERR_UNSUPPORTED;
+    }
+    if (pat->n_nodes > 0x7fffffffLL) {
+        set_error("too many rows for one launch");
+        return FE_ERR_INVALID_ARG;
+    }
+    const dim3 grid((unsigned)pat->n_nodes), block(64);
+    const int nb = pat->nb;
+    auto go = [&](auto kernel, const auto *K, auto *V) -> int {
+        if (lds > 64 * 1024)
+            FE_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL(kernel, grid, block, lds, st, pat->row_ptr, pat->cols, inc->offsets, inc->items, conn, nb,
+                           K, scale, V);
+        return FE_OK;
+    };
+    int rc;
+    if (f64)
+        rc = n_comp == 1 ? go(k_asm_rows<double, 1>, static_cast<const double *>(cell_mats), static_cast<double *>(values))
+                         : go(k_asm_rows<double, 3>, static_cast<const double *>(cell_mats), static_cast<double *>(values));
+    else
+        rc = n_comp == 1 ? go(k_asm_rows<float, 1>, static_cast<const float *>(cell_mats), static_cast<float *>(values))
+                         : go(k_asm_rows<float, 3>, static_cast<const float *>(cell_mats), static_cast<float *>(values));
+    if (rc) return rc;
     FE_HIP_CHECK(hipGetLastError());
     return FE_OK;
 }
