@@ -570,6 +570,8 @@ LaunchFn pick_order(int order, int form)
     if (order == 1) return pick<1, T>(form);
     if (order == 2) return pick<2, T>(form);
     if (order == 3) return pick<3, T>(form);
+    if (order == 4) return pick<4, T>(form);
+    if (order == 5) return pick<5, T>(form);
     return nullptr;
 }
 
@@ -598,6 +600,8 @@ int adj_order(int order, const ExecArgs &A, double scale, void *gmat, void *part
     if (order == 1) return launch_sf_adj<1, T>(A, scale, gmat, part, st);
     if (order == 2) return launch_sf_adj<2, T>(A, scale, gmat, part, st);
     if (order == 3) return launch_sf_adj<3, T>(A, scale, gmat, part, st);
+    if (order == 4) return launch_sf_adj<4, T>(A, scale, gmat, part, st);
+    if (order == 5) return launch_sf_adj<5, T>(A, scale, gmat, part, st);
     return FE_ERR_UNSUPPORTED;
 }
 
