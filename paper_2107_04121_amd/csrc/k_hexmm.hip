@@ -291,6 +291,10 @@ __device__ __forceinline__ int valid(int t)  // valid entries of tile t of a blo
     return H::NB - 16 * t < 16 ? H::NB - 16 * t : 16;
 }
 
+// The elasticity epilogues below evaluate lambda X + mu Y as
+// fma(lambda, X, mu Y) in every copy, so that an entry and its mirror are
+// rounded alike and the FP64/FP32 element matrices are exactly symmetric.
+//
 // Elasticity output of a DIAG job from c[t] = P_tt(i,j), t = 0,1,2:
 // K_tt(i,j) = (lambda + mu) P_tt(i,j) + mu sum_t' P_t't'(i,j), and the
 // mirrored tiles K_tt(j,i) = K_tt(i,j)^T when i != j.
@@ -310,7 +314,7 @@ __device__ __forceinline__ void epi_diag(const typename H::ACC *c, typename H::T
     for (int t = 0; t < 3; t++) {
         ACC k;
 #pragma unroll
-        for (int v = 0; v < 4; v++) k[v] = lm * c[t][v] + mu * S[v];
+        for (int v = 0; v < 4; v++) k[v] = fma(lm, c[t][v], mu * S[v]);
         store_tile<H>(oc, t * NB + 16 * i, t * NB + 16 * j, vi, vj, k, lane);
     }
     if (i != j) {
@@ -320,7 +324,7 @@ __device__ __forceinline__ void epi_diag(const typename H::ACC *c, typename H::T
             const ACC ct = transpose<H>(c[t], buf, lane);
             ACC k;
 #pragma unroll
-            for (int v = 0; v < 4; v++) k[v] = lm * ct[v] + mu * St[v];
+            for (int v = 0; v < 4; v++) k[v] = fma(lm, ct[v], mu * St[v]);
             store_tile<H>(oc, t * NB + 16 * j, t * NB + 16 * i, vj, vi, k, lane);
         }
     }
@@ -339,17 +343,17 @@ __device__ __forceinline__ void epi_pair(const typename H::ACC *c, typename H::T
     const ACC Bt = transpose<H>(c[1], buf, lane);
     ACC x;
 #pragma unroll
-    for (int v = 0; v < 4; v++) x[v] = lam * c[0][v] + mu * Bt[v];
+    for (int v = 0; v < 4; v++) x[v] = fma(lam, c[0][v], mu * Bt[v]);
     store_tile<H>(oc, r * NB + 16 * i, s * NB + 16 * j, vi, vj, x, lane);  // K_rs(i,j)
 #pragma unroll
-    for (int v = 0; v < 4; v++) x[v] = lam * Bt[v] + mu * c[0][v];
+    for (int v = 0; v < 4; v++) x[v] = fma(lam, Bt[v], mu * c[0][v]);
     store_tile<H>(oc, s * NB + 16 * i, r * NB + 16 * j, vi, vj, x, lane);  // K_sr(i,j)
     const ACC At = transpose<H>(c[0], buf, lane);
 #pragma unroll
-    for (int v = 0; v < 4; v++) x[v] = lam * c[1][v] + mu * At[v];
+    for (int v = 0; v < 4; v++) x[v] = fma(lam, c[1][v], mu * At[v]);
     store_tile<H>(oc, r * NB + 16 * j, s * NB + 16 * i, vj, vi, x, lane);  // K_rs(j,i)
 #pragma unroll
-    for (int v = 0; v < 4; v++) x[v] = lam * At[v] + mu * c[1][v];
+    for (int v = 0; v < 4; v++) x[v] = fma(lam, At[v], mu * c[1][v]);
     store_tile<H>(oc, s * NB + 16 * j, r * NB + 16 * i, vj, vi, x, lane);  // K_sr(j,i)
 }
 
@@ -364,11 +368,47 @@ __device__ __forceinline__ void epi_single(const typename H::ACC &a, typename H:
     const ACC at = transpose<H>(a, buf, lane);
     ACC x;
 #pragma unroll
-    for (int v = 0; v < 4; v++) x[v] = lam * a[v] + mu * at[v];
+    for (int v = 0; v < 4; v++) x[v] = fma(lam, a[v], mu * at[v]);
     store_tile<H>(oc, r * NB + 16 * i, s * NB + 16 * i, vi, vi, x, lane);
 #pragma unroll
-    for (int v = 0; v < 4; v++) x[v] = lam * at[v] + mu * a[v];
+    for (int v = 0; v < 4; v++) x[v] = fma(lam, at[v], mu * a[v]);
     store_tile<H>(oc, s * NB + 16 * i, r * NB + 16 * i, vi, vi, x, lane);
+}
+
+// Laplace output of a LAP job from S = sum_t P_tt(i,j), and its mirror.
+template <class H>
+__device__ __forceinline__ void epi_lap(const typename H::ACC &S, typename H::T *oc, typename H::T *buf, int i, int j,
+                                        int lane)
+{
+    const int vi = valid<H>(i), vj = valid<H>(j);
+    store_tile<H>(oc, 16 * i, 16 * j, vi, vj, S, lane);
+    if (i != j) store_tile<H>(oc, 16 * j, 16 * i, vj, vi, transpose<H>(S, buf, lane), lane);
+}
+
+// Mass output of a MASS job from a = P(i,j): scalar mass M(i,j) and its
+// mirror, or for the vector mass the tile in the three diagonal blocks and
+// zeros in the six others.
+template <class H, int FORM>
+__device__ __forceinline__ void epi_mass(const typename H::ACC &a, typename H::T *oc, typename H::T *buf, int i,
+                                         int j, int lane)
+{
+    using ACC = typename H::ACC;
+    const int vi = valid<H>(i), vj = valid<H>(j);
+    if constexpr (FORM == FE_FORM_MASS) {
+        store_tile<H>(oc, 16 * i, 16 * j, vi, vj, a, lane);
+        if (i != j) store_tile<H>(oc, 16 * j, 16 * i, vj, vi, transpose<H>(a, buf, lane), lane);
+    } else {
+        constexpr int NB = H::NB;
+        const ACC tt = i != j ? transpose<H>(a, buf, lane) : a;
+        const ACC z = {};
+#pragma unroll
+        for (int rr = 0; rr < 3; rr++)
+#pragma unroll
+            for (int ss = 0; ss < 3; ss++) {
+                store_tile<H>(oc, rr * NB + 16 * i, ss * NB + 16 * j, vi, vj, rr == ss ? a : z, lane);
+                if (i != j) store_tile<H>(oc, rr * NB + 16 * j, ss * NB + 16 * i, vj, vi, rr == ss ? tt : z, lane);
+            }
+    }
 }
 
 // One job of the current cell.  oc = the cell's output matrix.
@@ -379,7 +419,6 @@ __device__ __forceinline__ void run_job(uint32_t jb, const typename H::OPT *op, 
     using ACC = typename H::ACC;
     constexpr int NBP = H::NBP, KP = H::KP;
     const int kind = jb & 15, r = (jb >> 4) & 3, s = (jb >> 6) & 3, i = (jb >> 8) & 15, j = (jb >> 12) & 15;
-    const int vi = valid<H>(i), vj = valid<H>(j);
     if (kind == J_DIAG || kind == J_LAP) {
         ACC c[3] = {};
         const int ra[3] = {16 * i, NBP + 16 * i, 2 * NBP + 16 * i};
@@ -392,8 +431,7 @@ __device__ __forceinline__ void run_job(uint32_t jb, const typename H::OPT *op, 
         ACC S;
 #pragma unroll
         for (int v = 0; v < 4; v++) S[v] = c[0][v] + c[1][v] + c[2][v];
-        store_tile<H>(oc, 16 * i, 16 * j, vi, vj, S, lane);
-        if (i != j) store_tile<H>(oc, 16 * j, 16 * i, vj, vi, transpose<H>(S, buf, lane), lane);
+        epi_lap<H>(S, oc, buf, i, j, lane);
     } else if (kind == J_PAIR) {
         ACC c[2] = {};
         const int ra[2] = {r * NBP + 16 * i, r * NBP + 16 * j};
@@ -411,23 +449,10 @@ __device__ __forceinline__ void run_job(uint32_t jb, const typename H::OPT *op, 
         ACC a;
 #pragma unroll
         for (int v = 0; v < 4; v++) a[v] = c[0][v] + c[1][v];
-        if (kind == J_SINGLE) {
+        if (kind == J_SINGLE)
             epi_single<H>(a, oc, buf, lam, mu, r, s, i, lane);
-        } else if constexpr (FORM == FE_FORM_MASS) {
-            store_tile<H>(oc, 16 * i, 16 * j, vi, vj, a, lane);
-            if (i != j) store_tile<H>(oc, 16 * j, 16 * i, vj, vi, transpose<H>(a, buf, lane), lane);
-        } else {
-            constexpr int NB = H::NB;
-            const ACC tt = i != j ? transpose<H>(a, buf, lane) : a;
-            const ACC z = {};
-#pragma unroll
-            for (int rr = 0; rr < 3; rr++)
-#pragma unroll
-                for (int ss = 0; ss < 3; ss++) {
-                    store_tile<H>(oc, rr * NB + 16 * i, ss * NB + 16 * j, vi, vj, rr == ss ? a : z, lane);
-                    if (i != j) store_tile<H>(oc, rr * NB + 16 * j, ss * NB + 16 * i, vj, vi, rr == ss ? tt : z, lane);
-                }
-        }
+        else
+            epi_mass<H, FORM>(a, oc, buf, i, j, lane);
     }
 }
 
@@ -1008,6 +1033,493 @@ int launch_hexmm(const Plan &, const ExecArgs &A, hipStream_t st)
     return FE_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Q4 and Q5: the same products with the quadrature points taken in chunks.
+//
+// At p = 4, 5 the operand g (3 (p+1)^3 rows x (p+1)^3 points) no longer fits
+// in LDS (Q5, FP64: 1.2 MB), so only a chunk of KC points of it is built at a
+// time (FP64 16, FP32 and BF16X3 32).  The geometry (sqrt(w det J) J^-1 at
+// every point, FP64) is computed once per cell; the operand chunks are
+// rebuilt from it.  The jobs are the tiles of k_hexmm, grouped by kind into
+// passes small enough for their accumulators to stay in registers across
+// all chunks (16 FP64 / 32 FP32 tiles per wave):
+//   for each pass:  for each chunk: build it; barrier; every wave adds the
+//                   chunk's products to its jobs' accumulators; barrier
+//                   then every wave runs its jobs' epilogues
+// Every wave of a pass carries the same number of job slots, so the
+// products are straight-line code; slots beyond a wave's jobs multiply
+// operand rows 0 and are never stored.  Laplace jobs sum the three
+// gradient components into one accumulator.
+constexpr int mc_cap(int mm) { return mm == MM_F32 ? 32 : 16; }  // accumulator tiles per wave
+constexpr int mc_kc(int mm) { return mm == MM_F64 ? 16 : 32; }   // points per chunk
+constexpr int kind_na(int kind) { return kind == J_DIAG ? 3 : (kind == J_PAIR ? 2 : 1); }
+constexpr int kind_nprod(int kind) { return kind == J_DIAG || kind == J_LAP ? 3 : (kind == J_PAIR ? 2 : 1); }
+
+constexpr int MC_PASSES = 12, MC_JOBS = 32;
+struct MCSched {
+    int ng;             // job kinds (groups of passes)
+    int kind[3], nj[3];  // kind and job slots per wave of each group
+    int p0[3], np[3];   // first pass and passes of each group
+    uint8_t n[MC_PASSES][WAVES];
+    uint32_t job[MC_PASSES][WAVES][MC_JOBS];
+};
+
+constexpr MCSched make_mc_sched(int form, int nt, int cap)
+{
+    MCSched S{};
+    int kinds[3] = {J_LAP, 0, 0}, nk = 1;
+    if (form == FE_FORM_ELASTICITY) {
+        kinds[0] = J_DIAG;
+        kinds[1] = J_PAIR;
+        kinds[2] = J_SINGLE;
+        nk = 3;
+    } else if (form != FE_FORM_LAPLACE) {
+        kinds[0] = J_MASS;
+    }
+    int npass = 0;
+    for (int g = 0; g < nk; g++) {
+        const int kind = kinds[g];
+        uint32_t jobs[320] = {};
+        int nj = 0;
+        if (kind == J_PAIR) {
+            for (int r = 0; r < 3; r++)
+                for (int s = r + 1; s < 3; s++)
+                    for (int i = 0; i < nt; i++)
+                        for (int j = i + 1; j < nt; j++) jobs[nj++] = enc(J_PAIR, r, s, i, j);
+        } else if (kind == J_SINGLE) {
+            for (int r = 0; r < 3; r++)
+                for (int s = r + 1; s < 3; s++)
+                    for (int i = 0; i < nt; i++) jobs[nj++] = enc(J_SINGLE, r, s, i, i);
+        } else {
+            for (int i = 0; i < nt; i++)
+                for (int j = i; j < nt; j++) jobs[nj++] = enc(kind, 0, 0, i, j);
+        }
+        const int capj = cap / kind_na(kind);
+        const int np = (nj + WAVES * capj - 1) / (WAVES * capj);
+        S.kind[g] = kind;
+        S.np[g] = np;
+        S.nj[g] = (nj + WAVES * np - 1) / (WAVES * np);
+        S.p0[g] = npass;
+        for (int p = 0; p < np; p++, npass++) {
+            const int lo = p * nj / np, hi = (p + 1) * nj / np;
+            for (int k = lo; k < hi; k++) {
+                const int w = (k - lo) % WAVES;
+                S.job[npass][w][S.n[npass][w]++] = jobs[k];
+            }
+        }
+    }
+    S.ng = nk;
+    return S;
+}
+
+template <int P, int FORM, int MM>
+struct HexMC {
+    static constexpr int N1 = P + 1, NB = N1 * N1 * N1, NQ = NB;
+    static constexpr bool MASSF = FORM == FE_FORM_MASS || FORM == FE_FORM_VMASS;
+    static constexpr int NC = MASSF ? 1 : 3;
+    static constexpr int NCO = form_nc(FORM);
+    static constexpr int ND = NCO * NB;
+    static constexpr int NBP = align_to(NB, 16), NT = NBP / 16;
+    static constexpr bool RAGGED = NB % 16 != 0;
+    using T = typename MMT<MM>::T;
+    using ACC = typename MMT<MM>::acc;
+    using OPT = typename std::conditional<MM == MM_BF16X3, __bf16, T>::type;
+    static constexpr int KC = mc_kc(MM), NCH = (NQ + KC - 1) / KC;
+    static constexpr int KSTEP = MM == MM_BF16X3 ? 32 : 4;
+    static constexpr int KS = op_stride(MM, KC);
+    static constexpr int ROWS = NC * NBP;
+    static constexpr int NOP = MM == MM_BF16X3 ? 2 : 1;
+    static constexpr int OP_N = ROWS * KS;  // entries of one operand array
+    static constexpr int TS = 17;
+    static constexpr int OFF_TB = 0;  // double B1[N1][N1], D1[N1][N1], w[NQ]
+    static constexpr int OFF_X = q2::align16(OFF_TB + (2 * N1 * N1 + NQ) * 8);  // double xs[3][NB], T lm[2]
+    static constexpr int OFF_G = q2::align16(OFF_X + 3 * NB * 8 + 16);          // double [NQ][10] (J: [NQ][9])
+    static constexpr int OFF_OP = q2::align16(OFF_G + NQ * 10 * 8);
+    static constexpr int OFF_TR = q2::align16(OFF_OP + NOP * OP_N * (int)sizeof(OPT));
+    static constexpr int BYTES = q2::align16(OFF_TR + WAVES * 16 * TS * (int)sizeof(T));
+    static constexpr MCSched SCHED = make_mc_sched(FORM == FE_FORM_VMASS ? FE_FORM_MASS : FORM, NT, mc_cap(MM));
+    static_assert(BYTES <= 160 * 1024, "LDS");
+};
+
+// Operand chunk ch: columns = points ch*KC .. ch*KC+KC-1 (zero beyond NQ),
+// rows (c, a) for a < NB; item (point, a1, a2) writes a0 = 0..N1-1.
+template <class H>
+__device__ __forceinline__ void mc_build(typename H::OPT *op, const double *Mq, const double *B1, const double *D1,
+                                         int ch, int tid)
+{
+    using OPT = typename H::OPT;
+    constexpr int N1 = H::N1, NQ = H::NQ, NC = H::NC, NBP = H::NBP, KS = H::KS, KC = H::KC;
+    auto put = [&](int c, int a0, int a12, int ql, double x) {
+        const int o = (c * NBP + a0 + N1 * a12) * KS + ql;
+        if constexpr (H::NOP == 1) {
+            op[o] = static_cast<OPT>(x);
+        } else {
+            const float f = static_cast<float>(x);
+            const __bf16 h = static_cast<__bf16>(f);
+            op[o] = h;
+            op[H::OP_N + o] = static_cast<__bf16>(f - static_cast<float>(h));
+        }
+    };
+    for (int it = tid; it < KC * N1 * N1; it += THREADS) {
+        const int ql = it % KC, a12 = it / KC, a1 = a12 % N1, a2 = a12 / N1;
+        const int qq = ch * KC + ql;
+        if (qq < NQ) {
+            const int q0 = qq % N1, q1 = (qq / N1) % N1, q2 = qq / (N1 * N1);
+            const double by = B1[q1 * N1 + a1], bz = B1[q2 * N1 + a2];
+            const double *M = Mq + qq * 10;
+            if constexpr (NC == 1) {
+                const double f = M[9] * by * bz;
+#pragma unroll
+                for (int a0 = 0; a0 < N1; a0++) put(0, a0, a12, ql, f * B1[q0 * N1 + a0]);
+            } else {
+                const double dy = D1[q1 * N1 + a1], dz = D1[q2 * N1 + a2];
+                const double m[9] = {M[0], M[1], M[2], M[3], M[4], M[5], M[6], M[7], M[8]};
+#pragma unroll
+                for (int a0 = 0; a0 < N1; a0++) {
+                    const double bx = B1[q0 * N1 + a0], dx = D1[q0 * N1 + a0];
+                    const double d0 = dx * by * bz, d1 = bx * dy * bz, d2 = bx * by * dz;
+#pragma unroll
+                    for (int c = 0; c < 3; c++) put(c, a0, a12, ql, d0 * m[c] + d1 * m[3 + c] + d2 * m[6 + c]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < NC; c++)
+#pragma unroll
+                for (int a0 = 0; a0 < N1; a0++) put(c, a0, a12, ql, 0.0);
+        }
+    }
+}
+
+// accumulator of product u = m * NJ + jj (m-th product of job slot jj)
+template <int KIND, int NJ>
+constexpr int mc_acc(int u)
+{
+    return KIND == J_DIAG ? (u % NJ) * 3 + u / NJ : (KIND == J_PAIR ? (u % NJ) * 2 + u / NJ : u % NJ);
+}
+
+// Operand rows of product u: a base row per job (two for PAIR, whose
+// products differ in their tiles) plus, for DIAG and LAP, the component
+// block m * NBP as a compile-time offset.
+constexpr int mc_nbase(int kind) { return kind == J_PAIR ? 2 : 1; }
+template <class H, int KIND, int NJ>
+constexpr int mc_base(int u)
+{
+    return KIND == J_PAIR ? (u / NJ) * NJ + u % NJ : u % NJ;
+}
+template <class H, int KIND, int NJ>
+constexpr int mc_ofs(int u)
+{
+    return KIND == J_DIAG || KIND == J_LAP ? (u / NJ) * H::NBP : 0;
+}
+
+// The products of one chunk: acc[mc_acc(u)] += g[ra[u]..][chunk] g[rb[u]..][chunk]^T
+// for u < NS, in groups of G products whose fragments are loaded while the
+// previous group multiplies.
+template <class H, int KIND, int NJ>
+__device__ __forceinline__ void mc_mma(typename H::ACC *acc, const typename H::OPT *op, const int *ra, const int *rb,
+                                       int lane)
+{
+    using OPT = typename H::OPT;
+    constexpr int NS = NJ * kind_nprod(KIND);
+    constexpr int KS = H::KS, NSTEP = H::KC / H::KSTEP;
+    const int m = lane & 15, grp = lane >> 4;
+    if constexpr (H::NOP == 1) {
+        // k steps in a loop, the groups of one step unrolled; the first
+        // group of a step is loaded at its top
+        constexpr int G = sizeof(OPT) == 8 ? 4 : 8;
+        constexpr int NG = (NS + G - 1) / G;
+        OPT a[2][G], b[2][G];
+        auto load = [&](int buf, int g, int k) {
+#pragma unroll
+            for (int v = 0; v < G; v++)
+                if (g * G + v < NS) {
+                    const int u = g * G + v;
+                    a[buf][v] = op[(ra[mc_base<H, KIND, NJ>(u)] + mc_ofs<H, KIND, NJ>(u) + m) * KS + k];
+                    b[buf][v] = op[(rb[mc_base<H, KIND, NJ>(u)] + mc_ofs<H, KIND, NJ>(u) + m) * KS + k];
+                }
+        };
+        auto mfma = [&](int buf, int g) {
+#pragma unroll
+            for (int v = 0; v < G; v++)
+                if (g * G + v < NS) {
+                    const int x = mc_acc<KIND, NJ>(g * G + v);
+                    if constexpr (sizeof(OPT) == 8)
+                        acc[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[buf][v], b[buf][v], acc[x], 0, 0, 0);
+                    else
+                        acc[x] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[buf][v], b[buf][v], acc[x], 0, 0, 0);
+                }
+        };
+        for (int st = 0; st < NSTEP; st++) {
+            const int k = 4 * st + grp;
+            load(0, 0, k);
+#pragma unroll
+            for (int g = 0; g < NG; g++) {
+                if (g + 1 < NG) load((g + 1) & 1, g + 1, k);
+                __builtin_amdgcn_sched_barrier(0);
+                mfma(g & 1, g);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    } else {
+        const OPT *lo = op + H::OP_N;
+        constexpr int G = 2, NG = (NS + G - 1) / G;
+        bf8 ah[2][G], al[2][G], bh[2][G], bl[2][G];
+        auto load = [&](int buf, int it) {
+            const int g0 = it * G;
+#pragma unroll
+            for (int v = 0; v < G; v++)
+                if (g0 + v < NS) {
+                    const int u = g0 + v;
+                    const int oa = (ra[mc_base<H, KIND, NJ>(u)] + mc_ofs<H, KIND, NJ>(u) + m) * KS + 8 * grp;
+                    const int ob = (rb[mc_base<H, KIND, NJ>(u)] + mc_ofs<H, KIND, NJ>(u) + m) * KS + 8 * grp;
+                    ah[buf][v] = *reinterpret_cast<const bf8 *>(op + oa);
+                    al[buf][v] = *reinterpret_cast<const bf8 *>(lo + oa);
+                    bh[buf][v] = *reinterpret_cast<const bf8 *>(op + ob);
+                    bl[buf][v] = *reinterpret_cast<const bf8 *>(lo + ob);
+                }
+        };
+        auto mfma = [&](int buf, int it) {
+            const int g0 = it * G;
+#pragma unroll
+            for (int v = 0; v < G; v++)
+                if (g0 + v < NS) {
+                    const int x = mc_acc<KIND, NJ>(g0 + v);
+                    acc[x] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[buf][v], bh[buf][v], acc[x], 0, 0, 0);
+                    acc[x] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[buf][v], bl[buf][v], acc[x], 0, 0, 0);
+                    acc[x] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[buf][v], bh[buf][v], acc[x], 0, 0, 0);
+                }
+        };
+        load(0, 0);
+#pragma unroll
+        for (int it = 0; it < NG; it++) {
+            if (it + 1 < NG) load((it + 1) & 1, it + 1);
+            __builtin_amdgcn_sched_barrier(0);
+            mfma(it & 1, it);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+// One pass (jobs of one kind, NJ slots per wave) over all chunks of the cell.
+template <class H, int FORM, int KIND, int NJ>
+__device__ __forceinline__ void mc_pass(int ps, typename H::OPT *op, const double *Mq, const double *B1,
+                                        const double *D1, typename H::T *oc, typename H::T *buf, typename H::T lam,
+                                        typename H::T mu, int wave, int tid, int lane)
+{
+    using ACC = typename H::ACC;
+    constexpr int NBP = H::NBP;
+    const int nw = H::SCHED.n[ps][wave];
+    constexpr int NBS = mc_nbase(KIND);
+    int ra[NJ * NBS], rb[NJ * NBS];
+#pragma unroll
+    for (int jj = 0; jj < NJ; jj++) {
+        const uint32_t jb = jj < nw ? H::SCHED.job[ps][wave][jj] : 0u;
+        const int r = (jb >> 4) & 3, s = (jb >> 6) & 3, i = (jb >> 8) & 15, j = (jb >> 12) & 15;
+        if constexpr (KIND == J_DIAG || KIND == J_LAP || KIND == J_MASS) {
+            ra[jj] = 16 * i;
+            rb[jj] = 16 * j;
+        } else if constexpr (KIND == J_PAIR) {
+            ra[jj] = r * NBP + 16 * i;
+            rb[jj] = s * NBP + 16 * j;
+            ra[NJ + jj] = r * NBP + 16 * j;
+            rb[NJ + jj] = s * NBP + 16 * i;
+        } else {
+            ra[jj] = r * NBP + 16 * i;
+            rb[jj] = s * NBP + 16 * i;
+        }
+    }
+    ACC acc[NJ * kind_na(KIND)];
+#pragma unroll
+    for (int x = 0; x < NJ * kind_na(KIND); x++) acc[x] = ACC{};
+    for (int ch = 0; ch < H::NCH; ch++) {
+        mc_build<H>(op, Mq, B1, D1, ch, tid);
+        __syncthreads();
+        mc_mma<H, KIND, NJ>(acc, op, ra, rb, lane);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int jj = 0; jj < NJ; jj++) {
+        if (jj >= nw) continue;
+        const uint32_t jb = H::SCHED.job[ps][wave][jj];
+        const int r = (jb >> 4) & 3, s = (jb >> 6) & 3, i = (jb >> 8) & 15, j = (jb >> 12) & 15;
+        if constexpr (KIND == J_DIAG) {
+            epi_diag<H>(acc + 3 * jj, oc, buf, lam, mu, i, j, lane);
+        } else if constexpr (KIND == J_PAIR) {
+            epi_pair<H>(acc + 2 * jj, oc, buf, lam, mu, r, s, i, j, lane);
+        } else if constexpr (KIND == J_SINGLE) {
+            epi_single<H>(acc[jj], oc, buf, lam, mu, r, s, i, lane);
+        } else if constexpr (KIND == J_LAP) {
+            epi_lap<H>(acc[jj], oc, buf, i, j, lane);
+        } else {
+            epi_mass<H, FORM>(acc[jj], oc, buf, i, j, lane);
+        }
+    }
+}
+
+template <class H, int FORM, int G>
+__device__ __forceinline__ void mc_group(typename H::OPT *op, const double *Mq, const double *B1, const double *D1,
+                                         typename H::T *oc, typename H::T *buf, typename H::T lam, typename H::T mu,
+                                         int wave, int tid, int lane)
+{
+    if constexpr (G < H::SCHED.ng) {
+        constexpr int KIND = H::SCHED.kind[G], NJ = H::SCHED.nj[G];
+        for (int p = 0; p < H::SCHED.np[G]; p++)
+            mc_pass<H, FORM, KIND, NJ>(H::SCHED.p0[G] + p, op, Mq, B1, D1, oc, buf, lam, mu, wave, tid, lane);
+    }
+}
+
+template <int P, int FORM, int MM>
+__global__ __launch_bounds__(THREADS, 1) void k_hexmc(ExecArgs A)
+{
+    using H = HexMC<P, FORM, MM>;
+    using T = typename H::T;
+    using OPT = typename H::OPT;
+    constexpr int N1 = H::N1, NB = H::NB, NQ = H::NQ, NC = H::NC, NBP = H::NBP, KS = H::KS;
+    constexpr bool ELAST = FORM == FE_FORM_ELASTICITY;
+    __shared__ __align__(16) unsigned char smem[H::BYTES];
+    double *B1 = reinterpret_cast<double *>(smem + H::OFF_TB);
+    double *D1 = B1 + N1 * N1;
+    double *wq = D1 + N1 * N1;
+    double *xs = reinterpret_cast<double *>(smem + H::OFF_X);  // [3][NB]
+    T *lms = reinterpret_cast<T *>(xs + 3 * NB);
+    double *Jq = reinterpret_cast<double *>(smem + H::OFF_G);  // [NQ][9]
+    double *Mq = Jq;                                           // [NQ][10]: sqrt(wd) J^-1, sqrt(wd)
+    OPT *op = reinterpret_cast<OPT *>(smem + H::OFF_OP);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    T *buf = reinterpret_cast<T *>(smem + H::OFF_TR) + wave * 16 * H::TS;
+
+    int64_t e, e_end, stride;
+    cell_range(A.xcd_remap, A.n_cells, e, e_end, stride);
+    if (e >= e_end) return;  // uniform over the workgroup
+    const T *mat = static_cast<const T *>(A.mat);
+
+    for (int k = tid; k < N1 * N1; k += THREADS) {
+        B1[k] = A.tab.B1[k];
+        D1[k] = A.tab.D1[k];
+    }
+    for (int k = tid; k < NQ; k += THREADS) wq[k] = A.tab.w[k];
+    // padding rows a = NB .. NBP-1 of every component stay zero
+    for (int k = tid; k < H::NOP * NC * (NBP - NB) * KS; k += THREADS) {
+        const int arr = k / (NC * (NBP - NB) * KS), rem = k - arr * (NC * (NBP - NB) * KS);
+        const int rr = rem / KS, c = rr / (NBP - NB), a = NB + rr - c * (NBP - NB);
+        op[arr * H::OP_N + (c * NBP + a) * KS + rem - rr * KS] = OPT(0);
+    }
+
+    for (; e < e_end; e += stride) {
+        // coordinates relative to the cell's first node: J is unchanged (the
+        // basis gradients sum to zero) but no longer formed by cancelling
+        // terms of the size of |x| when the cell lies far from the origin
+        for (int k = tid; k < 3 * NB; k += THREADS) {
+            const int a = k / 3, c = k - 3 * a;
+            const int64_t n = checked_node(A.conn, e * NB + a, A.n_nodes, A.flags);
+            const int64_t n0 = checked_node(A.conn, e * NB, A.n_nodes, A.flags);
+            xs[c * NB + a] = A.coords[3 * n + c] - A.coords[3 * n0 + c];
+        }
+        if constexpr (ELAST)
+            if (tid < 2) lms[tid] = mat[2 * e + tid];
+        __syncthreads();
+        T lam = T(0), mu = T(0);
+        if constexpr (ELAST) {
+            lam = lms[0];
+            mu = lms[1];
+        }
+        // J[i][j] at each point by sum factorization over the 1-D tables
+        for (int it = tid; it < NQ * 9; it += THREADS) {
+            const int q = it % NQ, ij = it / NQ, i = ij / 3, jj = ij - 3 * (ij / 3);
+            const int q0 = q % N1, q1 = (q / N1) % N1, q2 = q / (N1 * N1);
+            const double *T0 = (jj == 0 ? D1 : B1) + q0 * N1;
+            const double *T1 = (jj == 1 ? D1 : B1) + q1 * N1;
+            const double *T2 = (jj == 2 ? D1 : B1) + q2 * N1;
+            const double *x = xs + i * NB;
+            double s2 = 0.0;
+#pragma unroll
+            for (int a2 = 0; a2 < N1; a2++) {
+                double s1 = 0.0;
+#pragma unroll
+                for (int a1 = 0; a1 < N1; a1++) {
+                    const double *xr = x + N1 * (a1 + N1 * a2);
+                    double s0 = 0.0;
+#pragma unroll
+                    for (int a0 = 0; a0 < N1; a0++) s0 = fma(T0[a0], xr[a0], s0);
+                    s1 = fma(T1[a1], s0, s1);
+                }
+                s2 = fma(T2[a2], s1, s2);
+            }
+            Jq[q * 9 + ij] = s2;
+        }
+        __syncthreads();
+        // det J, J^-1, sqrt(w det J) per point
+        double Mv[10];
+        const int q = tid;
+        if (q < NQ) {
+            double J[3][3], Ji[3][3];
+#pragma unroll
+            for (int r = 0; r < 3; r++)
+#pragma unroll
+                for (int c = 0; c < 3; c++) J[r][c] = Jq[q * 9 + r * 3 + c];
+            const double det = inverse3(J, Ji);
+            if (!(det > 0.0)) raise_fault(A.flags, FAULT_DET);
+            const double sw = sqrt(wq[q] * (det > 0.0 ? det : 0.0));
+#pragma unroll
+            for (int jj = 0; jj < 3; jj++)
+#pragma unroll
+                for (int i = 0; i < 3; i++) Mv[jj * 3 + i] = sw * Ji[jj][i];
+            Mv[9] = sw;
+        }
+        __syncthreads();  // every J read before Mq (same space) is written
+        if (q < NQ)
+#pragma unroll
+            for (int k = 0; k < 10; k++) Mq[q * 10 + k] = Mv[k];
+        __syncthreads();
+
+        T *oc = static_cast<T *>(A.out) + e * static_cast<int64_t>(H::ND) * H::ND;
+        mc_group<H, FORM, 0>(op, Mq, B1, D1, oc, buf, lam, mu, wave, tid, lane);
+        mc_group<H, FORM, 1>(op, Mq, B1, D1, oc, buf, lam, mu, wave, tid, lane);
+        mc_group<H, FORM, 2>(op, Mq, B1, D1, oc, buf, lam, mu, wave, tid, lane);
+        // the last chunk's barrier has passed: x and Mq may be rewritten
+    }
+}
+
+template <int P, int FORM, int MM>
+int launch_hexmc(const Plan &, const ExecArgs &A, hipStream_t st)
+{
+    if (A.n_cells <= 0) return FE_OK;
+    if (A.n_cells > 0x7fffffffLL) {
+        set_error("too many cells for one launch");
+        return FE_ERR_INVALID_ARG;
+    }
+    static int resident[64] = {0};
+    int dev = 0;
+    FE_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return FE_ERR_INVALID_ARG;
+    if (!resident[dev]) {
+        int per_cu = 0, cus = 0;
+        FE_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_hexmc<P, FORM, MM>, THREADS, 0));
+        FE_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        resident[dev] = per_cu * cus > 8 ? (per_cu * cus) & ~7 : 8;
+    }
+    const int64_t grid = A.n_cells < resident[dev] ? A.n_cells : resident[dev];
+    hipLaunchKernelGGL((k_hexmc<P, FORM, MM>), dim3((unsigned)grid), dim3(THREADS), 0, st, A);
+    FE_HIP_CHECK(hipGetLastError());
+    return FE_OK;
+}
+
+template <int P, int MM>
+LaunchFn pick_form_mc(const Plan &p)
+{
+    switch (p.form) {
+    case FE_FORM_MASS: return launch_hexmc<P, FE_FORM_MASS, MM>;
+    case FE_FORM_VMASS: return launch_hexmc<P, FE_FORM_VMASS, MM>;
+    case FE_FORM_LAPLACE: return launch_hexmc<P, FE_FORM_LAPLACE, MM>;
+    case FE_FORM_ELASTICITY:
+        if (p.mat_kind != FE_MAT_ISO_CELL) return nullptr;
+        return launch_hexmc<P, FE_FORM_ELASTICITY, MM>;
+    }
+    return nullptr;
+}
+
 template <int P, int MM>
 LaunchFn pick_form(const Plan &p)
 {
@@ -1028,6 +1540,8 @@ LaunchFn pick_order(const Plan &p)
 {
     if (p.order == 2) return pick_form<2, MM>(p);
     if (p.order == 3) return pick_form<3, MM>(p);
+    if (p.order == 4) return pick_form_mc<4, MM>(p);
+    if (p.order == 5) return pick_form_mc<5, MM>(p);
     return nullptr;
 }
 

@@ -107,3 +107,115 @@ def test_forms_without_kernel_refused(form, kind, mode):
         with pytest.raises(fe.FeError) as ei:
             fe.Plan("hex", p, form, mode, "fp64", material=kind)
         assert ei.value.status == 2  # FE_ERR_UNSUPPORTED
+
+
+MFORMS = [("mass", None), ("vmass", None), ("laplace", None), ("elasticity", "iso_cell")]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("form,kind", MFORMS)
+@pytest.mark.parametrize("p,dims,curved", HIGH)
+def test_matrix(orc, p, dims, curved, form, kind, prec):
+    """Element matrices on the matrix cores with the points taken in chunks
+    (ragged 16-row tiles: 125 = 7*16 + 13, 216 = 13*16 + 8)."""
+    import paper_2107_04121_amd as fe
+    mesh = _mesh(p, dims, curved, seed=46)
+    nb, nq = orc.sizes("hex", p)
+    mat = _material(kind, mesh, nq)
+    ref = orc.matrix(mesh, form, mat, kind)
+    plan = fe.Plan("hex", p, form, "matrix", prec, material=kind)
+    print(f"[high] matrix Q{p} {form}/{kind} {prec} variant={plan.variant} cells={mesh.n_cells}", flush=True)
+    assert plan.variant == "mfma"
+    out = plan(_t(mesh.coords), _t(mesh.conn), material=None if mat is None else _t(mat, plan.dtype))
+    plan.check()
+    got = out.cpu().numpy()
+    assert elem_rel_err(got, ref) < TOL[prec]
+    # every element matrix is symmetric: the mirrored tiles are transposes of
+    # the computed ones (exactly, except for BF16X3, whose split products
+    # are summed in another order for the mirrored entries of diagonal tiles)
+    if prec == "bf16x3":
+        assert elem_rel_err(got, np.swapaxes(got, 1, 2).astype(np.float64)) < 4 * TOL[prec]
+    else:
+        assert np.array_equal(got, np.swapaxes(got, 1, 2))
+
+
+def _sample(n, k=16, seed=5):
+    rng = np.random.default_rng(seed)
+    idx = set(rng.choice(n, size=min(k, n), replace=False).tolist())
+    for x in range(9):
+        c = min(n - 1, x * ((n + 7) // 8))
+        idx.update({c, max(0, c - 1)})
+    return np.array(sorted(idx))
+
+
+@pytest.mark.parametrize("p,form,prec", [(4, "laplace", "fp64"), (4, "elasticity", "fp32"),
+                                         (5, "elasticity", "fp64"), (5, "laplace", "bf16x3")])
+def test_matrix_1024_cells(orc, p, form, prec):
+    """The cell count of the paper's order 4-5 runs: 1,024 hexahedra (more
+    cells than the persistent grid has workgroups), as a 16 x 8 x 8 block of
+    unit cells.  The paper's bar would put nodes 1,024 cell sizes from the
+    origin, where the oracle's own J = sum_a x_a grad phi_a is only good to
+    2e-12 (Q4) / 5e-12 (Q5) (its element matrices move by that much when a
+    cell is translated that far), above the FP64 gate; matrix mode does not
+    depend on the topology.  Sampled cells against the oracle; every cell:
+    symmetry and the null space its form fixes (Laplace rows sum to zero,
+    elasticity annihilates the three rigid translations)."""
+    import torch
+    import paper_2107_04121_amd as fe
+    mesh = meshgen.hex_mesh((16, 8, 8), p, alpha=0.15, seed=50 + p, box=(16.0, 8.0, 8.0),
+                            curved=0.02 if p == 4 else 0.005)
+    kind = "iso_cell" if form == "elasticity" else None
+    lm = meshgen.lame_cell(mesh.n_cells, seed=51) if kind else None
+    plan = fe.Plan("hex", p, form, "matrix", prec, material=kind)
+    print(f"[high] 1024 cells Q{p} {form} {prec}", flush=True)
+    K = plan(_t(mesh.coords), _t(mesh.conn), material=None if lm is None else _t(lm, plan.dtype))
+    plan.check()
+    idx = _sample(mesh.n_cells)
+    sub = meshgen.Mesh(coords=mesh.coords, conn=mesh.conn[idx], cell="hex", order=p, h=mesh.h)
+    ref = orc.matrix(sub, form, None if lm is None else lm[idx], kind)
+    assert elem_rel_err(K[_t(idx)].cpu().numpy(), ref) < TOL[prec]
+    tol = TOL[prec]
+    nb = (p + 1) ** 3
+    for c0 in range(0, mesh.n_cells, 256):
+        Kd = K[c0:c0 + 256].double()
+        scale = Kd.abs().amax(dim=(1, 2))
+        asym = ((Kd - Kd.transpose(1, 2)).abs().amax(dim=(1, 2)) / scale).max().item()
+        assert asym < 4 * tol, asym
+        if form == "laplace":
+            rows = (Kd.sum(dim=2).abs().amax(dim=1) / scale).max().item()
+            assert rows < 50 * tol, rows
+        else:
+            for c in range(3):
+                t = torch.zeros(3 * nb, dtype=torch.float64, device=K.device)
+                t[c * nb:(c + 1) * nb] = 1
+                row = ((Kd @ t).abs().amax(dim=1) / scale).max().item()
+                assert row < 50 * tol, (c, row)
+        del Kd
+    del K
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("p,dims,curved", HIGH)
+def test_matrix_first_residual(orc, p, dims, curved):
+    """The matrix-first residual (element matrices materialised a chunk of
+    cells at a time, then applied) agrees with the oracle's residual."""
+    import paper_2107_04121_amd as fe
+    mesh = _mesh(p, dims, curved, seed=47)
+    nb, nq = orc.sizes("hex", p)
+    lm = _material("iso_cell", mesh, nq)
+    U = meshgen.dofs(mesh.n_nodes, 3, seed=48)
+    ref = orc.residual(mesh, "elasticity", U, lm, "iso_cell")
+    plan = fe.Plan("hex", p, "elasticity", "residual", "fp64", material="iso_cell",
+                   variant="matrix_first", chunk=5)
+    out = plan(_t(mesh.coords), _t(mesh.conn), material=_t(lm), dofs=_t(U))
+    plan.check()
+    assert elem_rel_err(out.cpu().numpy(), ref) < TOL["fp64"]
+
+
+@pytest.mark.parametrize("kind", ["iso_qp", "voigt_qp"])
+def test_matrix_material_per_point_refused(kind):
+    import paper_2107_04121_amd as fe
+    for p in (4, 5):
+        with pytest.raises(fe.FeError) as ei:
+            fe.Plan("hex", p, "elasticity", "matrix", "fp64", material=kind)
+        assert ei.value.status == 2
