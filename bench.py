@@ -26,7 +26,11 @@ Other configurations of the same hot path (--config):
   c7  the paper's two other benchmark forms on Q2 hexahedra, 32^3 cells,
       FP64 and FP32: weighted vector dot product (per-point 3x3 M) and
       Navier-Stokes convection (matrix = derivative at u ~ N(0,1)), matrix
-      and residual modes.
+      and residual modes;
+  c8  orders 4 and 5 at the paper's cell count for them, 1,024 cells:
+      Laplace and elasticity element matrices (FP64 / FP32 / BF16X3, on
+      the matrix cores, reported against their peak) and sum-factorized
+      residuals; primary Q5 elasticity matrices.
 Every configuration prints one JSON line.
 """
 from __future__ import annotations
@@ -53,9 +57,12 @@ MEASURED_TRAFFIC = {
     "k_elast_q2<0>": dict(bytes=5980620800, sha256="14f4c9ab9066dfda",
                           sources=["k_mfma.hip", "q2_device.h",
                                    "fe_device.h"]),
-    "k_elast_q3ws<0>": dict(bytes=9696710656, sha256="ef13c1bdbbb9c53e",
+    "k_elast_q3ws<0>": dict(bytes=9696700032, sha256="9f58d2b3c10a7e22",
                             sources=["k_hexmm.hip", "q2_device.h",
                                      "fe_device.h"]),
+    "k_hexmc<5,3,0>": dict(bytes=3533810560, sha256="9f58d2b3c10a7e22",
+                           sources=["k_hexmm.hip", "q2_device.h",
+                                    "fe_device.h"]),
     "k_cw_scalar<hex,1,laplace,double>@128^3": dict(
         bytes=1195318954, sha256="8f5712b5093a62b8",
         sources=["k_cellwise.hip", "cw_device.h", "fe_device.h"]),
@@ -85,7 +92,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c2",
-                    choices=["c1", "c2", "c3", "c4", "c5", "c6", "c7"])
+                    choices=["c1", "c2", "c3", "c4", "c5", "c6", "c7", "c8"])
     ap.add_argument("--n", type=int, default=0, help="cells per axis")
     ap.add_argument("--precision", default="fp64",
                     choices=["fp64", "fp32", "bf16x3"])
@@ -830,6 +837,107 @@ def run_c7(args, orc):
     return line
 
 
+# ------------------------------------------------------------------- c8 ---
+
+def c8_flops(form, p):
+    """Matrix-core work per cell, counted on the unpadded operand: every
+    entry of P = g^T g that the form needs (scalar Laplace: the upper
+    triangle of each of the three gradient blocks summed; elasticity: upper
+    triangles of the three diagonal blocks and the three full blocks r < s),
+    each a dot product over the n_q points, 2 flops per multiply-add."""
+    nb = (p + 1) ** 3
+    upper = nb * (nb + 1) // 2
+    entries = 3 * upper + (3 * nb * nb if form == "elasticity" else 0)
+    return entries * 2 * nb
+
+
+def run_c8(args, orc):
+    import torch
+    import meshgen
+    import paper_2107_04121_amd as fe
+    dev = torch.device("cuda:0")
+    dims = (16, 8, 8)
+    paths = {}
+    keep = {}
+    for p in (4, 5):
+        mesh = meshgen.hex_mesh(dims, p, alpha=0.15, seed=0, box=(16.0, 8.0, 8.0),
+                                curved=0.02 if p == 4 else 0.005)
+        lm = meshgen.lame_cell(mesh.n_cells, seed=0)
+        X = torch.from_numpy(mesh.coords).to(dev)
+        C = torch.from_numpy(mesh.conn).to(dev)
+        idx = sample_cells(mesh.n_cells, 12)
+        sub = submesh(mesh, idx)
+        keep[p] = (mesh, lm)
+        for form in ("laplace", "elasticity"):
+            kind = "iso_cell" if form == "elasticity" else None
+            nc = 3 if form == "elasticity" else 1
+            nd = nc * mesh.n_basis
+            U = meshgen.dofs(mesh.n_nodes, nc, seed=0)
+            refs = {"matrix": orc.matrix(sub, form, lm[idx] if kind else None, kind),
+                    "residual": orc.residual(sub, form, U, lm[idx] if kind else None, kind)}
+            for mode, precs in (("matrix", ("fp64", "fp32", "bf16x3")), ("residual", ("fp64", "fp32"))):
+                for prec in precs:
+                    primary = (p == 5 and form == "elasticity" and mode == "matrix"
+                               and prec == args.precision)
+                    if args.no_extra and not primary:
+                        continue
+                    plan = fe.Plan("hex", p, form, mode, prec, material=kind)
+                    dt = plan.dtype
+                    M = torch.from_numpy(lm).to(dev).to(dt) if kind else None
+                    Ud = torch.from_numpy(U).to(dev).to(dt) if mode == "residual" else None
+                    out = torch.empty(plan.out_shape(mesh.n_cells), dtype=dt, device=dev)
+                    wall, per = time_calls(lambda: plan(X, C, material=M, dofs=Ud, out=out),
+                                           args.steps, args.warmup)
+                    plan.check()
+                    kms = mean(per)
+                    esz = out.element_size()
+                    outb = nd * nd * esz if mode == "matrix" else nd * esz
+                    bpc = (outb + mesh.n_basis * 4 + (2 * esz if kind else 0)
+                           + mesh.n_nodes * (24 + (nc * esz if mode == "residual" else 0)) / mesh.n_cells)
+                    err = rel_err(out[torch.as_tensor(idx, device=dev)].cpu().numpy(), refs[mode])
+                    r = dict(kernel_ms=kms, ms_per_step=wall * 1e3 / args.steps,
+                             gelem_s=mesh.n_cells / (wall / args.steps) / 1e9,
+                             hbm_gbs=bpc * mesh.n_cells / (kms * 1e-3) / 1e9,
+                             alg_bytes_per_cell=bpc, variant=plan.variant, max_rel_err=err)
+                    if mode == "matrix":
+                        tf = c8_flops(form, p) * mesh.n_cells / (kms * 1e-3) / 1e12
+                        r.update(mfma_tflops=tf, mfma_frac=tf / MFMA_PEAK_TFLOPS[prec],
+                                 flops_per_cell=c8_flops(form, p))
+                    paths[f"q{p}/{form}/{mode}/{prec}"] = r
+                    del out
+                    torch.cuda.empty_cache()
+    prim = paths[f"q5/elasticity/matrix/{args.precision}"]
+    line = base_line(args, prim["gelem_s"], prim["ms_per_step"],
+                     {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[args.precision],
+                     dict(workload="orders 4-5 of the table of cell and DOF counts: 1,024 "
+                          "hexahedra (16 x 8 x 8 unit cells); primary Q5 linear-elasticity "
+                          "element matrices (216 nodes, 648 DOFs, 6x6x6 Gauss, 3.4 GB in FP64)",
+                          cells=1024, order=5, n_basis=216, n_qp=216, alpha=0.15, seed=0,
+                          material="per-cell lambda,mu lognormal(0,0.5)"))
+    line["max_rel_err_vs_fp64_oracle"] = prim["max_rel_err"]
+    line["roofline"] = {"bound": "mfma", "achieved": prim["mfma_tflops"],
+                        "peak": MFMA_PEAK_TFLOPS[args.precision], "unit": "TFLOP/s",
+                        "frac": prim["mfma_frac"],
+                        "traffic": (traffic("k_hexmc<5,3,0>") if args.precision == "fp64" else None),
+                        "kernel": "k_hexmc<5,elasticity>", "kernel_ms": prim["kernel_ms"],
+                        "flops_per_cell": prim["flops_per_cell"],
+                        "hbm_frac": prim["hbm_gbs"] / HBM_PEAK_GBS}
+    line["paths"] = paths
+    if not args.no_cpu:
+        mesh, lm = keep[5]
+
+        def call(k):
+            t = time.perf_counter()
+            orc.matrix(submesh(mesh, slice(0, k)), "elasticity", lm[:k], "iso_cell")
+            return time.perf_counter() - t
+        rate, k2, reps, tot = oracle_rate(call, mesh.n_cells, args.cpu_seconds)
+        line["cpu_baseline"] = {
+            "value": rate / 1e9, "unit": "GElem/s", "cores": orc.num_threads(), "kind": "oracle",
+            "sample": f"first {k2} cells of the 1,024-cell Q5 mesh x {reps} passes, FP64 "
+                      f"elasticity matrices, {tot:.1f} s"}
+    return line
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -841,7 +949,7 @@ def main():
     oracle.build()
     copy_calibration(args.copy_calibration)
     fn = {"c1": run_c1, "c2": run_c2, "c3": run_c3, "c4": run_c4,
-          "c5": run_c5, "c6": run_c6, "c7": run_c7}[args.config]
+          "c5": run_c5, "c6": run_c6, "c7": run_c7, "c8": run_c8}[args.config]
     line = fn(args, oracle)
     print(json.dumps(line))
     if "error" in line:

@@ -157,6 +157,7 @@ struct HexMM {
     static constexpr int ROWS = NC * NBP;
     static constexpr int NOP = MM == MM_BF16X3 ? 2 : 1;  // operand arrays (hi, lo)
     static constexpr int TS = 17;  // transpose buffer row stride (conflict-free for FP64)
+    static constexpr bool NT_STORE = true;  // tiles bypass the L2 on their way out
     // LDS layout (bytes)
     static constexpr int OFF_TB = 0;  // double B1[N1][N1], D1[N1][N1], w[NQ]
     static constexpr int OFF_X = q2::align16(OFF_TB + (2 * N1 * N1 + NQ) * 8);  // double xs[3][NB], T lm[2]
@@ -280,8 +281,13 @@ __device__ __forceinline__ void store_tile(typename H::T *oc, int row0, int col0
 #pragma unroll
     for (int v = 0; v < 4; v++) {
         const int row = acc_row<MM>(lane, v);
-        if (!H::RAGGED || (row < rl && col < cl))
-            __builtin_nontemporal_store(x[v], oc + static_cast<int64_t>(row0 + row) * H::ND + col0 + col);
+        if (!H::RAGGED || (row < rl && col < cl)) {
+            typename H::T *dst = oc + static_cast<int64_t>(row0 + row) * H::ND + col0 + col;
+            if constexpr (H::NT_STORE)
+                __builtin_nontemporal_store(x[v], dst);
+            else
+                *dst = x[v];
+        }
     }
 }
 
@@ -670,6 +676,7 @@ struct Q3WS {
     static constexpr int ROWS = 3 * NBP;
     static constexpr int NOP = MM == MM_BF16X3 ? 2 : 1;
     static constexpr int TS = 17;
+    static constexpr bool NT_STORE = true;
     static constexpr int OP_BYTES = q2::align16(ROWS * KS * (int)sizeof(OPT));  // one array of one half
     static constexpr int CONS = WAVES, PROD = 4, THREADS = 64 * (CONS + PROD), QW = KP / PROD;
     static constexpr int OFF_TB = 0;                                   // double B1[16], D1[16], w[64]
@@ -1131,6 +1138,12 @@ struct HexMC {
     static constexpr int NOP = MM == MM_BF16X3 ? 2 : 1;
     static constexpr int OP_N = ROWS * KS;  // entries of one operand array
     static constexpr int TS = 17;
+    // plain stores: a 16-entry row segment of these matrices straddles two
+    // 128-byte lines (rows of 375 or 648 entries, blocks starting at
+    // multiples of 125 or 216), and the L2 joins the halves written by
+    // neighbouring tiles before they go out (measured: Q4 elasticity 30 %
+    // faster in FP32 than with nontemporal stores)
+    static constexpr bool NT_STORE = false;
     static constexpr int OFF_TB = 0;  // double B1[N1][N1], D1[N1][N1], w[NQ]
     static constexpr int OFF_X = q2::align16(OFF_TB + (2 * N1 * N1 + NQ) * 8);  // double xs[3][NB], T lm[2]
     static constexpr int OFF_G = q2::align16(OFF_X + 3 * NB * 8 + 16);          // double [NQ][10] (J: [NQ][9])
