@@ -26,7 +26,7 @@ Other configurations of the same hot path (--config):
   c7  the paper's two other benchmark forms on Q2 hexahedra, 32^3 cells,
       FP64 and FP32: weighted vector dot product (per-point 3x3 M) and
       Navier-Stokes convection (matrix = derivative at u ~ N(0,1)), matrix
-      and residual modes;
+      (on the matrix cores) and residual modes;
   c8  orders 4 and 5 at the paper's cell count for them, 1,024 cells:
       Laplace and elasticity element matrices (FP64 / FP32 / BF16X3, on
       the matrix cores, reported against their peak) and sum-factorized
@@ -819,7 +819,7 @@ def run_c7(args, orc):
                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": prim["hbm_gbs"] / HBM_PEAK_GBS,
                         "traffic": None,
-                        "kernel": "k_matrix<hex,2,convect> (generic)",
+                        "kernel": "k_hexgm<2,convect,fp64>",
                         "kernel_ms": prim["kernel_ms"]}
     line["paths"] = paths
     if not args.no_cpu:

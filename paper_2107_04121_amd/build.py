@@ -23,7 +23,8 @@ HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
 SOURCES = ["api.hip", "reference.cpp", "k_generic_f64.hip",
            "k_generic_f32.hip", "k_mfma.hip", "k_sumfact.hip",
            "k_adjoint.hip", "k_batch.hip", "k_matfirst.hip",
-           "k_cellwise.hip", "k_hexmm.hip", "k_assembly.hip"]
+           "k_cellwise.hip", "k_hexmm.hip", "k_assembly.hip",
+           "k_hexgm.hip"]
 
 
 def _compile(src: str) -> str:

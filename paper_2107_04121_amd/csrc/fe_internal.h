@@ -88,6 +88,7 @@ LaunchFn select_mfma(const Plan &p);
 LaunchFn select_sumfact(const Plan &p);
 LaunchFn select_cellwise(const Plan &p);
 LaunchFn select_hexmm(const Plan &p);
+LaunchFn select_hexgm(const Plan &p);
 
 // Gradient of the elasticity eval value on hexahedra by sum factorization
 // (FE_ERR_UNSUPPORTED when the plan is not covered).

@@ -46,7 +46,7 @@
 //        BF16X3: v_mfma_f32_16x16x32_bf16 on hi*hi + hi*lo + lo*hi.
 // The next cell's connectivity is loaded during step 2, its coordinates
 // during step 4, and parked in LDS at the end of step 4.
-#include "q2_device.h"
+#include "mm_device.h"
 
 namespace fe {
 namespace {
@@ -65,24 +65,11 @@ constexpr int THREADS = 64 * WAVES;
 
 enum : int { J_DIAG = 0, J_PAIR = 1, J_SINGLE = 2, J_LAP = 3, J_MASS = 4 };
 
-constexpr int align_to(int x, int a) { return (x + a - 1) / a * a; }
-
-// LDS row stride (entries) of the operand for a padded depth KP, so that the
-// fragment reads (16 rows x 4 points, or 16 rows x 8 points for bf16) hit
-// distinct banks of the 32 four-byte LDS banks in every pass: FP64 odd,
-// FP32 2 mod 4, bf16 8 mod 16 (measured with the LDS bank-conflict
-// counter).
-constexpr int op_stride(int mm, int kp)
-{
-    int ks = kp;
-    if (mm == MM_F64)
-        while (ks % 2 != 1) ks++;
-    else if (mm == MM_F32)
-        while (ks % 4 != 2) ks++;
-    else
-        while (ks % 16 != 8) ks++;
-    return ks;
-}
+using mm::acc_row;
+using mm::align_to;
+using mm::op_stride;
+using mm::store_tile;
+using mm::valid;
 
 // Static schedule: jobs in order of decreasing weight (matrix-core tiles),
 // each given to the least loaded wave.
@@ -157,7 +144,10 @@ struct HexMM {
     static constexpr int ROWS = NC * NBP;
     static constexpr int NOP = MM == MM_BF16X3 ? 2 : 1;  // operand arrays (hi, lo)
     static constexpr int TS = 17;  // transpose buffer row stride (conflict-free for FP64)
-    static constexpr bool NT_STORE = true;  // tiles bypass the L2 on their way out
+    // nontemporal stores when the tiles' row segments fill whole 128-byte
+    // lines (Q3: rows of 64 or 192 entries); Q2 rows of 27 or 81 entries go
+    // through the L2, which joins the halves of straddled lines
+    static constexpr bool NT_STORE = ND % 16 == 0;
     // LDS layout (bytes)
     static constexpr int OFF_TB = 0;  // double B1[N1][N1], D1[N1][N1], w[NQ]
     static constexpr int OFF_X = q2::align16(OFF_TB + (2 * N1 * N1 + NQ) * 8);  // double xs[3][NB], T lm[2]
@@ -177,13 +167,6 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// accumulator row of element v for this lane (column = lane % 16)
-template <int MM>
-__device__ __forceinline__ int acc_row(int lane, int v)
-{
-    return MM == MM_F64 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v;
 }
 
 // acc[u] += sum over k in [k0, k1) of g[rowsA[u] + m][k] g[rowsB[u] + n][k]
@@ -268,33 +251,6 @@ __device__ __forceinline__ typename H::ACC transpose(const typename H::ACC &x, t
     for (int v = 0; v < 4; v++) y[v] = buf[col * H::TS + acc_row<MM>(lane, v)];
     wave_sync();
     return y;
-}
-
-// store tile (output rows row0.., columns col0..) of one cell's matrix;
-// rl / cl = valid rows / columns of the tile (16 unless the block is ragged)
-template <class H>
-__device__ __forceinline__ void store_tile(typename H::T *oc, int row0, int col0, int rl, int cl,
-                                           const typename H::ACC &x, int lane)
-{
-    constexpr int MM = sizeof(typename H::T) == 8 ? MM_F64 : MM_F32;
-    const int col = lane & 15;
-#pragma unroll
-    for (int v = 0; v < 4; v++) {
-        const int row = acc_row<MM>(lane, v);
-        if (!H::RAGGED || (row < rl && col < cl)) {
-            typename H::T *dst = oc + static_cast<int64_t>(row0 + row) * H::ND + col0 + col;
-            if constexpr (H::NT_STORE)
-                __builtin_nontemporal_store(x[v], dst);
-            else
-                *dst = x[v];
-        }
-    }
-}
-
-template <class H>
-__device__ __forceinline__ int valid(int t)  // valid entries of tile t of a block
-{
-    return H::NB - 16 * t < 16 ? H::NB - 16 * t : 16;
 }
 
 // The elasticity epilogues below evaluate lambda X + mu Y as

@@ -86,6 +86,7 @@ LaunchFn select_mfma(const Plan &p)
         if (p.prec == FE_PREC_FP32) return launch_elast_q2<MM_F32>;
         if (p.prec == FE_PREC_BF16X3) return launch_elast_q2<MM_BF16X3>;
     }
+    if (LaunchFn f = select_hexgm(p)) return f;
     return select_hexmm(p);
 }
 

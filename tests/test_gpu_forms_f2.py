@@ -92,3 +92,37 @@ def test_f2_argument_rules():
     plan = fe.Plan("hex", 1, "convect", "matrix", "fp64")
     with pytest.raises(fe.FeError):
         plan(_t(mesh.coords), _t(mesh.conn))                     # no state u
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("form", ["wdot", "convect"])
+@pytest.mark.parametrize("p", [2, 3])
+def test_forms_f2_matrix_cores_many_cells(orc, p, form, prec):
+    """Q2/Q3 matrices of the two forms on the matrix cores, on more cells
+    than the persistent grid has workgroups: sampled cells against the
+    oracle, every cell against the generic kernel."""
+    import torch
+    import paper_2107_04121_amd as fe
+    dims = {2: (11, 10, 10), 3: (9, 8, 8)}[p]
+    mesh = meshgen.hex_mesh(dims, p, alpha=0.15, seed=44 + p, curved=0.04)
+    nb, nq = orc.sizes("hex", p)
+    kind = "tensor_qp" if form == "wdot" else None
+    M = meshgen.tensor_qp(mesh.n_cells, nq, seed=45) if kind else None
+    U = meshgen.dofs(mesh.n_nodes, 3, seed=46)
+    plan = fe.Plan("hex", p, form, "matrix", prec, material=kind)
+    print(f"[f2] many cells Q{p} {form} {prec} variant={plan.variant} cells={mesh.n_cells}", flush=True)
+    assert plan.variant == "mfma"
+    dt = plan.dtype
+    X, C, Ud = _t(mesh.coords), _t(mesh.conn), _t(U, dt)
+    Md = None if M is None else _t(M, dt)
+    K = plan(X, C, material=Md, dofs=Ud)
+    plan.check()
+    gen = fe.Plan("hex", p, form, "matrix", prec, material=kind, variant="generic")
+    Kg = gen(X, C, material=Md, dofs=Ud)
+    gen.check()
+    assert _err(K.cpu().numpy(), Kg.double().cpu().numpy()) < TOL[prec]
+    rng = np.random.default_rng(7)
+    idx = np.unique(np.concatenate([rng.choice(mesh.n_cells, 20, replace=False), [0, mesh.n_cells - 1]]))
+    sub = meshgen.Mesh(coords=mesh.coords, conn=mesh.conn[idx], cell="hex", order=p, h=mesh.h)
+    ref = orc.matrix(sub, form, None if M is None else M[idx], kind, u=U)
+    assert _err(K[torch.as_tensor(idx, device=K.device)].cpu().numpy(), ref) < TOL[prec]
