@@ -28,6 +28,11 @@
 // Output layouts: cell-major [n_cells][n_comp][n_b] (default) or cell-minor
 // [n_comp][n_b][n_cells].
 //
+// The weighted vector dot product and the convection use the same passes
+// with value-type test functions: the flux at a point is w det J M u or
+// w det J (u . grad) u, the latter from both the values and the gradients
+// of u at the points.
+//
 // ADJ (elasticity only): the gradient of the eval value J = sum u^T K u.
 // The same geometry and gradient passes, then at every point
 //   dJ/dlambda = w det (tr eps)^2,  dJ/dmu = 2 w det eps:eps,
@@ -59,7 +64,11 @@ struct SF {
     static constexpr int CW = 64 / NPL;  // cells per wave
     static constexpr int CB = 4 * CW;    // cells per 256-thread workgroup
     static constexpr int NC = form_nc(FORM);
+    // gradient test functions (and gradients of u); the other forms test
+    // with values
     static constexpr bool GRAD = FORM == FE_FORM_LAPLACE || FORM == FE_FORM_ELASTICITY;
+    static constexpr bool UGRAD = GRAD || FORM == FE_FORM_CONVECT;  // gradients of u at the points
+    static constexpr bool UVAL = !GRAD;                            // values of u at the points
     // stage-array layout (see idx).  Q3: a dense XOR-swizzled 4x4x4 block,
     // no bank conflicts.  Q2: plane stride 20, array stride 49 and cell
     // stride 153 doubles, the best of a search over strides for the bank
@@ -202,7 +211,7 @@ __global__ __launch_bounds__(256) void k_sf(ExecArgs A, int cell_minor, T *gmat,
 {
     using S = SF<P, FORM, T>;
     constexpr int N1 = S::N1, NPL = S::NPL, NP = S::NP, CW = S::CW, NC = S::NC, ZS = S::ZS, AS = S::AS;
-    constexpr bool GRAD = S::GRAD;
+    constexpr bool GRAD = S::GRAD, UGRAD = S::UGRAD, UVAL = S::UVAL;
     __shared__ double lds[S::CB * S::CELL];
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -287,22 +296,24 @@ __global__ __launch_bounds__(256) void k_sf(ExecArgs A, int cell_minor, T *gmat,
             for (int d = 0; d < 3; d++) Ji[q][j][d] = static_cast<T>(Jid[j][d]);
     }
 
-    // ---- u at the points: reference gradients (GRAD) or values
+    // ---- u at the points: reference gradients and/or values
     T gx[N1][NC][3], val[N1][NC];
 #pragma unroll
     for (int c = 0; c < NC; c++) {
         T f[N1], g[N1][3], v[N1];
 #pragma unroll
         for (int a = 0; a < N1; a++) f[a] = U[a][c];
-        forward3<N1, ZS, AS, GRAD>(f, Lt, tt, p0, p1, slot, g, v);
+        if constexpr (UGRAD) {
+            forward3<N1, ZS, AS, true>(f, Lt, tt, p0, p1, slot, g, v);
 #pragma unroll
-        for (int q = 0; q < N1; q++) {
-            if constexpr (GRAD) {
+            for (int q = 0; q < N1; q++)
 #pragma unroll
                 for (int j = 0; j < 3; j++) gx[q][c][j] = g[q][j];
-            } else {
-                val[q][c] = v[q];
-            }
+        }
+        if constexpr (UVAL) {
+            forward3<N1, ZS, AS, false>(f, Lt, tt, p0, p1, slot, g, v);
+#pragma unroll
+            for (int q = 0; q < N1; q++) val[q][c] = v[q];
         }
     }
 
@@ -400,6 +411,33 @@ __global__ __launch_bounds__(256) void k_sf(ExecArgs A, int cell_minor, T *gmat,
 #pragma unroll
                 for (int j = 0; j < 3; j++)
                     F[q][c][j] = wd[q] * (Ji[q][j][0] * Sg[c][0] + Ji[q][j][1] * Sg[c][1] + Ji[q][j][2] * Sg[c][2]);
+        } else if constexpr (FORM == FE_FORM_WDOT) {
+            // flux w det J M u (M row-major per point)
+            T m[9] = {};
+            if (live) {
+                const T *mp = mat + (e * NP + pp + NPL * q) * 9;
+#pragma unroll
+                for (int k = 0; k < 9; k++) m[k] = mp[k];
+            }
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                const T mu = m[3 * c] * val[q][0] + m[3 * c + 1] * val[q][1] + m[3 * c + 2] * val[q][2];
+                F[q][c][0] = wd[q] * mu;
+                energy += wd[q] * val[q][c] * mu;
+            }
+        } else if constexpr (FORM == FE_FORM_CONVECT) {
+            // flux w det J (u . grad) u, grad u = (du/dxi) J^-1
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                T adv = T(0);
+#pragma unroll
+                for (int d = 0; d < 3; d++) {
+                    const T h = gx[q][c][0] * Ji[q][0][d] + gx[q][c][1] * Ji[q][1][d] + gx[q][c][2] * Ji[q][2][d];
+                    adv += val[q][d] * h;
+                }
+                F[q][c][0] = wd[q] * adv;
+                energy += wd[q] * val[q][c] * adv;
+            }
         } else {
 #pragma unroll
             for (int c = 0; c < NC; c++) {
@@ -560,6 +598,8 @@ LaunchFn pick(int form)
     case FE_FORM_VMASS: return launch_sf<P, FE_FORM_VMASS, T>;
     case FE_FORM_LAPLACE: return launch_sf<P, FE_FORM_LAPLACE, T>;
     case FE_FORM_ELASTICITY: return launch_sf<P, FE_FORM_ELASTICITY, T>;
+    case FE_FORM_WDOT: return launch_sf<P, FE_FORM_WDOT, T>;
+    case FE_FORM_CONVECT: return launch_sf<P, FE_FORM_CONVECT, T>;
     }
     return nullptr;
 }

@@ -126,3 +126,37 @@ def test_forms_f2_matrix_cores_many_cells(orc, p, form, prec):
     sub = meshgen.Mesh(coords=mesh.coords, conn=mesh.conn[idx], cell="hex", order=p, h=mesh.h)
     ref = orc.matrix(sub, form, None if M is None else M[idx], kind, u=U)
     assert _err(K[torch.as_tensor(idx, device=K.device)].cpu().numpy(), ref) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("form", ["wdot", "convect"])
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_forms_f2_residual_sumfact_vs_generic(orc, p, form, prec):
+    """Hex residuals and evals of the two forms: the sum-factorized kernel
+    (cell-major and cell-minor output) against the generic kernel and the
+    oracle."""
+    import paper_2107_04121_amd as fe
+    mesh = _mesh("hex", p, True)
+    nb, nq = orc.sizes("hex", p)
+    kind = "tensor_qp" if form == "wdot" else None
+    M = meshgen.tensor_qp(mesh.n_cells, nq, seed=51) if kind else None
+    U = meshgen.dofs(mesh.n_nodes, 3, seed=52)
+    X, C = _t(mesh.coords), _t(mesh.conn)
+    ref = orc.residual(mesh, form, U, M, kind)
+    outs = {}
+    for variant, layout in (("auto", "cell_major"), ("auto", "cell_minor"), ("generic", "cell_major")):
+        plan = fe.Plan("hex", p, form, "residual", prec, material=kind, variant=variant, layout=layout)
+        assert plan.variant == ("sumfact" if variant == "auto" else "generic")
+        out = plan(X, C, material=None if M is None else _t(M, plan.dtype), dofs=_t(U, plan.dtype))
+        plan.check()
+        got = out.cpu().numpy()
+        if layout == "cell_minor":
+            got = np.moveaxis(got, -1, 0)
+        outs[(variant, layout)] = got
+        assert _err(got, ref) < TOL[prec], (variant, layout)
+    assert np.array_equal(outs[("auto", "cell_major")], outs[("auto", "cell_minor")])
+    ev = fe.Plan("hex", p, form, "eval", prec, material=kind)
+    assert ev.variant == "sumfact"
+    e = ev(X, C, material=None if M is None else _t(M, ev.dtype), dofs=_t(U, ev.dtype)).cpu().numpy()
+    ref_e = orc.energy(mesh, form, U, M, kind)
+    assert float(np.abs(e - ref_e).max() / np.abs(ref_e).max()) < TOL[prec]

@@ -1,8 +1,8 @@
 """Orders 4 and 5 on hexahedra (the highest orders of the paper's table of
 cell and DOF counts) through the C ABI against the FP64 oracle: residual
-and eval by sum factorization in both output layouts, the adjoint of the
-elastic energy, and the forms without a kernel at these orders refused at
-plan creation.  Meshes span several workgroups with a ragged tail (Q4: two
+and eval by sum factorization in both output layouts (all six forms), the
+adjoint of the elastic energy, element matrices on the matrix cores, and
+the plans without a kernel at these orders refused at plan creation.  Meshes span several workgroups with a ragged tail (Q4: two
 cells per wave, eight per workgroup; Q5: one per wave, four per workgroup);
 the curvature noise is scaled down with the order so that every Jacobian
 stays positive."""
@@ -98,9 +98,33 @@ def test_energy_grad(orc, p, dims, curved, prec):
     assert em < TOL[prec] and ex < TOL[prec], (em, ex)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("form,kind", [("wdot", "tensor_qp"), ("convect", None)])
+@pytest.mark.parametrize("p,dims,curved", HIGH)
+def test_forms_f2_residual_and_eval(orc, p, dims, curved, form, kind, prec):
+    """The weighted dot and the convection at orders 4-5 (residual and eval,
+    sum-factorized), against the oracle."""
+    import paper_2107_04121_amd as fe
+    mesh = _mesh(p, dims, curved, seed=48)
+    nb, nq = orc.sizes("hex", p)
+    M = meshgen.tensor_qp(mesh.n_cells, nq, seed=49) if kind else None
+    U = meshgen.dofs(mesh.n_nodes, 3, seed=50)
+    X, C = _t(mesh.coords), _t(mesh.conn)
+    refs = {"residual": orc.residual(mesh, form, U, M, kind), "eval": orc.energy(mesh, form, U, M, kind)}
+    for mode, ref in refs.items():
+        plan = fe.Plan("hex", p, form, mode, prec, material=kind)
+        print(f"[high] {mode} Q{p} {form} {prec} variant={plan.variant}", flush=True)
+        assert plan.variant == "sumfact"
+        out = plan(X, C, material=None if M is None else _t(M, plan.dtype), dofs=_t(U, plan.dtype))
+        plan.check()
+        got = out.cpu().numpy()
+        err = (float(np.abs(got - ref).max() / np.abs(ref).max()) if mode == "eval" else elem_rel_err(got, ref))
+        assert err < TOL[prec], (mode, err)
+
+
 @pytest.mark.parametrize("form,kind,mode", [("elasticity", "voigt_qp", "residual"),
-                                            ("wdot", "tensor_qp", "residual"),
-                                            ("convect", None, "residual")])
+                                            ("wdot", "tensor_qp", "matrix"),
+                                            ("convect", None, "matrix")])
 def test_forms_without_kernel_refused(form, kind, mode):
     import paper_2107_04121_amd as fe
     for p in (4, 5):
