@@ -27,10 +27,11 @@ Other configurations of the same hot path (--config):
       FP64 and FP32: weighted vector dot product (per-point 3x3 M) and
       Navier-Stokes convection (matrix = derivative at u ~ N(0,1)), matrix
       (on the matrix cores) and residual modes;
-  c8  orders 4 and 5 at the paper's cell count for them, 1,024 cells:
-      Laplace and elasticity element matrices (FP64 / FP32 / BF16X3, on
-      the matrix cores, reported against their peak) and sum-factorized
-      residuals; primary Q5 elasticity matrices.
+  c8  orders 4 and 5 at the paper's cell count for them, 1,024 cells: the
+      paper's five forms (Laplace, vector dot, weighted dot, convection,
+      elasticity) as element matrices (on the matrix cores, reported against
+      their peak) and sum-factorized residuals; primary Q5 elasticity
+      matrices.
 Every configuration prints one JSON line.
 """
 from __future__ import annotations
@@ -845,14 +846,17 @@ def run_c7(args, orc):
 # ------------------------------------------------------------------- c8 ---
 
 def c8_flops(form, p):
-    """Matrix-core work per cell, counted on the unpadded operand: every
-    entry of P = g^T g that the form needs (scalar Laplace: the upper
-    triangle of each of the three gradient blocks summed; elasticity: upper
-    triangles of the three diagonal blocks and the three full blocks r < s),
-    each a dot product over the n_q points, 2 flops per multiply-add."""
+    """Matrix-core work per cell, counted on the unpadded operands, 2 flops
+    per multiply-add over the n_q points: the entries each form needs of its
+    products (scalar Laplace: the upper triangle of each of the three
+    gradient blocks summed; vector mass: the upper triangle of the scalar
+    mass; elasticity: upper triangles of the three diagonal blocks of
+    P = g^T g and the three full blocks r < s; weighted dot and convection:
+    the nine full blocks Phi^T W_rs)."""
     nb = (p + 1) ** 3
     upper = nb * (nb + 1) // 2
-    entries = 3 * upper + (3 * nb * nb if form == "elasticity" else 0)
+    entries = {"laplace": 3 * upper, "vmass": upper, "elasticity": 3 * upper + 3 * nb * nb,
+               "wdot": 9 * nb * nb, "convect": 9 * nb * nb}[form]
     return entries * 2 * nb
 
 
@@ -873,14 +877,18 @@ def run_c8(args, orc):
         idx = sample_cells(mesh.n_cells, 12)
         sub = submesh(mesh, idx)
         keep[p] = (mesh, lm)
-        for form in ("laplace", "elasticity"):
-            kind = "iso_cell" if form == "elasticity" else None
-            nc = 3 if form == "elasticity" else 1
+        Mt = meshgen.tensor_qp(mesh.n_cells, mesh.n_basis, seed=0)
+        for form in ("laplace", "vmass", "wdot", "convect", "elasticity"):
+            kind = {"elasticity": "iso_cell", "wdot": "tensor_qp"}.get(form)
+            mat = {"iso_cell": lm, "tensor_qp": Mt}.get(kind)
+            nc = 1 if form == "laplace" else 3
             nd = nc * mesh.n_basis
             U = meshgen.dofs(mesh.n_nodes, nc, seed=0)
-            refs = {"matrix": orc.matrix(sub, form, lm[idx] if kind else None, kind),
-                    "residual": orc.residual(sub, form, U, lm[idx] if kind else None, kind)}
-            for mode, precs in (("matrix", ("fp64", "fp32", "bf16x3")), ("residual", ("fp64", "fp32"))):
+            refs = {"matrix": orc.matrix(sub, form, mat[idx] if kind else None, kind,
+                                         u=U if form == "convect" else None),
+                    "residual": orc.residual(sub, form, U, mat[idx] if kind else None, kind)}
+            mprecs = ("fp64", "fp32") if form in ("wdot", "convect") else ("fp64", "fp32", "bf16x3")
+            for mode, precs in (("matrix", mprecs), ("residual", ("fp64", "fp32"))):
                 for prec in precs:
                     primary = (p == 5 and form == "elasticity" and mode == "matrix"
                                and prec == args.precision)
@@ -888,8 +896,9 @@ def run_c8(args, orc):
                         continue
                     plan = fe.Plan("hex", p, form, mode, prec, material=kind)
                     dt = plan.dtype
-                    M = torch.from_numpy(lm).to(dev).to(dt) if kind else None
-                    Ud = torch.from_numpy(U).to(dev).to(dt) if mode == "residual" else None
+                    M = torch.from_numpy(mat).to(dev).to(dt) if kind else None
+                    Ud = (torch.from_numpy(U).to(dev).to(dt)
+                          if mode == "residual" or form == "convect" else None)
                     out = torch.empty(plan.out_shape(mesh.n_cells), dtype=dt, device=dev)
                     wall, per = time_calls(lambda: plan(X, C, material=M, dofs=Ud, out=out),
                                            args.steps, args.warmup)
@@ -897,8 +906,9 @@ def run_c8(args, orc):
                     kms = mean(per)
                     esz = out.element_size()
                     outb = nd * nd * esz if mode == "matrix" else nd * esz
-                    bpc = (outb + mesh.n_basis * 4 + (2 * esz if kind else 0)
-                           + mesh.n_nodes * (24 + (nc * esz if mode == "residual" else 0)) / mesh.n_cells)
+                    matb = {"iso_cell": 2 * esz, "tensor_qp": 9 * mesh.n_basis * esz}.get(kind, 0)
+                    bpc = (outb + mesh.n_basis * 4 + matb
+                           + mesh.n_nodes * (24 + (nc * esz if Ud is not None else 0)) / mesh.n_cells)
                     err = rel_err(out[torch.as_tensor(idx, device=dev)].cpu().numpy(), refs[mode])
                     r = dict(kernel_ms=kms, ms_per_step=wall * 1e3 / args.steps,
                              gelem_s=mesh.n_cells / (wall / args.steps) / 1e9,

@@ -84,6 +84,100 @@ struct HexGM {
     static_assert(BYTES * MINB <= 160 * 1024, "LDS");
 };
 
+// The cell's coordinates into xs[3][NB], and its DOFs into us[3][NB]
+// (convection) or its per-point M into Ms[NQ][9] (weighted dot).
+template <class H>
+__device__ __forceinline__ void gm_gather(const ExecArgs &A, int64_t e, double *xs, double *us, double *Ms, int tid)
+{
+    using T = typename H::T;
+    constexpr int NB = H::NB, NQ = H::NQ;
+    const T *mat = static_cast<const T *>(A.mat);
+    const T *Ug = static_cast<const T *>(A.dofs);
+    for (int k = tid; k < 3 * NB; k += GM_THREADS) {
+        const int a = k / 3, c = k - 3 * a;
+        const int64_t n = checked_node(A.conn, e * NB + a, A.n_nodes, A.flags);
+        xs[c * NB + a] = A.coords[3 * n + c];
+        if constexpr (H::CONV) us[c * NB + a] = static_cast<double>(Ug[n * 3 + c]);
+    }
+    if constexpr (!H::CONV)
+        for (int k = tid; k < NQ * 9; k += GM_THREADS) Ms[k] = static_cast<double>(mat[e * NQ * 9 + k]);
+}
+
+// Per-point data of the cell in Pq[NQ][PS] (F[NF][NQ]: scratch):
+//   1. entry f at point q by sum factorization: f < 9: dx_i/dxi_j
+//      (i = f / 3, j = f % 3); 9 <= f < 18: du_i/dxi_j; 18 <= f < 21: u_i;
+//   2. the block coefficients c_rs and, for the convection, w det J v.
+// Contains one barrier, between the two steps.
+template <class H>
+__device__ __forceinline__ void gm_points(const ExecArgs &A, const double *B1, const double *D1, const double *wq,
+                                          const double *xs, const double *us, const double *Ms, double *F, double *Pq,
+                                          int tid)
+{
+    constexpr int N1 = H::N1, NB = H::NB, NQ = H::NQ, NF = H::NF, PS = H::PS;
+    static_assert(NQ <= GM_THREADS, "one point per thread in step 2");
+    // 1. entry f at point q: f < 9: dx_i/dxi_j (i = f / 3, j = f % 3);
+    //    9 <= f < 18: du_i/dxi_j; 18 <= f < 21: u_i
+    for (int it = tid; it < NF * NQ; it += GM_THREADS) {
+        const int q = it % NQ, f = it / NQ;
+        const int q0 = q % N1, q1 = (q / N1) % N1, q2 = q / (N1 * N1);
+        const double *src = f < 9 ? xs + (f / 3) * NB : (f < 18 ? us + ((f - 9) / 3) * NB : us + (f - 18) * NB);
+        const int j = f < 18 ? f % 3 : -1;
+        const double *T0 = (j == 0 ? D1 : B1) + q0 * N1;
+        const double *T1 = (j == 1 ? D1 : B1) + q1 * N1;
+        const double *T2 = (j == 2 ? D1 : B1) + q2 * N1;
+        double s2 = 0.0;
+#pragma unroll
+        for (int a2 = 0; a2 < N1; a2++) {
+            double s1 = 0.0;
+#pragma unroll
+            for (int a1 = 0; a1 < N1; a1++) {
+                const double *xr = src + N1 * (a1 + N1 * a2);
+                double s0 = 0.0;
+#pragma unroll
+                for (int a0 = 0; a0 < N1; a0++) s0 = fma(T0[a0], xr[a0], s0);
+                s1 = fma(T1[a1], s0, s1);
+            }
+            s2 = fma(T2[a2], s1, s2);
+        }
+        F[f * NQ + q] = s2;
+    }
+    __syncthreads();
+
+    // 2. per point: the block coefficients c_rs and, for the convection,
+    //    w det J v
+    if (tid < NQ) {
+        const int q = tid;
+        double J[3][3], Ji[3][3];
+#pragma unroll
+        for (int r = 0; r < 3; r++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) J[r][c] = F[(r * 3 + c) * NQ + q];
+        const double det = inverse3(J, Ji);
+        if (!(det > 0.0)) raise_fault(A.flags, FAULT_DET);
+        const double wd = wq[q] * det;
+        double *pq = Pq + q * PS;
+        if constexpr (H::CONV) {
+            double u[3];
+#pragma unroll
+            for (int s = 0; s < 3; s++) u[s] = F[(18 + s) * NQ + q];
+#pragma unroll
+            for (int j = 0; j < 3; j++) pq[9 + j] = wd * (Ji[j][0] * u[0] + Ji[j][1] * u[1] + Ji[j][2] * u[2]);
+#pragma unroll
+            for (int r = 0; r < 3; r++)
+#pragma unroll
+                for (int s = 0; s < 3; s++) {
+                    double g = 0.0;
+#pragma unroll
+                    for (int j = 0; j < 3; j++) g = fma(F[(9 + r * 3 + j) * NQ + q], Ji[j][s], g);
+                    pq[r * 3 + s] = wd * g;
+                }
+        } else {
+#pragma unroll
+            for (int rs = 0; rs < 9; rs++) pq[rs] = wd * Ms[q * 9 + rs];
+        }
+    }
+}
+
 template <int P, int FORM, int MM>
 __global__ __launch_bounds__(GM_THREADS, (2 * HexGM<P, FORM, MM>::MINB)) void k_hexgm(ExecArgs A)
 {
@@ -91,7 +185,7 @@ __global__ __launch_bounds__(GM_THREADS, (2 * HexGM<P, FORM, MM>::MINB)) void k_
     using T = typename H::T;
     using ACC = typename H::ACC;
     constexpr int N1 = H::N1, NB = H::NB, NQ = H::NQ, NBP = H::NBP, NT = H::NT, KP = H::KP, KS = H::KS;
-    constexpr int G = H::G, NF = H::NF, PS = H::PS, NJ = H::NJ;
+    constexpr int G = H::G, PS = H::PS, NJ = H::NJ;
     constexpr bool CONV = H::CONV;
     __shared__ __align__(16) unsigned char smem[H::BYTES];
     double *B1 = reinterpret_cast<double *>(smem + H::OFF_TB);
@@ -111,8 +205,6 @@ __global__ __launch_bounds__(GM_THREADS, (2 * HexGM<P, FORM, MM>::MINB)) void k_
     int64_t e, e_end, stride;
     cell_range(A.xcd_remap, A.n_cells, e, e_end, stride);
     if (e >= e_end) return;  // uniform over the workgroup
-    const T *mat = static_cast<const T *>(A.mat);
-    const T *Ug = static_cast<const T *>(A.dofs);
 
     for (int k = tid; k < N1 * N1; k += GM_THREADS) {
         B1[k] = A.tab.B1[k];
@@ -133,78 +225,10 @@ __global__ __launch_bounds__(GM_THREADS, (2 * HexGM<P, FORM, MM>::MINB)) void k_
     }
 
     for (; e < e_end; e += stride) {
-        for (int k = tid; k < 3 * NB; k += GM_THREADS) {
-            const int a = k / 3, c = k - 3 * a;
-            const int64_t n = checked_node(A.conn, e * NB + a, A.n_nodes, A.flags);
-            xs[c * NB + a] = A.coords[3 * n + c];
-            if constexpr (CONV) us[c * NB + a] = static_cast<double>(Ug[n * 3 + c]);
-        }
-        if constexpr (!CONV)
-            for (int k = tid; k < NQ * 9; k += GM_THREADS) Ms[k] = static_cast<double>(mat[e * NQ * 9 + k]);
+        gm_gather<H>(A, e, xs, us, Ms, tid);
         __syncthreads();
-
-        // 1. entry f at point q: f < 9: dx_i/dxi_j (i = f / 3, j = f % 3);
-        //    9 <= f < 18: du_i/dxi_j; 18 <= f < 21: u_i
-        for (int it = tid; it < NF * NQ; it += GM_THREADS) {
-            const int q = it % NQ, f = it / NQ;
-            const int q0 = q % N1, q1 = (q / N1) % N1, q2 = q / (N1 * N1);
-            const double *src = f < 9 ? xs + (f / 3) * NB : (f < 18 ? us + ((f - 9) / 3) * NB : us + (f - 18) * NB);
-            const int j = f < 18 ? f % 3 : -1;
-            const double *T0 = (j == 0 ? D1 : B1) + q0 * N1;
-            const double *T1 = (j == 1 ? D1 : B1) + q1 * N1;
-            const double *T2 = (j == 2 ? D1 : B1) + q2 * N1;
-            double s2 = 0.0;
-#pragma unroll
-            for (int a2 = 0; a2 < N1; a2++) {
-                double s1 = 0.0;
-#pragma unroll
-                for (int a1 = 0; a1 < N1; a1++) {
-                    const double *xr = src + N1 * (a1 + N1 * a2);
-                    double s0 = 0.0;
-#pragma unroll
-                    for (int a0 = 0; a0 < N1; a0++) s0 = fma(T0[a0], xr[a0], s0);
-                    s1 = fma(T1[a1], s0, s1);
-                }
-                s2 = fma(T2[a2], s1, s2);
-            }
-            F[f * NQ + q] = s2;
-        }
-        __syncthreads();
-
-        // 2. per point: the block coefficients c_rs and, for the convection,
-        //    w det J v
-        if (tid < NQ) {
-            const int q = tid;
-            double J[3][3], Ji[3][3];
-#pragma unroll
-            for (int r = 0; r < 3; r++)
-#pragma unroll
-                for (int c = 0; c < 3; c++) J[r][c] = F[(r * 3 + c) * NQ + q];
-            const double det = inverse3(J, Ji);
-            if (!(det > 0.0)) raise_fault(A.flags, FAULT_DET);
-            const double wd = wq[q] * det;
-            double *pq = Pq + q * PS;
-            if constexpr (CONV) {
-                double u[3];
-#pragma unroll
-                for (int s = 0; s < 3; s++) u[s] = F[(18 + s) * NQ + q];
-#pragma unroll
-                for (int j = 0; j < 3; j++) pq[9 + j] = wd * (Ji[j][0] * u[0] + Ji[j][1] * u[1] + Ji[j][2] * u[2]);
-#pragma unroll
-                for (int r = 0; r < 3; r++)
-#pragma unroll
-                    for (int s = 0; s < 3; s++) {
-                        double g = 0.0;
-#pragma unroll
-                        for (int j = 0; j < 3; j++) g = fma(F[(9 + r * 3 + j) * NQ + q], Ji[j][s], g);
-                        pq[r * 3 + s] = wd * g;
-                    }
-            } else {
-#pragma unroll
-                for (int rs = 0; rs < 9; rs++) pq[rs] = wd * Ms[q * 9 + rs];
-            }
-        }
-        __syncthreads();  // F (in W's space) is read for the last time above
+        gm_points<H>(A, B1, D1, wq, xs, us, Ms, F, Pq, tid);
+        __syncthreads();  // F (in W's space) is read for the last time in gm_points
 
         T *oc = static_cast<T *>(A.out) + e * static_cast<int64_t>(H::ND) * H::ND;
         for (int g = 0; g < H::NGRP; g++) {
@@ -289,28 +313,219 @@ __global__ __launch_bounds__(GM_THREADS, (2 * HexGM<P, FORM, MM>::MINB)) void k_
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Q4 and Q5: the points in chunks.
+//
+// Phi (224 x 216 at Q5) and the nine W blocks no longer fit in LDS.  The
+// per-point coefficients are computed once per cell as above; the output
+// tiles (nine blocks of NT x NT) are taken in passes of 8 NJ tiles, NJ
+// accumulators per wave (16 FP64 / 32 FP32 tiles) that stay in registers
+// while the points go by in chunks of KC = 16:
+//   for each pass: for each chunk: Phi chunk (read from the basis table,
+//   the same for every cell) and the W chunks of the pass's blocks in LDS;
+//   barrier; products; barrier; then the tiles are stored.
+constexpr int gmc_cap(int mm) { return mm == MM_F64 ? 16 : 32; }
+
 template <int P, int FORM, int MM>
-int launch_hexgm(const Plan &, const ExecArgs &A, hipStream_t st)
+struct HexGMC {
+    static constexpr int N1 = P + 1, NB = N1 * N1 * N1, NQ = NB;
+    static constexpr int ND = 3 * NB;
+    static constexpr int NBP = align_to(NB, 16), NT = NBP / 16, TPB = NT * NT;
+    static constexpr bool RAGGED = NB % 16 != 0;
+    static constexpr bool NT_STORE = ND % 16 == 0;
+    using T = typename MMT<MM>::T;
+    using ACC = typename MMT<MM>::acc;
+    static constexpr int KC = 16, NCH = (NQ + KC - 1) / KC, KS = op_stride(MM, KC);
+    static constexpr int NTILES = 9 * TPB;
+    static constexpr int NPASS = (NTILES + GM_WAVES * gmc_cap(MM) - 1) / (GM_WAVES * gmc_cap(MM));
+    static constexpr int NJ = (NTILES + GM_WAVES * NPASS - 1) / (GM_WAVES * NPASS);  // tiles per wave and pass
+    static constexpr int PT = GM_WAVES * NJ;                                          // tiles per pass
+    static constexpr int WB = (PT + TPB - 1) / TPB + 1 < 9 ? (PT + TPB - 1) / TPB + 1 : 9;  // blocks a pass touches
+    static constexpr bool CONV = FORM == FE_FORM_CONVECT;
+    static constexpr int NF = CONV ? 21 : 9;
+    static constexpr int PS = CONV ? 12 : 9;
+    // LDS layout (bytes); F (sum-factorization scratch) shares the space of
+    // the Phi and W chunks, free between the last products of a cell and the
+    // first chunk of the next
+    static constexpr int OFF_TB = 0;  // double B1[N1][N1], D1[N1][N1], w[NQ]
+    static constexpr int OFF_X = q2::align16(OFF_TB + (2 * N1 * N1 + NQ) * 8);
+    static constexpr int OFF_P = q2::align16(OFF_X + (CONV ? 6 * NB : 3 * NB + 9 * NQ) * 8);  // double Pq[NQ][PS]
+    static constexpr int OFF_A = q2::align16(OFF_P + NQ * PS * 8);  // T Phi[NBP][KS]; double F[NF][NQ]
+    static constexpr int OFF_W = q2::align16(OFF_A + NBP * KS * (int)sizeof(T));  // T W[WB][NBP][KS]
+    static constexpr int CH_END = OFF_W + WB * NBP * KS * (int)sizeof(T);
+    static constexpr int F_END = OFF_A + NF * NQ * 8;
+    static constexpr int BYTES = q2::align16(CH_END > F_END ? CH_END : F_END);
+    static_assert(BYTES <= 160 * 1024, "LDS");
+};
+
+template <int P, int FORM, int MM>
+__global__ __launch_bounds__(GM_THREADS, 2) void k_hexgmc(ExecArgs A)
+{
+    using H = HexGMC<P, FORM, MM>;
+    using T = typename H::T;
+    using ACC = typename H::ACC;
+    constexpr int N1 = H::N1, NB = H::NB, NQ = H::NQ, NBP = H::NBP, NT = H::NT, TPB = H::TPB, KC = H::KC;
+    constexpr int KS = H::KS, NJ = H::NJ, PT = H::PT, PS = H::PS;
+    constexpr bool CONV = H::CONV;
+    __shared__ __align__(16) unsigned char smem[H::BYTES];
+    double *B1 = reinterpret_cast<double *>(smem + H::OFF_TB);
+    double *D1 = B1 + N1 * N1;
+    double *wq = D1 + N1 * N1;
+    double *xs = reinterpret_cast<double *>(smem + H::OFF_X);  // [3][NB]
+    double *us = xs + 3 * NB;                                  // [3][NB] (convection)
+    double *Ms = xs + 3 * NB;                                  // [NQ][9] (weighted dot)
+    double *Pq = reinterpret_cast<double *>(smem + H::OFF_P);  // [NQ][PS]
+    T *Ph = reinterpret_cast<T *>(smem + H::OFF_A);            // [NBP][KS]: points of the chunk
+    double *F = reinterpret_cast<double *>(smem + H::OFF_A);   // [NF][NQ]
+    T *W = reinterpret_cast<T *>(smem + H::OFF_W);             // [WB][NBP][KS]
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int m = lane & 15, grp = lane >> 4;
+
+    int64_t e, e_end, stride;
+    cell_range(A.xcd_remap, A.n_cells, e, e_end, stride);
+    if (e >= e_end) return;  // uniform over the workgroup
+
+    for (int k = tid; k < N1 * N1; k += GM_THREADS) {
+        B1[k] = A.tab.B1[k];
+        D1[k] = A.tab.D1[k];
+    }
+    for (int k = tid; k < NQ; k += GM_THREADS) wq[k] = A.tab.w[k];
+    __syncthreads();
+
+    for (; e < e_end; e += stride) {
+        gm_gather<H>(A, e, xs, us, Ms, tid);
+        __syncthreads();
+        gm_points<H>(A, B1, D1, wq, xs, us, Ms, F, Pq, tid);
+        __syncthreads();  // F (in the chunks' space) is read for the last time in gm_points
+
+        T *oc = static_cast<T *>(A.out) + e * static_cast<int64_t>(H::ND) * H::ND;
+        for (int ps = 0; ps < H::NPASS; ps++) {
+            const int t0 = ps * PT;
+            const int t1 = t0 + PT < H::NTILES ? t0 + PT : H::NTILES;
+            const int blo = t0 / TPB, nbk = (t1 - 1) / TPB - blo + 1;
+            // this wave's tiles t = t0 + wave + 8 u; slots past t1 multiply
+            // the pass's first tile and are not stored
+            ACC acc[NJ];
+            int ra[NJ], rb[NJ];
+#pragma unroll
+            for (int u = 0; u < NJ; u++) {
+                acc[u] = ACC{};
+                const int t = t0 + wave + GM_WAVES * u, tt = t < t1 ? t : t0;
+                const int blk = tt / TPB, rem = tt - blk * TPB, ti = rem / NT, tj = rem - ti * NT;
+                ra[u] = 16 * ti;
+                rb[u] = (blk - blo) * NBP + 16 * tj;
+            }
+            for (int ch = 0; ch < H::NCH; ch++) {
+                const int k0 = ch * KC;
+                // Phi chunk: basis b at the chunk's points (zero past NB / NQ)
+                for (int it = tid; it < NBP * KC; it += GM_THREADS) {
+                    const int b = it % NBP, ql = it / NBP, q = k0 + ql;
+                    Ph[b * KS + ql] = static_cast<T>(b < NB && q < NQ ? A.tab.bf[q * NB + b] : 0.0);
+                }
+                // W chunks of the pass's blocks
+                for (int it = tid; it < nbk * NBP * KC; it += GM_THREADS) {
+                    const int ql = it % KC, rest = it / KC, b = rest % NBP, bk = rest / NBP;
+                    const int q = k0 + ql, rs = blo + bk;
+                    double x = 0.0;
+                    if (q < NQ && b < NB) {
+                        const int q0 = q % N1, q1 = (q / N1) % N1, q2 = q / (N1 * N1);
+                        const int b0 = b % N1, b1 = (b / N1) % N1, b2 = b / (N1 * N1);
+                        const double bx = B1[q0 * N1 + b0], by = B1[q1 * N1 + b1], bz = B1[q2 * N1 + b2];
+                        const double *pq = Pq + q * PS;
+                        x = pq[rs] * (bx * by * bz);
+                        if (CONV && rs / 3 == rs % 3) {
+                            const double dx = D1[q0 * N1 + b0], dy = D1[q1 * N1 + b1], dz = D1[q2 * N1 + b2];
+                            x += pq[9] * (dx * by * bz) + pq[10] * (bx * dy * bz) + pq[11] * (bx * by * dz);
+                        }
+                    }
+                    W[(bk * NBP + b) * KS + ql] = static_cast<T>(x);
+                }
+                __syncthreads();
+                // products over the chunk's points: k steps in a loop, the
+                // slots in groups whose fragments are loaded while the
+                // previous group multiplies
+                constexpr int G = sizeof(T) == 8 ? 4 : 8, NG = (NJ + G - 1) / G;
+                T a[2][G], bb[2][G];
+                auto load = [&](int buf, int g, int k) {
+#pragma unroll
+                    for (int v = 0; v < G; v++)
+                        if (g * G + v < NJ) {
+                            a[buf][v] = Ph[(ra[g * G + v] + m) * KS + k];
+                            bb[buf][v] = W[(rb[g * G + v] + m) * KS + k];
+                        }
+                };
+                auto mfma = [&](int buf, int g) {
+#pragma unroll
+                    for (int v = 0; v < G; v++)
+                        if (g * G + v < NJ) {
+                            if constexpr (MM == MM_F64)
+                                acc[g * G + v] =
+                                    __builtin_amdgcn_mfma_f64_16x16x4f64(a[buf][v], bb[buf][v], acc[g * G + v], 0, 0, 0);
+                            else
+                                acc[g * G + v] =
+                                    __builtin_amdgcn_mfma_f32_16x16x4f32(a[buf][v], bb[buf][v], acc[g * G + v], 0, 0, 0);
+                        }
+                };
+                for (int st = 0; st < KC / 4; st++) {
+                    const int k = 4 * st + grp;
+                    load(0, 0, k);
+#pragma unroll
+                    for (int g = 0; g < NG; g++) {
+                        if (g + 1 < NG) load((g + 1) & 1, g + 1, k);
+                        __builtin_amdgcn_sched_barrier(0);
+                        mfma(g & 1, g);
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                }
+                __syncthreads();  // the chunks are rebuilt next
+            }
+#pragma unroll
+            for (int u = 0; u < NJ; u++) {
+                const int t = t0 + wave + GM_WAVES * u;
+                if (t < t1) {
+                    const int blk = t / TPB, rem = t - blk * TPB, ti = rem / NT, tj = rem - ti * NT;
+                    const int r = blk / 3, s = blk - 3 * r;
+                    store_tile<H>(oc, r * NB + 16 * ti, s * NB + 16 * tj, valid<H>(ti), valid<H>(tj), acc[u], lane);
+                }
+            }
+        }
+    }
+}
+
+// persistent launch: as many workgroups as fit on the device at once
+template <class K>
+int launch_persistent(K kernel, const ExecArgs &A, hipStream_t st, int *resident)
 {
     if (A.n_cells <= 0) return FE_OK;
     if (A.n_cells > 0x7fffffffLL) {
         set_error("too many cells for one launch");
         return FE_ERR_INVALID_ARG;
     }
-    static int resident[64] = {0};
     int dev = 0;
     FE_HIP_CHECK(hipGetDevice(&dev));
     if (dev < 0 || dev >= 64) return FE_ERR_INVALID_ARG;
     if (!resident[dev]) {
         int per_cu = 0, cus = 0;
-        FE_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_hexgm<P, FORM, MM>, GM_THREADS, 0));
+        FE_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, GM_THREADS, 0));
         FE_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         resident[dev] = per_cu * cus > 8 ? (per_cu * cus) & ~7 : 8;
     }
     const int64_t grid = A.n_cells < resident[dev] ? A.n_cells : resident[dev];
-    hipLaunchKernelGGL((k_hexgm<P, FORM, MM>), dim3((unsigned)grid), dim3(GM_THREADS), 0, st, A);
+    hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3(GM_THREADS), 0, st, A);
     FE_HIP_CHECK(hipGetLastError());
     return FE_OK;
+}
+
+template <int P, int FORM, int MM>
+int launch_hexgm(const Plan &, const ExecArgs &A, hipStream_t st)
+{
+    static int resident[64] = {0};
+    if constexpr (P <= 3)
+        return launch_persistent(k_hexgm<P, FORM, MM>, A, st, resident);
+    else
+        return launch_persistent(k_hexgmc<P, FORM, MM>, A, st, resident);
 }
 
 template <int P, int MM>
@@ -326,6 +541,8 @@ LaunchFn pick_order(const Plan &p)
 {
     if (p.order == 2) return pick<2, MM>(p);
     if (p.order == 3) return pick<3, MM>(p);
+    if (p.order == 4) return pick<4, MM>(p);
+    if (p.order == 5) return pick<5, MM>(p);
     return nullptr;
 }
 

@@ -122,9 +122,28 @@ def test_forms_f2_residual_and_eval(orc, p, dims, curved, form, kind, prec):
         assert err < TOL[prec], (mode, err)
 
 
-@pytest.mark.parametrize("form,kind,mode", [("elasticity", "voigt_qp", "residual"),
-                                            ("wdot", "tensor_qp", "matrix"),
-                                            ("convect", None, "matrix")])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("form,kind", [("wdot", "tensor_qp"), ("convect", None)])
+@pytest.mark.parametrize("p,dims,curved", HIGH)
+def test_forms_f2_matrix(orc, p, dims, curved, form, kind, prec):
+    """Weighted dot and convection matrices at orders 4-5 on the matrix
+    cores, points in chunks, against the oracle."""
+    import paper_2107_04121_amd as fe
+    mesh = _mesh(p, dims, curved, seed=52)
+    nb, nq = orc.sizes("hex", p)
+    M = meshgen.tensor_qp(mesh.n_cells, nq, seed=53) if kind else None
+    U = meshgen.dofs(mesh.n_nodes, 3, seed=54)
+    plan = fe.Plan("hex", p, form, "matrix", prec, material=kind)
+    print(f"[high] matrix Q{p} {form} {prec} variant={plan.variant} cells={mesh.n_cells}", flush=True)
+    assert plan.variant == "mfma"
+    out = plan(_t(mesh.coords), _t(mesh.conn), material=None if M is None else _t(M, plan.dtype),
+               dofs=_t(U, plan.dtype))
+    plan.check()
+    ref = orc.matrix(mesh, form, M, kind, u=U if form == "convect" else None)
+    assert elem_rel_err(out.cpu().numpy(), ref) < TOL[prec]
+
+
+@pytest.mark.parametrize("form,kind,mode", [("elasticity", "voigt_qp", "residual")])
 def test_forms_without_kernel_refused(form, kind, mode):
     import paper_2107_04121_amd as fe
     for p in (4, 5):
