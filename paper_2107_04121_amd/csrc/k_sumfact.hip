@@ -206,7 +206,7 @@ __device__ __forceinline__ void forward3(const V (&f)[N1], V *L, const TB &tb, i
     }
 }
 
-template <int P, int FORM, typename T, bool ADJ>
+template <int P, int FORM, typename T, bool ADJ, bool VOIGT = false>
 __global__ __launch_bounds__(256) void k_sf(ExecArgs A, int cell_minor, T *gmat, double scale)
 {
     using S = SF<P, FORM, T>;
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(256) void k_sf(ExecArgs A, int cell_minor, T *gmat,
     const T *mat = static_cast<const T *>(A.mat);
     T lam = T(0), mu = T(0);
     if constexpr (FORM == FE_FORM_ELASTICITY)
-        if (live && A.mat_kind != FE_MAT_ISO_QP) {
+        if (live && A.mat_kind == FE_MAT_ISO_CELL) {
             lam = mat[2 * e];
             mu = mat[2 * e + 1];
         }
@@ -389,6 +389,31 @@ __global__ __launch_bounds__(256) void k_sf(ExecArgs A, int cell_minor, T *gmat,
                     for (int j = 0; j < 3; j++) F[q][k][j] = Mk[0] * Ji[q][j][0] + Mk[1] * Ji[q][j][1] + Mk[2] * Ji[q][j][2];
                 }
                 continue;
+            } else if constexpr (VOIGT) {
+                // sigma = D eps in Voigt order 11,22,33,12,13,23 with
+                // engineering shear; D row-major per point
+                const T ev[6] = {H[0][0], H[1][1], H[2][2], H[0][1] + H[1][0], H[0][2] + H[2][0], H[1][2] + H[2][1]};
+                T sv[6] = {};
+                if (live) {
+                    const T *D = mat + (e * NP + pp + NPL * q) * 36;
+#pragma unroll
+                    for (int I = 0; I < 6; I++) {
+                        T x = T(0);
+#pragma unroll
+                        for (int K = 0; K < 6; K++) x += D[I * 6 + K] * ev[K];
+                        sv[I] = x;
+                    }
+                }
+                Sg[0][0] = sv[0];
+                Sg[1][1] = sv[1];
+                Sg[2][2] = sv[2];
+                Sg[0][1] = Sg[1][0] = sv[3];
+                Sg[0][2] = Sg[2][0] = sv[4];
+                Sg[1][2] = Sg[2][1] = sv[5];
+                T ee = T(0);
+#pragma unroll
+                for (int I = 0; I < 6; I++) ee += ev[I] * sv[I];
+                energy += wd[q] * ee;
             } else {
                 if (live && A.mat_kind == FE_MAT_ISO_QP) {
                     const int64_t k = e * NP + pp + NPL * q;
@@ -584,8 +609,15 @@ int launch_sf(const Plan &p, const ExecArgs &A, hipStream_t st)
         set_error("too many cells for one launch");
         return FE_ERR_INVALID_ARG;
     }
-    hipLaunchKernelGGL((k_sf<P, FORM, T, false>), dim3((unsigned)blocks), dim3(256), 0, st, A,
-                       p.opts.layout == FE_LAYOUT_CELL_MINOR ? 1 : 0, static_cast<T *>(nullptr), 1.0);
+    const int minor = p.opts.layout == FE_LAYOUT_CELL_MINOR ? 1 : 0;
+    // a separate instantiation for the per-point Voigt D keeps the
+    // isotropic kernels' registers as they are
+    if (FORM == FE_FORM_ELASTICITY && A.mat_kind == FE_MAT_VOIGT_QP)
+        hipLaunchKernelGGL((k_sf<P, FORM, T, false, FORM == FE_FORM_ELASTICITY>), dim3((unsigned)blocks), dim3(256),
+                           0, st, A, minor, static_cast<T *>(nullptr), 1.0);
+    else
+        hipLaunchKernelGGL((k_sf<P, FORM, T, false>), dim3((unsigned)blocks), dim3(256), 0, st, A, minor,
+                           static_cast<T *>(nullptr), 1.0);
     FE_HIP_CHECK(hipGetLastError());
     return FE_OK;
 }
@@ -660,7 +692,6 @@ int adjoint_sumfact(const Plan &p, const ExecArgs &A, double scale, void *gmat, 
 LaunchFn select_sumfact(const Plan &p)
 {
     if (p.cell != FE_CELL_HEX || p.mode == FE_MODE_MATRIX) return nullptr;
-    if (p.form == FE_FORM_ELASTICITY && p.mat_kind == FE_MAT_VOIGT_QP) return nullptr;
     if (p.prec == FE_PREC_FP64) return pick_order<double>(p.order, p.form);
     if (p.prec == FE_PREC_FP32) return pick_order<float>(p.order, p.form);
     return nullptr;

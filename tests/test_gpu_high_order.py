@@ -2,7 +2,7 @@
 cell and DOF counts) through the C ABI against the FP64 oracle: residual
 and eval by sum factorization in both output layouts (all six forms), the
 adjoint of the elastic energy, element matrices on the matrix cores, and
-the plans without a kernel at these orders refused at plan creation.  Meshes span several workgroups with a ragged tail (Q4: two
+the elasticity matrices with per-point material refused at plan creation.  Meshes span several workgroups with a ragged tail (Q4: two
 cells per wave, eight per workgroup; Q5: one per wave, four per workgroup);
 the curvature noise is scaled down with the order so that every Jacobian
 stays positive."""
@@ -32,6 +32,8 @@ def _material(kind, mesh, nq):
         return meshgen.lame_cell(mesh.n_cells, seed=41)
     if kind == "iso_qp":
         return meshgen.lame_qp(mesh.n_cells, nq, seed=41)
+    if kind == "voigt_qp":
+        return meshgen.voigt_random_spd((mesh.n_cells, nq), seed=41)
     return None
 
 
@@ -43,7 +45,7 @@ def elem_rel_err(got, ref):
 
 
 FORMS = [("mass", None), ("vmass", None), ("laplace", None),
-         ("elasticity", "iso_cell"), ("elasticity", "iso_qp")]
+         ("elasticity", "iso_cell"), ("elasticity", "iso_qp"), ("elasticity", "voigt_qp")]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -141,15 +143,6 @@ def test_forms_f2_matrix(orc, p, dims, curved, form, kind, prec):
     plan.check()
     ref = orc.matrix(mesh, form, M, kind, u=U if form == "convect" else None)
     assert elem_rel_err(out.cpu().numpy(), ref) < TOL[prec]
-
-
-@pytest.mark.parametrize("form,kind,mode", [("elasticity", "voigt_qp", "residual")])
-def test_forms_without_kernel_refused(form, kind, mode):
-    import paper_2107_04121_amd as fe
-    for p in (4, 5):
-        with pytest.raises(fe.FeError) as ei:
-            fe.Plan("hex", p, form, mode, "fp64", material=kind)
-        assert ei.value.status == 2  # FE_ERR_UNSUPPORTED
 
 
 MFORMS = [("mass", None), ("vmass", None), ("laplace", None), ("elasticity", "iso_cell")]

@@ -184,7 +184,8 @@ def test_elasticity_q2_variants(orc, prec, variant):
 @pytest.mark.parametrize("form,kind", [("mass", None), ("vmass", None),
                                        ("laplace", None),
                                        ("elasticity", "iso_cell"),
-                                       ("elasticity", "iso_qp")])
+                                       ("elasticity", "iso_qp"),
+                                       ("elasticity", "voigt_qp")])
 @pytest.mark.parametrize("p", [1, 2, 3])
 def test_residual_variants(orc, p, form, kind, prec):
     """Sum-factorized (auto for hexahedra), generic and matrix-first
