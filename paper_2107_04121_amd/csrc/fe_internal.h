@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -80,6 +81,39 @@ void set_error(const std::string &msg);
             return FE_ERR_HIP;                                                 \
         }                                                                      \
     } while (0)
+
+// Persistent launch of a kernel that walks XCD-contiguous cell ranges: as
+// many workgroups as the device holds at once (a multiple of 8, at least 8,
+// at most the number of cells).  The count is queried once per device and
+// kernel and kept in resident[device] (0 = not yet known; concurrent first
+// calls store the same value).
+template <class K>
+int launch_persistent(K kernel, int threads, const ExecArgs &A, hipStream_t st, std::atomic<int> *resident)
+{
+    if (A.n_cells <= 0) return FE_OK;
+    if (A.n_cells > 0x7fffffffLL) {
+        set_error("too many cells for one launch");
+        return FE_ERR_INVALID_ARG;
+    }
+    int dev = 0;
+    FE_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) {
+        set_error("device index beyond 63");
+        return FE_ERR_INVALID_ARG;
+    }
+    int r = resident[dev].load(std::memory_order_relaxed);
+    if (!r) {
+        int per_cu = 0, cus = 0;
+        FE_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0));
+        FE_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        r = per_cu * cus > 8 ? (per_cu * cus) & ~7 : 8;
+        resident[dev].store(r, std::memory_order_relaxed);
+    }
+    const int64_t grid = A.n_cells < r ? A.n_cells : r;
+    hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3(threads), 0, st, A);
+    FE_HIP_CHECK(hipGetLastError());
+    return FE_OK;
+}
 
 // Kernel family selectors; each returns nullptr when it has no kernel for the
 // plan (the caller then tries the next family).

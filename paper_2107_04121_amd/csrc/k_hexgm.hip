@@ -494,38 +494,14 @@ __global__ __launch_bounds__(GM_THREADS, 2) void k_hexgmc(ExecArgs A)
     }
 }
 
-// persistent launch: as many workgroups as fit on the device at once
-template <class K>
-int launch_persistent(K kernel, const ExecArgs &A, hipStream_t st, int *resident)
-{
-    if (A.n_cells <= 0) return FE_OK;
-    if (A.n_cells > 0x7fffffffLL) {
-        set_error("too many cells for one launch");
-        return FE_ERR_INVALID_ARG;
-    }
-    int dev = 0;
-    FE_HIP_CHECK(hipGetDevice(&dev));
-    if (dev < 0 || dev >= 64) return FE_ERR_INVALID_ARG;
-    if (!resident[dev]) {
-        int per_cu = 0, cus = 0;
-        FE_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, GM_THREADS, 0));
-        FE_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        resident[dev] = per_cu * cus > 8 ? (per_cu * cus) & ~7 : 8;
-    }
-    const int64_t grid = A.n_cells < resident[dev] ? A.n_cells : resident[dev];
-    hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3(GM_THREADS), 0, st, A);
-    FE_HIP_CHECK(hipGetLastError());
-    return FE_OK;
-}
-
 template <int P, int FORM, int MM>
 int launch_hexgm(const Plan &, const ExecArgs &A, hipStream_t st)
 {
-    static int resident[64] = {0};
+    static std::atomic<int> resident[64];
     if constexpr (P <= 3)
-        return launch_persistent(k_hexgm<P, FORM, MM>, A, st, resident);
+        return launch_persistent(k_hexgm<P, FORM, MM>, GM_THREADS, A, st, resident);
     else
-        return launch_persistent(k_hexgmc<P, FORM, MM>, A, st, resident);
+        return launch_persistent(k_hexgmc<P, FORM, MM>, GM_THREADS, A, st, resident);
 }
 
 template <int P, int MM>

@@ -951,49 +951,15 @@ __global__ __launch_bounds__(Q3WS<MM>::THREADS, 1) void k_elast_q3ws(ExecArgs A)
 template <int MM>
 int launch_q3ws(const Plan &, const ExecArgs &A, hipStream_t st)
 {
-    if (A.n_cells <= 0) return FE_OK;
-    if (A.n_cells > 0x7fffffffLL) {
-        set_error("too many cells for one launch");
-        return FE_ERR_INVALID_ARG;
-    }
-    static int resident[64] = {0};
-    int dev = 0;
-    FE_HIP_CHECK(hipGetDevice(&dev));
-    if (dev < 0 || dev >= 64) return FE_ERR_INVALID_ARG;
-    if (!resident[dev]) {
-        int per_cu = 0, cus = 0;
-        FE_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_elast_q3ws<MM>, Q3WS<MM>::THREADS, 0));
-        FE_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        resident[dev] = per_cu * cus > 8 ? (per_cu * cus) & ~7 : 8;
-    }
-    const int64_t grid = A.n_cells < resident[dev] ? A.n_cells : resident[dev];
-    hipLaunchKernelGGL(k_elast_q3ws<MM>, dim3((unsigned)grid), dim3(Q3WS<MM>::THREADS), 0, st, A);
-    FE_HIP_CHECK(hipGetLastError());
-    return FE_OK;
+    static std::atomic<int> resident[64];
+    return launch_persistent(k_elast_q3ws<MM>, Q3WS<MM>::THREADS, A, st, resident);
 }
 
 template <int P, int FORM, int MM>
 int launch_hexmm(const Plan &, const ExecArgs &A, hipStream_t st)
 {
-    if (A.n_cells <= 0) return FE_OK;
-    if (A.n_cells > 0x7fffffffLL) {
-        set_error("too many cells for one launch");
-        return FE_ERR_INVALID_ARG;
-    }
-    static int resident[64] = {0};
-    int dev = 0;
-    FE_HIP_CHECK(hipGetDevice(&dev));
-    if (dev < 0 || dev >= 64) return FE_ERR_INVALID_ARG;
-    if (!resident[dev]) {
-        int per_cu = 0, cus = 0;
-        FE_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_hexmm<P, FORM, MM>, THREADS, 0));
-        FE_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        resident[dev] = per_cu * cus > 8 ? (per_cu * cus) & ~7 : 8;
-    }
-    const int64_t grid = A.n_cells < resident[dev] ? A.n_cells : resident[dev];
-    hipLaunchKernelGGL((k_hexmm<P, FORM, MM>), dim3((unsigned)grid), dim3(THREADS), 0, st, A);
-    FE_HIP_CHECK(hipGetLastError());
-    return FE_OK;
+    static std::atomic<int> resident[64];
+    return launch_persistent(k_hexmm<P, FORM, MM>, THREADS, A, st, resident);
 }
 
 // ---------------------------------------------------------------------------
@@ -1454,25 +1420,8 @@ __global__ __launch_bounds__(THREADS, 1) void k_hexmc(ExecArgs A)
 template <int P, int FORM, int MM>
 int launch_hexmc(const Plan &, const ExecArgs &A, hipStream_t st)
 {
-    if (A.n_cells <= 0) return FE_OK;
-    if (A.n_cells > 0x7fffffffLL) {
-        set_error("too many cells for one launch");
-        return FE_ERR_INVALID_ARG;
-    }
-    static int resident[64] = {0};
-    int dev = 0;
-    FE_HIP_CHECK(hipGetDevice(&dev));
-    if (dev < 0 || dev >= 64) return FE_ERR_INVALID_ARG;
-    if (!resident[dev]) {
-        int per_cu = 0, cus = 0;
-        FE_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_hexmc<P, FORM, MM>, THREADS, 0));
-        FE_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        resident[dev] = per_cu * cus > 8 ? (per_cu * cus) & ~7 : 8;
-    }
-    const int64_t grid = A.n_cells < resident[dev] ? A.n_cells : resident[dev];
-    hipLaunchKernelGGL((k_hexmc<P, FORM, MM>), dim3((unsigned)grid), dim3(THREADS), 0, st, A);
-    FE_HIP_CHECK(hipGetLastError());
-    return FE_OK;
+    static std::atomic<int> resident[64];
+    return launch_persistent(k_hexmc<P, FORM, MM>, THREADS, A, st, resident);
 }
 
 template <int P, int MM>

@@ -50,30 +50,12 @@ template <int MM>
 int launch_elast_q2(const Plan &, const ExecArgs &A, hipStream_t st)
 {
     if (A.n_cells <= 0) return FE_OK;
-    if (A.n_cells > 0x7fffffffLL) {
-        set_error("too many cells for one launch");
-        return FE_ERR_INVALID_ARG;
-    }
     if (reinterpret_cast<uintptr_t>(A.out) % 16 != 0) {
         set_error("out must be 16-byte aligned for the matrix-core kernel");
         return FE_ERR_INVALID_ARG;
     }
-    // persistent grid: as many workgroups as are resident at once, a
-    // multiple of 8 (one share per XCD), never more than the cells
-    static int resident[64] = {0};
-    int dev = 0;
-    FE_HIP_CHECK(hipGetDevice(&dev));
-    if (dev < 0 || dev >= 64) return FE_ERR_INVALID_ARG;
-    if (!resident[dev]) {
-        int per_cu = 0, cus = 0;
-        FE_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_elast_q2<MM>, 256, 0));
-        FE_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        resident[dev] = per_cu * cus > 8 ? (per_cu * cus) & ~7 : 8;
-    }
-    const int64_t grid = A.n_cells < resident[dev] ? A.n_cells : resident[dev];
-    hipLaunchKernelGGL(k_elast_q2<MM>, dim3((unsigned)grid), dim3(256), 0, st, A);
-    FE_HIP_CHECK(hipGetLastError());
-    return FE_OK;
+    static std::atomic<int> resident[64];
+    return launch_persistent(k_elast_q2<MM>, 256, A, st, resident);
 }
 
 }  // namespace
