@@ -115,7 +115,7 @@ typedef enum {
 /* Kernel variant (0 = automatic choice). */
 typedef enum {
     FE_VARIANT_AUTO = 0,
-    FE_VARIANT_GENERIC = 1,   /* reference-table VALU kernel, any cell/order */
+    FE_VARIANT_GENERIC = 1,   /* reference-table VALU kernel, hex Q1-Q3 and tets */
     FE_VARIANT_MFMA = 2,      /* matrix mode: per-element GEMM on matrix cores */
     FE_VARIANT_SUMFACT = 3,   /* hex residual/eval: sum-factorized, gradient-first */
     FE_VARIANT_MATRIX_FIRST = 4, /* residual: form K_e then K_e u_e */
@@ -160,7 +160,17 @@ int fe_reference_tables(int cell, int order, double *weights, double *points,
 
 /* Create a plan for one (cell, order, form, mode, precision, material kind)
  * on the current HIP device: builds the reference tables and copies them to
- * the device.  opts may be NULL. */
+ * the device.  opts may be NULL.
+ *
+ * Supported (every other combination returns FE_ERR_UNSUPPORTED):
+ *   cells and orders: HEX 1-5, TET 1-2;
+ *   RESIDUAL and EVAL: every form and material kind, FP64 and FP32;
+ *   MATRIX, FP64 and FP32: every form and material kind on HEX 1-3 and TET
+ *     1-2; on HEX 4-5 every form except ELASTICITY with ISO_QP or VOIGT_QP;
+ *   MATRIX, BF16X3: MASS, VMASS, LAPLACE and ELASTICITY with ISO_CELL on
+ *     HEX 2-5.
+ * MATRIX_FIRST (a residual variant) needs a matrix kernel for the same
+ * combination and is refused for CONVECT. */
 int fe_plan_create(int cell, int order, int form, int mode, int precision,
                    int material_kind, const fe_options *opts, fe_plan *out);
 
