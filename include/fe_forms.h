@@ -164,9 +164,8 @@ int fe_reference_tables(int cell, int order, double *weights, double *points,
  *
  * Supported (every other combination returns FE_ERR_UNSUPPORTED):
  *   cells and orders: HEX 1-5, TET 1-2;
- *   RESIDUAL and EVAL: every form and material kind, FP64 and FP32;
- *   MATRIX, FP64 and FP32: every form and material kind on HEX 1-3 and TET
- *     1-2; on HEX 4-5 every form except ELASTICITY with ISO_QP or VOIGT_QP;
+ *   RESIDUAL, EVAL and MATRIX: every form and material kind, FP64 and
+ *     FP32;
  *   MATRIX, BF16X3: MASS, VMASS, LAPLACE and ELASTICITY with ISO_CELL on
  *     HEX 2-5.
  * MATRIX_FIRST (a residual variant) needs a matrix kernel for the same

@@ -62,6 +62,7 @@ struct HexGM {
     static constexpr int NTILE = G * NT * NT;                         // output tiles per group
     static constexpr int NJ = (NTILE + GM_WAVES - 1) / GM_WAVES;      // tiles per wave
     static constexpr bool CONV = FORM == FE_FORM_CONVECT;
+    static constexpr bool ELAST = false;
     // entries per point from the sum factorization: dx_i/dxi_j (9); for the
     // convection also du_i/dxi_j (9) and u_i (3)
     static constexpr int NF = CONV ? 21 : 9;
@@ -99,14 +100,15 @@ __device__ __forceinline__ void gm_gather(const ExecArgs &A, int64_t e, double *
         xs[c * NB + a] = A.coords[3 * n + c];
         if constexpr (H::CONV) us[c * NB + a] = static_cast<double>(Ug[n * 3 + c]);
     }
-    if constexpr (!H::CONV)
+    if constexpr (!H::CONV && !H::ELAST)
         for (int k = tid; k < NQ * 9; k += GM_THREADS) Ms[k] = static_cast<double>(mat[e * NQ * 9 + k]);
 }
 
 // Per-point data of the cell in Pq[NQ][PS] (F[NF][NQ]: scratch):
 //   1. entry f at point q by sum factorization: f < 9: dx_i/dxi_j
 //      (i = f / 3, j = f % 3); 9 <= f < 18: du_i/dxi_j; 18 <= f < 21: u_i;
-//   2. the block coefficients c_rs and, for the convection, w det J v.
+//   2. the block coefficients c_rs and, for the convection, w det J v; for
+//      elasticity J^-1 (row-major) and w det J.
 // Contains one barrier, between the two steps.
 template <class H>
 __device__ __forceinline__ void gm_points(const ExecArgs &A, const double *B1, const double *D1, const double *wq,
@@ -156,7 +158,13 @@ __device__ __forceinline__ void gm_points(const ExecArgs &A, const double *B1, c
         if (!(det > 0.0)) raise_fault(A.flags, FAULT_DET);
         const double wd = wq[q] * det;
         double *pq = Pq + q * PS;
-        if constexpr (H::CONV) {
+        if constexpr (H::ELAST) {
+#pragma unroll
+            for (int mm = 0; mm < 3; mm++)
+#pragma unroll
+                for (int j = 0; j < 3; j++) pq[mm * 3 + j] = Ji[mm][j];
+            pq[9] = wd;
+        } else if constexpr (H::CONV) {
             double u[3];
 #pragma unroll
             for (int s = 0; s < 3; s++) u[s] = F[(18 + s) * NQ + q];
@@ -327,6 +335,43 @@ __global__ __launch_bounds__(GM_THREADS, (2 * HexGM<P, FORM, MM>::MINB)) void k_
 //   barrier; products; barrier; then the tiles are stored.
 constexpr int gmc_cap(int mm) { return mm == MM_F64 ? 16 : 32; }
 
+// Reference gradient d phi_b / d xi_m (m = 0..2) at point q from the 1-D
+// value and derivative tables.
+template <class H>
+__device__ __forceinline__ void ref_grad(const double *B1, const double *D1, int b, int q, double (&g)[3])
+{
+    constexpr int N1 = H::N1;
+    const int q0 = q % N1, q1 = (q / N1) % N1, q2 = q / (N1 * N1);
+    const int b0 = b % N1, b1 = (b / N1) % N1, b2 = b / (N1 * N1);
+    const double bx = B1[q0 * N1 + b0], by = B1[q1 * N1 + b1], bz = B1[q2 * N1 + b2];
+    g[0] = D1[q0 * N1 + b0] * by * bz;
+    g[1] = bx * D1[q1 * N1 + b1] * bz;
+    g[2] = bx * by * D1[q2 * N1 + b2];
+}
+
+// Voigt index of the symmetric pair (a, b): 11,22,33,12,13,23
+__device__ __forceinline__ int voigt(int a, int b) { return a == b ? a : a + b + 2; }
+
+// c[k] = C_rjsk at point kq = e n_q + q of the elasticity tensor written by
+// the material: isotropic lambda delta_rj delta_sk + mu (delta_rs delta_jk +
+// delta_rk delta_js) from ISO_QP, or D[voigt(r,j)][voigt(s,k)] from VOIGT_QP
+// (engineering shear, so that sum C_rjsk du_s/dx_k is the stress).
+template <typename T>
+__device__ __forceinline__ void material_row(const ExecArgs &A, int64_t kq, int r, int j, int s, double (&c)[3])
+{
+    const T *mat = static_cast<const T *>(A.mat);
+    if (A.mat_kind == FE_MAT_VOIGT_QP) {
+        const T *D = mat + kq * 36 + voigt(r, j) * 6;
+#pragma unroll
+        for (int k = 0; k < 3; k++) c[k] = static_cast<double>(D[voigt(s, k)]);
+    } else {
+        const double lam = static_cast<double>(mat[2 * kq]), mu = static_cast<double>(mat[2 * kq + 1]);
+#pragma unroll
+        for (int k = 0; k < 3; k++)
+            c[k] = (r == j && s == k ? lam : 0.0) + (r == s && j == k ? mu : 0.0) + (r == k && j == s ? mu : 0.0);
+    }
+}
+
 template <int P, int FORM, int MM>
 struct HexGMC {
     static constexpr int N1 = P + 1, NB = N1 * N1 * N1, NQ = NB;
@@ -336,22 +381,26 @@ struct HexGMC {
     static constexpr bool NT_STORE = ND % 16 == 0;
     using T = typename MMT<MM>::T;
     using ACC = typename MMT<MM>::acc;
-    static constexpr int KC = 16, NCH = (NQ + KC - 1) / KC, KS = op_stride(MM, KC);
+    static constexpr bool CONV = FORM == FE_FORM_CONVECT;
+    static constexpr bool ELAST = FORM == FE_FORM_ELASTICITY;  // per-point material
+    // depth of the products: the points, or (point, gradient component)
+    // pairs for elasticity
+    static constexpr int DQ = ELAST ? 3 * NQ : NQ;
+    static constexpr int KC = 16, NCH = (DQ + KC - 1) / KC, KS = op_stride(MM, KC);
     static constexpr int NTILES = 9 * TPB;
     static constexpr int NPASS = (NTILES + GM_WAVES * gmc_cap(MM) - 1) / (GM_WAVES * gmc_cap(MM));
     static constexpr int NJ = (NTILES + GM_WAVES * NPASS - 1) / (GM_WAVES * NPASS);  // tiles per wave and pass
     static constexpr int PT = GM_WAVES * NJ;                                          // tiles per pass
     static constexpr int WB = (PT + TPB - 1) / TPB + 1 < 9 ? (PT + TPB - 1) / TPB + 1 : 9;  // blocks a pass touches
-    static constexpr bool CONV = FORM == FE_FORM_CONVECT;
     static constexpr int NF = CONV ? 21 : 9;
-    static constexpr int PS = CONV ? 12 : 9;
+    static constexpr int PS = ELAST ? 10 : (CONV ? 12 : 9);
     // LDS layout (bytes); F (sum-factorization scratch) shares the space of
     // the Phi and W chunks, free between the last products of a cell and the
     // first chunk of the next
     static constexpr int OFF_TB = 0;  // double B1[N1][N1], D1[N1][N1], w[NQ]
     static constexpr int OFF_X = q2::align16(OFF_TB + (2 * N1 * N1 + NQ) * 8);
-    static constexpr int OFF_P = q2::align16(OFF_X + (CONV ? 6 * NB : 3 * NB + 9 * NQ) * 8);  // double Pq[NQ][PS]
-    static constexpr int OFF_A = q2::align16(OFF_P + NQ * PS * 8);  // T Phi[NBP][KS]; double F[NF][NQ]
+    static constexpr int OFF_P = q2::align16(OFF_X + (CONV ? 6 * NB : (ELAST ? 3 * NB : 3 * NB + 9 * NQ)) * 8);  // double Pq[NQ][PS]
+    static constexpr int OFF_A = q2::align16(OFF_P + NQ * PS * 8);  // T Phi[NBP][KS] or G; double F[NF][NQ]
     static constexpr int OFF_W = q2::align16(OFF_A + NBP * KS * (int)sizeof(T));  // T W[WB][NBP][KS]
     static constexpr int CH_END = OFF_W + WB * NBP * KS * (int)sizeof(T);
     static constexpr int F_END = OFF_A + NF * NQ * 8;
@@ -367,7 +416,7 @@ __global__ __launch_bounds__(GM_THREADS, 2) void k_hexgmc(ExecArgs A)
     using ACC = typename H::ACC;
     constexpr int N1 = H::N1, NB = H::NB, NQ = H::NQ, NBP = H::NBP, NT = H::NT, TPB = H::TPB, KC = H::KC;
     constexpr int KS = H::KS, NJ = H::NJ, PT = H::PT, PS = H::PS;
-    constexpr bool CONV = H::CONV;
+    constexpr bool CONV = H::CONV, ELAST = H::ELAST;
     __shared__ __align__(16) unsigned char smem[H::BYTES];
     double *B1 = reinterpret_cast<double *>(smem + H::OFF_TB);
     double *D1 = B1 + N1 * N1;
@@ -419,6 +468,39 @@ __global__ __launch_bounds__(GM_THREADS, 2) void k_hexgmc(ExecArgs A)
             }
             for (int ch = 0; ch < H::NCH; ch++) {
                 const int k0 = ch * KC;
+                if constexpr (ELAST) {
+                    // G chunk: G_ja(q) at depth d = 3 q + j; W chunks:
+                    // w det J sum_k C_rjsk(q) G_kb(q)
+                    for (int it = tid; it < NBP * KC; it += GM_THREADS) {
+                        const int b = it % NBP, dl = it / NBP, d = k0 + dl, q = d / 3, j = d - 3 * (d / 3);
+                        double v = 0.0;
+                        if (b < NB && q < NQ) {
+                            double gx[3];
+                            ref_grad<H>(B1, D1, b, q, gx);
+                            const double *pq = Pq + q * PS;
+                            v = gx[0] * pq[j] + gx[1] * pq[3 + j] + gx[2] * pq[6 + j];
+                        }
+                        Ph[b * KS + dl] = static_cast<T>(v);
+                    }
+                    for (int it = tid; it < nbk * NBP * KC; it += GM_THREADS) {
+                        const int dl = it % KC, rest = it / KC, b = rest % NBP, bk = rest / NBP;
+                        const int d = k0 + dl, q = d / 3, j = d - 3 * (d / 3);
+                        const int rs = blo + bk, r = rs / 3, s = rs - 3 * r;
+                        double x = 0.0;
+                        if (q < NQ && b < NB) {
+                            double gx[3];
+                            ref_grad<H>(B1, D1, b, q, gx);
+                            const double *pq = Pq + q * PS;
+                            double c[3];
+                            material_row<T>(A, e * NQ + q, r, j, s, c);
+#pragma unroll
+                            for (int k = 0; k < 3; k++)
+                                x += c[k] * (gx[0] * pq[k] + gx[1] * pq[3 + k] + gx[2] * pq[6 + k]);
+                            x *= pq[9];
+                        }
+                        W[(bk * NBP + b) * KS + dl] = static_cast<T>(x);
+                    }
+                } else {
                 // Phi chunk: basis b at the chunk's points (zero past NB / NQ)
                 for (int it = tid; it < NBP * KC; it += GM_THREADS) {
                     const int b = it % NBP, ql = it / NBP, q = k0 + ql;
@@ -441,6 +523,7 @@ __global__ __launch_bounds__(GM_THREADS, 2) void k_hexgmc(ExecArgs A)
                         }
                     }
                     W[(bk * NBP + b) * KS + ql] = static_cast<T>(x);
+                }
                 }
                 __syncthreads();
                 // products over the chunk's points: k steps in a loop, the
@@ -498,7 +581,7 @@ template <int P, int FORM, int MM>
 int launch_hexgm(const Plan &, const ExecArgs &A, hipStream_t st)
 {
     static std::atomic<int> resident[64];
-    if constexpr (P <= 3)
+    if constexpr (P <= 3 && FORM != FE_FORM_ELASTICITY)
         return launch_persistent(k_hexgm<P, FORM, MM>, GM_THREADS, A, st, resident);
     else
         return launch_persistent(k_hexgmc<P, FORM, MM>, GM_THREADS, A, st, resident);
@@ -509,6 +592,11 @@ LaunchFn pick(const Plan &p)
 {
     if (p.form == FE_FORM_WDOT && p.mat_kind == FE_MAT_TENSOR_QP) return launch_hexgm<P, FE_FORM_WDOT, MM>;
     if (p.form == FE_FORM_CONVECT) return launch_hexgm<P, FE_FORM_CONVECT, MM>;
+    // elasticity with per-point material at orders 4-5 (below, the generic
+    // kernel keeps all points' gradients in LDS)
+    if constexpr (P >= 4)
+        if (p.form == FE_FORM_ELASTICITY && (p.mat_kind == FE_MAT_ISO_QP || p.mat_kind == FE_MAT_VOIGT_QP))
+            return launch_hexgm<P, FE_FORM_ELASTICITY, MM>;
     return nullptr;
 }
 

@@ -1,8 +1,8 @@
 """Orders 4 and 5 on hexahedra (the highest orders of the paper's table of
 cell and DOF counts) through the C ABI against the FP64 oracle: residual
 and eval by sum factorization in both output layouts (all six forms), the
-adjoint of the elastic energy, element matrices on the matrix cores, and
-the elasticity matrices with per-point material refused at plan creation.  Meshes span several workgroups with a ragged tail (Q4: two
+adjoint of the elastic energy, and element matrices on the matrix cores
+(every form and material kind).  Meshes span several workgroups with a ragged tail (Q4: two
 cells per wave, eight per workgroup; Q5: one per wave, four per workgroup);
 the curvature noise is scaled down with the order so that every Jacobian
 stays positive."""
@@ -248,10 +248,23 @@ def test_matrix_first_residual(orc, p, dims, curved):
     assert elem_rel_err(out.cpu().numpy(), ref) < TOL["fp64"]
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("kind", ["iso_qp", "voigt_qp"])
-def test_matrix_material_per_point_refused(kind):
+@pytest.mark.parametrize("p,dims,curved", HIGH)
+def test_matrix_material_per_point(orc, p, dims, curved, kind, prec):
+    """Elasticity matrices with per-point material at orders 4-5 (one
+    non-symmetric product per block over (point, gradient component) pairs)
+    against the oracle; symmetric up to rounding, as the material is."""
     import paper_2107_04121_amd as fe
-    for p in (4, 5):
-        with pytest.raises(fe.FeError) as ei:
-            fe.Plan("hex", p, "elasticity", "matrix", "fp64", material=kind)
-        assert ei.value.status == 2
+    mesh = _mesh(p, dims, curved, seed=55)
+    nb, nq = orc.sizes("hex", p)
+    mat = _material(kind, mesh, nq)
+    plan = fe.Plan("hex", p, "elasticity", "matrix", prec, material=kind)
+    print(f"[high] matrix Q{p} elasticity/{kind} {prec} variant={plan.variant} cells={mesh.n_cells}", flush=True)
+    assert plan.variant == "mfma"
+    out = plan(_t(mesh.coords), _t(mesh.conn), material=_t(mat, plan.dtype))
+    plan.check()
+    got = out.cpu().numpy()
+    ref = orc.matrix(mesh, "elasticity", mat, kind)
+    assert elem_rel_err(got, ref) < TOL[prec]
+    assert elem_rel_err(got, np.swapaxes(got, 1, 2).astype(np.float64)) < 4 * TOL[prec]

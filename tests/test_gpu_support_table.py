@@ -17,9 +17,7 @@ def documented(cell, p, form, mode, prec, kind):
     if mode in ("residual", "eval"):
         return prec in ("fp64", "fp32")
     if prec in ("fp64", "fp32"):
-        if cell == "tet" or p <= 3:
-            return True
-        return not (form == "elasticity" and kind in ("iso_qp", "voigt_qp"))
+        return True
     # bf16x3 matrices
     return (cell == "hex" and 2 <= p <= 5 and
             (form in ("mass", "vmass", "laplace") or (form == "elasticity" and kind == "iso_cell")))
