@@ -852,9 +852,12 @@ def c8_flops(form, p):
     gradient blocks summed; vector mass: the upper triangle of the scalar
     mass; elasticity: upper triangles of the three diagonal blocks of
     P = g^T g and the three full blocks r < s; weighted dot and convection:
-    the nine full blocks Phi^T W_rs)."""
+    the nine full blocks Phi^T W_rs; elasticity with per-point D: the nine
+    full blocks over 3 n_q (point, gradient component) pairs)."""
     nb = (p + 1) ** 3
     upper = nb * (nb + 1) // 2
+    if form == "elasticity_voigt":  # nine full blocks over 3 n_q (point, component) pairs
+        return 9 * nb * nb * 2 * 3 * nb
     entries = {"laplace": 3 * upper, "vmass": upper, "elasticity": 3 * upper + 3 * nb * nb,
                "wdot": 9 * nb * nb, "convect": 9 * nb * nb}[form]
     return entries * 2 * nb
@@ -878,19 +881,22 @@ def run_c8(args, orc):
         sub = submesh(mesh, idx)
         keep[p] = (mesh, lm)
         Mt = meshgen.tensor_qp(mesh.n_cells, mesh.n_basis, seed=0)
-        for form in ("laplace", "vmass", "wdot", "convect", "elasticity"):
-            kind = {"elasticity": "iso_cell", "wdot": "tensor_qp"}.get(form)
-            mat = {"iso_cell": lm, "tensor_qp": Mt}.get(kind)
+        Dv = meshgen.voigt_random_spd((mesh.n_cells, mesh.n_basis), seed=0)
+        for label in ("laplace", "vmass", "wdot", "convect", "elasticity", "elasticity_voigt"):
+            form = "elasticity" if label.startswith("elasticity") else label
+            kind = {"elasticity": "iso_cell", "elasticity_voigt": "voigt_qp", "wdot": "tensor_qp"}.get(label)
+            mat = {"iso_cell": lm, "tensor_qp": Mt, "voigt_qp": Dv}.get(kind)
             nc = 1 if form == "laplace" else 3
             nd = nc * mesh.n_basis
             U = meshgen.dofs(mesh.n_nodes, nc, seed=0)
             refs = {"matrix": orc.matrix(sub, form, mat[idx] if kind else None, kind,
                                          u=U if form == "convect" else None),
                     "residual": orc.residual(sub, form, U, mat[idx] if kind else None, kind)}
-            mprecs = ("fp64", "fp32") if form in ("wdot", "convect") else ("fp64", "fp32", "bf16x3")
+            mprecs = (("fp64", "fp32") if form in ("wdot", "convect") or kind == "voigt_qp"
+                      else ("fp64", "fp32", "bf16x3"))
             for mode, precs in (("matrix", mprecs), ("residual", ("fp64", "fp32"))):
                 for prec in precs:
-                    primary = (p == 5 and form == "elasticity" and mode == "matrix"
+                    primary = (p == 5 and label == "elasticity" and mode == "matrix"
                                and prec == args.precision)
                     if args.no_extra and not primary:
                         continue
@@ -906,7 +912,8 @@ def run_c8(args, orc):
                     kms = mean(per)
                     esz = out.element_size()
                     outb = nd * nd * esz if mode == "matrix" else nd * esz
-                    matb = {"iso_cell": 2 * esz, "tensor_qp": 9 * mesh.n_basis * esz}.get(kind, 0)
+                    matb = {"iso_cell": 2 * esz, "tensor_qp": 9 * mesh.n_basis * esz,
+                            "voigt_qp": 36 * mesh.n_basis * esz}.get(kind, 0)
                     bpc = (outb + mesh.n_basis * 4 + matb
                            + mesh.n_nodes * (24 + (nc * esz if Ud is not None else 0)) / mesh.n_cells)
                     err = rel_err(out[torch.as_tensor(idx, device=dev)].cpu().numpy(), refs[mode])
@@ -915,10 +922,10 @@ def run_c8(args, orc):
                              hbm_gbs=bpc * mesh.n_cells / (kms * 1e-3) / 1e9,
                              alg_bytes_per_cell=bpc, variant=plan.variant, max_rel_err=err)
                     if mode == "matrix":
-                        tf = c8_flops(form, p) * mesh.n_cells / (kms * 1e-3) / 1e12
-                        r.update(mfma_tflops=tf, mfma_frac=tf / MFMA_PEAK_TFLOPS[prec],
-                                 flops_per_cell=c8_flops(form, p))
-                    paths[f"q{p}/{form}/{mode}/{prec}"] = r
+                        fl = c8_flops(label, p)
+                        tf = fl * mesh.n_cells / (kms * 1e-3) / 1e12
+                        r.update(mfma_tflops=tf, mfma_frac=tf / MFMA_PEAK_TFLOPS[prec], flops_per_cell=fl)
+                    paths[f"q{p}/{label}/{mode}/{prec}"] = r
                     del out
                     torch.cuda.empty_cache()
     prim = paths[f"q5/elasticity/matrix/{args.precision}"]
