@@ -26,7 +26,9 @@ _TORCH_DT = {"fp64": "float64", "fp32": "float32", "bf16x3": "float32"}
 
 
 def n_comp(form: str) -> int:
-    return 3 if form in ("vmass", "elasticity") else 1
+    """Vector components of a form's variables: 1 for mass and Laplace, 3
+    for the vector forms."""
+    return 1 if form in ("mass", "laplace") else 3
 
 
 def reference_sizes(cell: str, order: int):

@@ -131,3 +131,12 @@ def test_emitted_einsum_matches_oracle(orc, expr, args, kind, mode):
         ref = orc.energy(mesh, t.form, U, mat, kind)
     got = np.asarray(got).reshape(ref.shape)
     assert np.abs(got - ref).max() / np.abs(ref).max() < 1e-12
+
+
+def test_component_counts_agree():
+    """The package's n_comp and the front-end's component count agree for
+    every form (mass and Laplace scalar, the rest vector)."""
+    import paper_2107_04121_amd as fe
+    from paper_2107_04121_amd.transpile import _N_COMP
+    for form, nc in _N_COMP.items():
+        assert fe.n_comp(form) == nc, form
