@@ -9,8 +9,10 @@
 // evaluation per cell:
 //   - Q2 hexahedra: the matrix-core cell routine (elasticity GEMM P = G^T W G,
 //     Laplace = P_00 + P_11 + P_22, mass on the matrix cores);
-//   - P1/P2 tetrahedra and Q1 hexahedra: the same product on the matrix
-//     cores for several cells per pass (see SmallMM).
+//   - P2 tetrahedra and Q1 hexahedra: the same product on the matrix cores
+//     for several cells per pass (see SmallMM);
+//   - P1 tetrahedra: one geometry per cell and the factored quadrature sums
+//     (see AffineTet).
 // The counter reset and the kernel are captured once in a HIP graph; running
 // the batch is one graph launch.  Tiles per group are tuned by timing the
 // graph over a small candidate set.
@@ -43,7 +45,7 @@ namespace {
 
 using namespace q2;
 
-// Low-order cells (P1/P2 tetrahedra, Q1 hexahedra) on the matrix cores, CPP
+// Low-order cells (P2 tetrahedra, Q1 hexahedra) on the matrix cores, CPP
 // cells per pass: every (cell, quadrature point) pair's FP64 geometry is
 // evaluated once by one thread, G = dphi/dxi J^-1 goes to LDS in the
 // contraction type, and each wave forms, for CPW cells,
@@ -328,11 +330,122 @@ __device__ void small_tile(const GroupDev &g, int64_t c0, int64_t c1, unsigned *
     }
 }
 
+// P1 tetrahedra: the map is affine, so J, det J and the physical gradients
+// G_i[a] = sum_j dphi_a/dxi_j (J^-1)_ji are the same at every quadrature
+// point and each form's quadrature sum factors exactly into a per-cell
+// geometry term times a reference sum:
+//   K[(r,a),(s,b)] = det J (sum_q w_q) (lambda G_r[a] G_s[b] + mu G_s[a] G_r[b]
+//                    + delta_rs mu G[a].G[b])
+//   L[a][b] = det J (sum_q w_q) G[a].G[b],   M[a][b] = det J sum_q w_q phi_a phi_b.
+// A pass takes 256 cells: one thread per cell evaluates the FP64 geometry and
+// leaves G (in the output type), the two volume factors and the coefficients
+// in LDS; then consecutive threads produce consecutive output entries of the
+// pass's contiguous cells, so every store stream is contiguous.
+template <typename T>
+struct AffineTet {
+    static constexpr int NB = 4, ND = 12, CPP = 256;
+    static constexpr int SA = 17;  // per-cell LDS record (odd stride): G[12], vol, det, lambda, mu
+    static constexpr int OFF_M = 0;  // double Mref[16] = sum_q w_q phi_a phi_b, then sum_q w_q
+    static constexpr int OFF_C = align16(OFF_M + 17 * 8);
+    static constexpr int BYTES = align16(OFF_C + CPP * SA * (int)sizeof(T));
+};
+
+template <typename T>
+__device__ void affine_tile(const GroupDev &g, int64_t c0, int64_t c1, unsigned *flags, unsigned char *smem, int tid)
+{
+    using L = AffineTet<T>;
+    constexpr int NB = L::NB, ND = L::ND, NQ = cell_nq(FE_CELL_TET, 1), SA = L::SA;
+    double *Mref = reinterpret_cast<double *>(smem + L::OFF_M);
+    T *rec = reinterpret_cast<T *>(smem + L::OFF_C);
+    if (c0 >= c1) return;
+    if (tid < NB * NB + 1) {
+        const int a = tid / NB, b = tid - a * NB;
+        double s = 0.0;
+        for (int q = 0; q < NQ; q++)
+            s += g.tab.w[q] * (tid < NB * NB ? g.tab.bf[q * NB + a] * g.tab.bf[q * NB + b] : 1.0);
+        Mref[tid] = s;
+    }
+    __syncthreads();
+    const bool want_el = g.forms & FORM_BIT_ELAST;
+    unsigned fault = 0;
+    for (int64_t e0 = c0; e0 < c1; e0 += L::CPP) {
+        const int n = c1 - e0 < L::CPP ? int(c1 - e0) : L::CPP;
+        // 1. geometry of cell e0 + tid
+        if (tid < n) {
+            const int64_t e = e0 + tid;
+            double J[3][3] = {};
+            double gr[NB][3];
+#pragma unroll
+            for (int a = 0; a < NB; a++) {
+                int64_t nd = g.conn[e * NB + a];
+                if (nd < 0 || nd >= g.n_nodes) {
+                    fault |= FAULT_INDEX;
+                    nd = 0;
+                }
+                const double x0 = g.coords[3 * nd], x1 = g.coords[3 * nd + 1], x2 = g.coords[3 * nd + 2];
+#pragma unroll
+                for (int j = 0; j < 3; j++) {
+                    gr[a][j] = g.tab.bfgT[(a * 3 + j) * NQ];  // constant over the cell
+                    J[0][j] = fma(x0, gr[a][j], J[0][j]);
+                    J[1][j] = fma(x1, gr[a][j], J[1][j]);
+                    J[2][j] = fma(x2, gr[a][j], J[2][j]);
+                }
+            }
+            double Ji[3][3];
+            const double det = inverse3(J, Ji);
+            if (!(det > 0.0)) fault |= FAULT_DET;
+            T *r = rec + tid * SA;
+#pragma unroll
+            for (int a = 0; a < NB; a++)
+#pragma unroll
+                for (int i = 0; i < 3; i++)
+                    r[i * NB + a] = static_cast<T>(gr[a][0] * Ji[0][i] + gr[a][1] * Ji[1][i] + gr[a][2] * Ji[2][i]);
+            r[12] = static_cast<T>(det * Mref[NB * NB]);
+            r[13] = static_cast<T>(det);
+            if (want_el) {
+                r[14] = static_cast<const T *>(g.mat)[2 * e];
+                r[15] = static_cast<const T *>(g.mat)[2 * e + 1];
+            }
+        }
+        __syncthreads();
+        // 2. outputs, entry by entry
+        if (want_el) {
+            T *out = static_cast<T *>(g.out_el) + e0 * (ND * ND);
+            for (int f = tid; f < n * ND * ND; f += 256) {
+                const int c = f / (ND * ND), rem = f - c * (ND * ND), row = rem / ND, cl = rem - row * ND;
+                const int r = row / NB, a = row - r * NB, s = cl / NB, b = cl - s * NB;
+                const T *G = rec + c * SA;
+                const T lam = G[14], mu = G[15];
+                T v = lam * G[r * NB + a] * G[s * NB + b] + mu * G[s * NB + a] * G[r * NB + b];
+                if (r == s) v += mu * (G[a] * G[b] + G[NB + a] * G[NB + b] + G[2 * NB + a] * G[2 * NB + b]);
+                q2::out_store(G[12] * v, out + f);
+            }
+        }
+        if (g.forms & FORM_BIT_LAPLACE) {
+            T *out = static_cast<T *>(g.out_lap) + e0 * (NB * NB);
+            for (int f = tid; f < n * NB * NB; f += 256) {
+                const int c = f / (NB * NB), a = (f / NB) % NB, b = f % NB;
+                const T *G = rec + c * SA;
+                q2::out_store(G[12] * (G[a] * G[b] + G[NB + a] * G[NB + b] + G[2 * NB + a] * G[2 * NB + b]), out + f);
+            }
+        }
+        if (g.forms & FORM_BIT_MASS) {
+            T *out = static_cast<T *>(g.out_mass) + e0 * (NB * NB);
+            for (int f = tid; f < n * NB * NB; f += 256) {
+                const int c = f / (NB * NB), ab = f % (NB * NB);
+                q2::out_store(static_cast<T>(static_cast<double>(rec[c * SA + 13]) * Mref[ab]), out + f);
+            }
+        }
+        __syncthreads();  // the records are rewritten by the next pass
+    }
+    if (fault) raise_fault(flags, fault);
+}
+
 template <typename T>
 struct BatchLds {
     static constexpr int MM = sizeof(T) == 8 ? MM_F64 : MM_F32;
     static constexpr int v0 = Q2Layout<MM>::BYTES;
-    static constexpr int v1 = SmallMM<FE_CELL_TET, 1, T>::BYTES;
+    static constexpr int v1 = AffineTet<T>::BYTES;
     static constexpr int v2 = SmallMM<FE_CELL_TET, 2, T>::BYTES;
     static constexpr int v3 = SmallMM<FE_CELL_HEX, 1, T>::BYTES;
     static constexpr int m01 = v0 > v1 ? v0 : v1, m23 = v2 > v3 ? v2 : v3;
@@ -386,7 +499,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) void k_batch(const Bat
         } else if (g.cell == FE_CELL_HEX && g.order == 1) {
             small_tile<FE_CELL_HEX, 1, T>(g, c0, c1, flags, smem, tid);
         } else if (g.cell == FE_CELL_TET && g.order == 1) {
-            small_tile<FE_CELL_TET, 1, T>(g, c0, c1, flags, smem, tid);
+            affine_tile<T>(g, c0, c1, flags, smem, tid);
         } else if (g.cell == FE_CELL_TET && g.order == 2) {
             small_tile<FE_CELL_TET, 2, T>(g, c0, c1, flags, smem, tid);
         }
@@ -397,7 +510,7 @@ int group_pass_cells(int cell, int order, bool f64)
 {
     if (cell == FE_CELL_HEX && order == 2) return 1;
     if (cell == FE_CELL_HEX) return f64 ? SmallMM<FE_CELL_HEX, 1, double>::CPP : SmallMM<FE_CELL_HEX, 1, float>::CPP;
-    if (order == 1) return f64 ? SmallMM<FE_CELL_TET, 1, double>::CPP : SmallMM<FE_CELL_TET, 1, float>::CPP;
+    if (order == 1) return AffineTet<double>::CPP;
     return f64 ? SmallMM<FE_CELL_TET, 2, double>::CPP : SmallMM<FE_CELL_TET, 2, float>::CPP;
 }
 

@@ -211,7 +211,10 @@ __device__ __forceinline__ typename MMT<MM>::acc mass_tile(const double *B1, con
         if (f >= NB) return 0.0;
         return B1[(q % 3) * 3 + f % 3] * B1[((q / 3) % 3) * 3 + (f / 3) % 3] * B1[(q / 9) * 3 + f / 9];
     };
-#pragma unroll
+    // kept as a loop: unrolled, its table loads are all hoisted and stay
+    // live next to the elasticity accumulators (the FP32 batched kernel then
+    // spilled to scratch)
+#pragma unroll 1
     for (int kk = 0; kk < 7; kk++) {
         const int k = 4 * kk + grp;
         const bool ok = k < NQ;

@@ -95,3 +95,60 @@ def test_batch_form_subset_and_faults(orc):
     with pytest.raises(fe.FeError) as ei:
         b2.check()
     assert ei.value.status == 3
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_p1_tets_passes_and_subsets(orc, prec):
+    """P1 tetrahedra take the affine routine: 256 cells per pass.  3,024
+    cells in items of 512 (a ragged last pass and item) and a form subset
+    without elasticity, against the oracle."""
+    import torch
+    import paper_2107_04121_amd as fe
+    dt = {"fp64": torch.float64, "fp32": torch.float32}[prec]
+    m = meshgen.tet_mesh((9, 8, 7), 1, alpha=0.2, seed=21)
+    lm = meshgen.lame_cell(m.n_cells, seed=22)
+    b = fe.Batch([dict(cell="tet", order=1, coords=_t(m.coords),
+                       conn=_t(m.conn), material=_t(lm, dt),
+                       forms=("mass", "laplace", "elasticity"), tile=300),
+                  dict(cell="tet", order=1, coords=_t(m.coords),
+                       conn=_t(m.conn[:700]), forms=("mass", "laplace"))],
+                 precision=prec, autotune=False)
+    print(f"[batch-p1] {prec} tiles={b.tiles} cells={m.n_cells}", flush=True)
+    assert b.tiles[0] == 512
+    o = b.run()
+    b.check()
+    sub = meshgen.Mesh(coords=m.coords, conn=m.conn[:700], cell="tet",
+                       order=1, h=m.h)
+    for form in ("mass", "laplace", "elasticity"):
+        mat, kind = (lm, "iso_cell") if form == "elasticity" else (None, None)
+        ref = orc.matrix(m, form, mat, kind)
+        err = _err(o[0][form].cpu().numpy(), ref)
+        print(f"[batch-p1] {form} {err:.2e}", flush=True)
+        assert err < TOL[prec], (form, err)
+        if form != "elasticity":
+            assert _err(o[1][form].cpu().numpy(),
+                        orc.matrix(sub, form)) < TOL[prec]
+    assert set(o[1]) == {"mass", "laplace"}
+
+
+def test_batch_p1_tet_faults():
+    import paper_2107_04121_amd as fe
+    m = meshgen.tet_mesh((4, 3, 3), 1, alpha=0.15, seed=23)
+    conn = m.conn.copy()
+    conn[200, [0, 1]] = conn[200, [1, 0]]     # inverted tetrahedron
+    b = fe.Batch([dict(cell="tet", order=1, coords=_t(m.coords),
+                        conn=_t(conn), forms=("laplace",))],
+                 precision="fp32", autotune=False)
+    b.run()
+    with pytest.raises(fe.FeError) as ei:
+        b.check()
+    assert ei.value.status == 3
+    conn = m.conn.copy()
+    conn[17, 2] = m.n_nodes                   # node number out of range
+    b = fe.Batch([dict(cell="tet", order=1, coords=_t(m.coords),
+                        conn=_t(conn), forms=("mass",))],
+                 precision="fp64", autotune=False)
+    b.run()
+    with pytest.raises(fe.FeError) as ei:
+        b.check()
+    assert ei.value.status == 4
