@@ -64,16 +64,23 @@ struct SmallMM {
     static constexpr int KS = NQP + 1;            // odd row stride of the operand
     static constexpr int NT = ND > 16 ? 2 : 1;    // 16x16 tiles per side of P
     static constexpr int RP = 16 * NT;            // operand rows, padded
-    static constexpr int CPW = NQ > 8 ? 1 : (NB > 4 ? 2 : 4);  // cells per wave
+    // cells per wave: 4 for FP32 Q1 hexahedra (16 cells per pass, 128
+    // geometry threads), 2 otherwise (the FP64 records would not fit next
+    // to a second workgroup)
+    static constexpr int CPW = NB > 4 && (sizeof(T) == 8 || NQ > 8) ? 2 : 4;
     static constexpr int CPP = 4 * CPW;                       // cells per pass
     static constexpr int PS = ND + 1, MS = NB + 1;            // LDS row strides of P, M
     static constexpr int XB = CPP * NB * 3;                                    // doubles per x buffer
     static constexpr int OFF_X = 0;                                            // double x[2][CPP][NB*3]
     static constexpr int OFF_LM = align16(OFF_X + 2 * XB * 8);                 // T lm[2][CPP][2]
     static constexpr int OFF_WD = align16(OFF_LM + 2 * CPP * 2 * (int)sizeof(T));  // double wd[CPP][NQP]
-    static constexpr int OFF_G = align16(OFF_WD + CPP * NQP * 8);              // T G[CPP][RP][KS]
-    static constexpr int OFF_P = align16(OFF_G + CPP * RP * KS * (int)sizeof(T));  // T P[CPP][ND][PS]
-    static constexpr int OFF_M = align16(OFF_P + CPP * ND * PS * (int)sizeof(T));  // T M[CPP][NB][MS]
+    // a cell's operand G[RP][KS] and its product P[ND][PS] share one record
+    // of CR entries: only the wave that owns the cell reads G, and it has
+    // read all of it (its MFMA operands) before it writes P
+    static constexpr int CR = RP * KS > ND * PS ? RP * KS : ND * PS;
+    static constexpr int OFF_G = align16(OFF_WD + CPP * NQP * 8);                // T G[CPP][CR]
+    static constexpr int OFF_P = OFF_G;                                          // T P[CPP][CR]
+    static constexpr int OFF_M = align16(OFF_P + CPP * CR * (int)sizeof(T));     // T M[CPP][NB][MS]
     static constexpr int BYTES = align16(OFF_M + CPP * NB * MS * (int)sizeof(T));
 };
 
@@ -144,7 +151,7 @@ __device__ void small_pass(const GroupDev &g, int64_t e0, int n, int buf, int64_
     if constexpr (ZR + ZC > 0)
         for (int t = tid; t < CPP * (ZR + ZC); t += 256) {
             const int c = t / (ZR + ZC), u = t - c * (ZR + ZC);
-            T *G = Gs + c * RP * KS;
+            T *G = Gs + c * L::CR;
             if (u < ZR) G[ND * KS + u] = T(0);
             else if constexpr (ZC > 0) G[((u - ZR) / (NQP - NQ)) * KS + NQ + (u - ZR) % (NQP - NQ)] = T(0);
         }
@@ -183,7 +190,7 @@ __device__ void small_pass(const GroupDev &g, int64_t e0, int n, int buf, int64_
         const bool live = c < n;
         if (live && !(det > 0.0)) fault |= FAULT_DET;
         wd[c * NQP + q] = live ? g.tab.w[q] * det : 0.0;
-        T *G = Gs + c * RP * KS + q;
+        T *G = Gs + c * L::CR + q;
 #pragma unroll
         for (int a = 0; a < NB; a++) {
             const double r0 = g.tab.bfgT[(a * 3 + 0) * NQ + q], r1 = g.tab.bfgT[(a * 3 + 1) * NQ + q],
@@ -221,7 +228,7 @@ __device__ void small_pass(const GroupDev &g, int64_t e0, int n, int buf, int64_
 #pragma unroll
         for (int k = 0; k < CPW; k++) {
             const int c = wave * CPW + k;
-            const T *G = Gs + c * RP * KS;
+            const T *G = Gs + c * L::CR;
             ACC acc[NT][NT], am{};
 #pragma unroll
             for (int i = 0; i < NT; i++)
@@ -246,7 +253,7 @@ __device__ void small_pass(const GroupDev &g, int64_t e0, int n, int buf, int64_
             }
             // accumulator layout: column = lane % 16; FP32 rows 4*(lane/16)+v,
             // FP64 rows lane/16 + 4v
-            T *Pc = Ps + c * ND * PS;
+            T *Pc = Ps + c * L::CR;
 #pragma unroll
             for (int i = 0; i < NT; i++)
 #pragma unroll
@@ -282,7 +289,7 @@ __device__ void small_pass(const GroupDev &g, int64_t e0, int n, int buf, int64_
         for (int f = tid; f < n * ND * ND; f += 256) {
             const int c = f / (ND * ND), rem = f - c * (ND * ND), row = rem / ND, cl = rem - row * ND;
             const int r = row / NB, a = row - r * NB, s = cl / NB, b = cl - s * NB;
-            const T *Pc = Ps + c * ND * PS;
+            const T *Pc = Ps + c * L::CR;
             const T lam = lm[2 * c], mu = lm[2 * c + 1];
             T v = lam * Pc[row * PS + cl] + mu * Pc[(s * NB + a) * PS + r * NB + b];
             if (r == s) v += mu * (Pc[a * PS + b] + Pc[(NB + a) * PS + NB + b] + Pc[(2 * NB + a) * PS + 2 * NB + b]);
@@ -293,7 +300,7 @@ __device__ void small_pass(const GroupDev &g, int64_t e0, int n, int buf, int64_
         T *out = static_cast<T *>(g.out_lap) + e0 * (NB * NB);
         for (int f = tid; f < n * NB * NB; f += 256) {
             const int c = f / (NB * NB), rem = f - c * (NB * NB), a = rem / NB, b = rem - a * NB;
-            const T *Pc = Ps + c * ND * PS;
+            const T *Pc = Ps + c * L::CR;
             q2::out_store(Pc[a * PS + b] + Pc[(NB + a) * PS + NB + b] + Pc[(2 * NB + a) * PS + 2 * NB + b], out + f);
         }
     }
