@@ -302,6 +302,9 @@ int fe_energy_grad(fe_plan plan, fe_incidence inc, int64_t n_cells, int64_t n_no
  *          (1 << FE_FORM_ELASTICITY); all of a group's forms share one
  *          geometry evaluation per cell;
  *   tile:  cells per work item, 0 = default (tuned when autotune is on);
+ *          rounded up to a multiple of the group's pass (cells evaluated
+ *          together: 256 for P1 tets, 8 for P2 tets, 16 for FP32 and 8 for
+ *          FP64 Q1 hexahedra, 1 for Q2); the default is four passes;
  *   material: [n_cells][2] (lambda, mu) when ELASTICITY is requested;
  *   out_mass, out_laplace: [n_cells][n_basis][n_basis];
  *   out_elasticity: [n_cells][3 n_basis][3 n_basis] (16-byte aligned). */
