@@ -283,32 +283,57 @@ __device__ void small_pass(const GroupDev &g, int64_t e0, int n, int buf, int64_
     if (want_el && tid < 2 * CPP) lmn[tid] = plm;
     __syncthreads();
 
-    // 4. outputs of the pass's n contiguous cells
+    // 4. outputs of the pass's n contiguous cells.  The rows of all n cells
+    //    are contiguous in each output; a sweep covers RPS whole rows with
+    //    one thread per entry, so a thread keeps its column (and the block
+    //    indices derived from it) and only steps its row and cell, and the
+    //    stores of a sweep are one contiguous run.
     if (want_el) {
-        T *out = static_cast<T *>(g.out_el) + e0 * (ND * ND);
-        for (int f = tid; f < n * ND * ND; f += 256) {
-            const int c = f / (ND * ND), rem = f - c * (ND * ND), row = rem / ND, cl = rem - row * ND;
-            const int r = row / NB, a = row - r * NB, s = cl / NB, b = cl - s * NB;
-            const T *Pc = Ps + c * L::CR;
-            const T lam = lm[2 * c], mu = lm[2 * c + 1];
-            T v = lam * Pc[row * PS + cl] + mu * Pc[(s * NB + a) * PS + r * NB + b];
-            if (r == s) v += mu * (Pc[a * PS + b] + Pc[(NB + a) * PS + NB + b] + Pc[(2 * NB + a) * PS + 2 * NB + b]);
-            q2::out_store(v, out + f);
+        constexpr int RPS = 256 / ND;
+        if (tid < RPS * ND) {
+            const int col = tid % ND, s = col / NB, b = col - s * NB;
+            int row = (tid / ND) % ND, c = tid / (ND * ND);
+            T *out = static_cast<T *>(g.out_el) + e0 * (ND * ND) + tid;
+            for (int rr = tid / ND; rr < n * ND; rr += RPS) {
+                const int r = row / NB, a = row - r * NB;
+                const T *Pc = Ps + c * L::CR;
+                const T lam = lm[2 * c], mu = lm[2 * c + 1];
+                T v = lam * Pc[row * PS + col] + mu * Pc[(s * NB + a) * PS + r * NB + b];
+                if (r == s) v += mu * (Pc[a * PS + b] + Pc[(NB + a) * PS + NB + b] + Pc[(2 * NB + a) * PS + 2 * NB + b]);
+                q2::out_store(v, out);
+                out += RPS * ND;
+                row += RPS % ND;
+                c += RPS / ND;
+                if (row >= ND) {
+                    row -= ND;
+                    c++;
+                }
+            }
         }
     }
-    if (g.forms & FORM_BIT_LAPLACE) {
-        T *out = static_cast<T *>(g.out_lap) + e0 * (NB * NB);
-        for (int f = tid; f < n * NB * NB; f += 256) {
-            const int c = f / (NB * NB), rem = f - c * (NB * NB), a = rem / NB, b = rem - a * NB;
-            const T *Pc = Ps + c * L::CR;
-            q2::out_store(Pc[a * PS + b] + Pc[(NB + a) * PS + NB + b] + Pc[(2 * NB + a) * PS + 2 * NB + b], out + f);
-        }
-    }
-    if (g.forms & FORM_BIT_MASS) {
-        T *out = static_cast<T *>(g.out_mass) + e0 * (NB * NB);
-        for (int f = tid; f < n * NB * NB; f += 256) {
-            const int c = f / (NB * NB), rem = f - c * (NB * NB), a = rem / NB, b = rem - a * NB;
-            q2::out_store(Ms[(c * NB + a) * MS + b], out + f);
+    constexpr int RPB = 256 / NB;  // rows per sweep of the nb x nb outputs
+    if ((g.forms & (FORM_BIT_LAPLACE | FORM_BIT_MASS)) && tid < RPB * NB) {
+        const int b = tid % NB;
+        const bool lap = g.forms & FORM_BIT_LAPLACE, mass = g.forms & FORM_BIT_MASS;
+        int a = (tid / NB) % NB, c = tid / (NB * NB);
+        T *ol = lap ? static_cast<T *>(g.out_lap) + e0 * (NB * NB) + tid : nullptr;
+        T *om = mass ? static_cast<T *>(g.out_mass) + e0 * (NB * NB) + tid : nullptr;
+        for (int rr = tid / NB; rr < n * NB; rr += RPB) {
+            if (lap) {
+                const T *Pc = Ps + c * L::CR;
+                q2::out_store(Pc[a * PS + b] + Pc[(NB + a) * PS + NB + b] + Pc[(2 * NB + a) * PS + 2 * NB + b], ol);
+                ol += RPB * NB;
+            }
+            if (mass) {
+                q2::out_store(Ms[(c * NB + a) * MS + b], om);
+                om += RPB * NB;
+            }
+            a += RPB % NB;
+            c += RPB / NB;
+            if (a >= NB) {
+                a -= NB;
+                c++;
+            }
         }
     }
     if (fault) raise_fault(flags, fault);
@@ -415,17 +440,30 @@ __device__ void affine_tile(const GroupDev &g, int64_t c0, int64_t c1, unsigned 
             }
         }
         __syncthreads();
-        // 2. outputs, entry by entry
+        // 2. outputs, one thread per entry; the elasticity rows go in sweeps
+        //    of RPS whole rows, so a thread keeps its column and steps its
+        //    row and cell (one contiguous store run per sweep)
         if (want_el) {
-            T *out = static_cast<T *>(g.out_el) + e0 * (ND * ND);
-            for (int f = tid; f < n * ND * ND; f += 256) {
-                const int c = f / (ND * ND), rem = f - c * (ND * ND), row = rem / ND, cl = rem - row * ND;
-                const int r = row / NB, a = row - r * NB, s = cl / NB, b = cl - s * NB;
-                const T *G = rec + c * SA;
-                const T lam = G[14], mu = G[15];
-                T v = lam * G[r * NB + a] * G[s * NB + b] + mu * G[s * NB + a] * G[r * NB + b];
-                if (r == s) v += mu * (G[a] * G[b] + G[NB + a] * G[NB + b] + G[2 * NB + a] * G[2 * NB + b]);
-                q2::out_store(G[12] * v, out + f);
+            constexpr int RPS = 256 / ND;
+            if (tid < RPS * ND) {
+                const int col = tid % ND, s = col / NB, b = col - s * NB;
+                int row = (tid / ND) % ND, c = tid / (ND * ND);
+                T *out = static_cast<T *>(g.out_el) + e0 * (ND * ND) + tid;
+                for (int rr = tid / ND; rr < n * ND; rr += RPS) {
+                    const int r = row / NB, a = row - r * NB;
+                    const T *G = rec + c * SA;
+                    const T lam = G[14], mu = G[15];
+                    T v = lam * G[r * NB + a] * G[s * NB + b] + mu * G[s * NB + a] * G[r * NB + b];
+                    if (r == s) v += mu * (G[a] * G[b] + G[NB + a] * G[NB + b] + G[2 * NB + a] * G[2 * NB + b]);
+                    q2::out_store(G[12] * v, out);
+                    out += RPS * ND;
+                    row += RPS % ND;
+                    c += RPS / ND;
+                    if (row >= ND) {
+                        row -= ND;
+                        c++;
+                    }
+                }
             }
         }
         if (g.forms & FORM_BIT_LAPLACE) {
