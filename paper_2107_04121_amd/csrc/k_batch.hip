@@ -102,21 +102,21 @@ __device__ __forceinline__ unsigned small_gather(const GroupDev &g, int64_t e0, 
         const int c = t / NB, a = t - c * NB;
         double x0 = 0.0, x1 = 0.0, x2 = 0.0;
         if (c < n) {
-            int64_t nd = g.conn[(e0 + c) * NB + a];
+            int64_t nd = gmem(g.conn)[(e0 + c) * NB + a];
             if (nd < 0 || nd >= g.n_nodes) {
                 fault |= FAULT_INDEX;
                 nd = 0;
             }
-            x0 = g.coords[3 * nd];
-            x1 = g.coords[3 * nd + 1];
-            x2 = g.coords[3 * nd + 2];
+            x0 = gmem(g.coords)[3 * nd];
+            x1 = gmem(g.coords)[3 * nd + 1];
+            x2 = gmem(g.coords)[3 * nd + 2];
         }
         xb[t * 3] = x0;
         xb[t * 3 + 1] = x1;
         xb[t * 3 + 2] = x2;
     }
     if ((g.forms & FORM_BIT_ELAST) && tid < 2 * CPP)
-        lmb[tid] = tid < 2 * n ? static_cast<const T *>(g.mat)[2 * e0 + tid] : T(0);
+        lmb[tid] = tid < 2 * n ? gmem(static_cast<const T *>(g.mat))[2 * e0 + tid] : T(0);
     return fault;
 }
 
@@ -165,9 +165,9 @@ __device__ void small_pass(const GroupDev &g, int64_t e0, int n, int buf, int64_
 #pragma unroll
     for (int k = 0; k < PF; k++) {
         const int t = tid + 256 * k, c = t / NB;
-        pn[k] = (t < CPP * NB && c < nn_next) ? g.conn[en * NB + t] : 0;
+        pn[k] = (t < CPP * NB && c < nn_next) ? gmem(g.conn)[en * NB + t] : 0;
     }
-    if (want_el && tid < 2 * nn_next) plm = static_cast<const T *>(g.mat)[2 * en + tid];
+    if (want_el && tid < 2 * nn_next) plm = gmem(static_cast<const T *>(g.mat))[2 * en + tid];
 
     // 2. FP64 geometry, one (cell, point) pair per thread
     for (int t = tid; t < CPP * NQ; t += 256) {
@@ -179,7 +179,7 @@ __device__ void small_pass(const GroupDev &g, int64_t e0, int n, int buf, int64_
             const double x0 = x[a * 3], x1 = x[a * 3 + 1], x2 = x[a * 3 + 2];
 #pragma unroll
             for (int j = 0; j < 3; j++) {
-                const double gr = g.tab.bfgT[(a * 3 + j) * NQ + q];
+                const double gr = gmem(g.tab.bfgT)[(a * 3 + j) * NQ + q];
                 J[0][j] = fma(x0, gr, J[0][j]);
                 J[1][j] = fma(x1, gr, J[1][j]);
                 J[2][j] = fma(x2, gr, J[2][j]);
@@ -189,12 +189,12 @@ __device__ void small_pass(const GroupDev &g, int64_t e0, int n, int buf, int64_
         const double det = inverse3(J, Ji);
         const bool live = c < n;
         if (live && !(det > 0.0)) fault |= FAULT_DET;
-        wd[c * NQP + q] = live ? g.tab.w[q] * det : 0.0;
+        wd[c * NQP + q] = live ? gmem(g.tab.w)[q] * det : 0.0;
         T *G = Gs + c * L::CR + q;
 #pragma unroll
         for (int a = 0; a < NB; a++) {
-            const double r0 = g.tab.bfgT[(a * 3 + 0) * NQ + q], r1 = g.tab.bfgT[(a * 3 + 1) * NQ + q],
-                         r2 = g.tab.bfgT[(a * 3 + 2) * NQ + q];
+            const double r0 = gmem(g.tab.bfgT)[(a * 3 + 0) * NQ + q], r1 = gmem(g.tab.bfgT)[(a * 3 + 1) * NQ + q],
+                         r2 = gmem(g.tab.bfgT)[(a * 3 + 2) * NQ + q];
 #pragma unroll
             for (int i = 0; i < 3; i++)
                 G[(i * NB + a) * KS] = live ? static_cast<T>(r0 * Ji[0][i] + r1 * Ji[1][i] + r2 * Ji[2][i]) : T(0);
@@ -216,9 +216,9 @@ __device__ void small_pass(const GroupDev &g, int64_t e0, int n, int buf, int64_
                 fault |= FAULT_INDEX;
                 nd = 0;
             }
-            px[k][0] = g.coords[3 * nd];
-            px[k][1] = g.coords[3 * nd + 1];
-            px[k][2] = g.coords[3 * nd + 2];
+            px[k][0] = gmem(g.coords)[3 * nd];
+            px[k][1] = gmem(g.coords)[3 * nd + 1];
+            px[k][2] = gmem(g.coords)[3 * nd + 2];
         }
     }
 
@@ -248,7 +248,7 @@ __device__ void small_pass(const GroupDev &g, int64_t e0, int n, int buf, int64_
                 for (int i = 0; i < NT; i++)
 #pragma unroll
                     for (int j = 0; j < NT; j++) mma4<T>(a[i], b[j], acc[i][j]);
-                const T phi = (col < NB && q < NQ) ? static_cast<T>(g.tab.bf[q * NB + col]) : T(0);
+                const T phi = (col < NB && q < NQ) ? static_cast<T>(gmem(g.tab.bf)[q * NB + col]) : T(0);
                 mma4<T>(phi * w, phi, am);
             }
             // accumulator layout: column = lane % 16; FP32 rows 4*(lane/16)+v,
@@ -293,7 +293,7 @@ __device__ void small_pass(const GroupDev &g, int64_t e0, int n, int buf, int64_
         if (tid < RPS * ND) {
             const int col = tid % ND, s = col / NB, b = col - s * NB;
             int row = (tid / ND) % ND, c = tid / (ND * ND);
-            T *out = static_cast<T *>(g.out_el) + e0 * (ND * ND) + tid;
+            auto out = gmem(static_cast<T *>(g.out_el)) + e0 * (ND * ND) + tid;
             for (int rr = tid / ND; rr < n * ND; rr += RPS) {
                 const int r = row / NB, a = row - r * NB;
                 const T *Pc = Ps + c * L::CR;
@@ -316,8 +316,8 @@ __device__ void small_pass(const GroupDev &g, int64_t e0, int n, int buf, int64_
         const int b = tid % NB;
         const bool lap = g.forms & FORM_BIT_LAPLACE, mass = g.forms & FORM_BIT_MASS;
         int a = (tid / NB) % NB, c = tid / (NB * NB);
-        T *ol = lap ? static_cast<T *>(g.out_lap) + e0 * (NB * NB) + tid : nullptr;
-        T *om = mass ? static_cast<T *>(g.out_mass) + e0 * (NB * NB) + tid : nullptr;
+        auto ol = gmem(lap ? static_cast<T *>(g.out_lap) + e0 * (NB * NB) + tid : nullptr);
+        auto om = gmem(mass ? static_cast<T *>(g.out_mass) + e0 * (NB * NB) + tid : nullptr);
         for (int rr = tid / NB; rr < n * NB; rr += RPB) {
             if (lap) {
                 const T *Pc = Ps + c * L::CR;
@@ -394,7 +394,7 @@ __device__ void affine_tile(const GroupDev &g, int64_t c0, int64_t c1, unsigned 
         const int a = tid / NB, b = tid - a * NB;
         double s = 0.0;
         for (int q = 0; q < NQ; q++)
-            s += g.tab.w[q] * (tid < NB * NB ? g.tab.bf[q * NB + a] * g.tab.bf[q * NB + b] : 1.0);
+            s += gmem(g.tab.w)[q] * (tid < NB * NB ? gmem(g.tab.bf)[q * NB + a] * gmem(g.tab.bf)[q * NB + b] : 1.0);
         Mref[tid] = s;
     }
     __syncthreads();
@@ -409,15 +409,15 @@ __device__ void affine_tile(const GroupDev &g, int64_t c0, int64_t c1, unsigned 
             double gr[NB][3];
 #pragma unroll
             for (int a = 0; a < NB; a++) {
-                int64_t nd = g.conn[e * NB + a];
+                int64_t nd = gmem(g.conn)[e * NB + a];
                 if (nd < 0 || nd >= g.n_nodes) {
                     fault |= FAULT_INDEX;
                     nd = 0;
                 }
-                const double x0 = g.coords[3 * nd], x1 = g.coords[3 * nd + 1], x2 = g.coords[3 * nd + 2];
+                const double x0 = gmem(g.coords)[3 * nd], x1 = gmem(g.coords)[3 * nd + 1], x2 = gmem(g.coords)[3 * nd + 2];
 #pragma unroll
                 for (int j = 0; j < 3; j++) {
-                    gr[a][j] = g.tab.bfgT[(a * 3 + j) * NQ];  // constant over the cell
+                    gr[a][j] = gmem(g.tab.bfgT)[(a * 3 + j) * NQ];  // constant over the cell
                     J[0][j] = fma(x0, gr[a][j], J[0][j]);
                     J[1][j] = fma(x1, gr[a][j], J[1][j]);
                     J[2][j] = fma(x2, gr[a][j], J[2][j]);
@@ -435,8 +435,8 @@ __device__ void affine_tile(const GroupDev &g, int64_t c0, int64_t c1, unsigned 
             r[12] = static_cast<T>(det * Mref[NB * NB]);
             r[13] = static_cast<T>(det);
             if (want_el) {
-                r[14] = static_cast<const T *>(g.mat)[2 * e];
-                r[15] = static_cast<const T *>(g.mat)[2 * e + 1];
+                r[14] = gmem(static_cast<const T *>(g.mat))[2 * e];
+                r[15] = gmem(static_cast<const T *>(g.mat))[2 * e + 1];
             }
         }
         __syncthreads();
@@ -448,7 +448,7 @@ __device__ void affine_tile(const GroupDev &g, int64_t c0, int64_t c1, unsigned 
             if (tid < RPS * ND) {
                 const int col = tid % ND, s = col / NB, b = col - s * NB;
                 int row = (tid / ND) % ND, c = tid / (ND * ND);
-                T *out = static_cast<T *>(g.out_el) + e0 * (ND * ND) + tid;
+                auto out = gmem(static_cast<T *>(g.out_el)) + e0 * (ND * ND) + tid;
                 for (int rr = tid / ND; rr < n * ND; rr += RPS) {
                     const int r = row / NB, a = row - r * NB;
                     const T *G = rec + c * SA;
@@ -467,7 +467,7 @@ __device__ void affine_tile(const GroupDev &g, int64_t c0, int64_t c1, unsigned 
             }
         }
         if (g.forms & FORM_BIT_LAPLACE) {
-            T *out = static_cast<T *>(g.out_lap) + e0 * (NB * NB);
+            const auto out = gmem(static_cast<T *>(g.out_lap)) + e0 * (NB * NB);
             for (int f = tid; f < n * NB * NB; f += 256) {
                 const int c = f / (NB * NB), a = (f / NB) % NB, b = f % NB;
                 const T *G = rec + c * SA;
@@ -475,7 +475,7 @@ __device__ void affine_tile(const GroupDev &g, int64_t c0, int64_t c1, unsigned 
             }
         }
         if (g.forms & FORM_BIT_MASS) {
-            T *out = static_cast<T *>(g.out_mass) + e0 * (NB * NB);
+            const auto out = gmem(static_cast<T *>(g.out_mass)) + e0 * (NB * NB);
             for (int f = tid; f < n * NB * NB; f += 256) {
                 const int c = f / (NB * NB), ab = f % (NB * NB);
                 q2::out_store(static_cast<T>(static_cast<double>(rec[c * SA + 13]) * Mref[ab]), out + f);
@@ -509,7 +509,7 @@ __device__ __forceinline__ void q2_item(const GroupDev &g, int64_t c0, int64_t c
 __global__ void k_batch_reset(unsigned long long *ctr) { ctr[0] = 0ULL; }
 
 template <typename T>
-__global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) void k_batch(const BatchDev *B, unsigned long long *ctr, unsigned *flags)
+__global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) void k_batch(const BatchDev *__restrict__ B, unsigned long long *ctr, unsigned *flags)
 {
     __shared__ __align__(16) unsigned char smem[BatchLds<T>::BYTES];
     __shared__ long long s_item;
@@ -536,6 +536,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) void k_batch(const Bat
         asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"(static_cast<int>(threadIdx.x)));
         int gi = 0;
         while (gi + 1 < ng && it >= B->g[gi + 1].item0) gi++;
+        gi = __builtin_amdgcn_readfirstlane(gi);  // uniform: the descriptor loads stay scalar
         const GroupDev &g = B->g[gi];
         const int64_t c0 = (it - g.item0) * g.tile;
         const int64_t c1 = c0 + g.tile < g.n_cells ? c0 + g.tile : g.n_cells;

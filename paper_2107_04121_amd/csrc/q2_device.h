@@ -234,6 +234,23 @@ __device__ __forceinline__ void out_store(const V &v, V *p)
     __builtin_nontemporal_store(v, p);
 }
 
+// The global-memory view of a generic pointer.  Pointers that reach a kernel
+// through a descriptor in memory (not as kernel arguments) are otherwise
+// accessed with flat instructions, which also count against the LDS wait
+// counter: every wait for an LDS read would then wait for the prefetch loads
+// and output stores in flight as well.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gmem(T *p)
+{
+    return (__attribute__((address_space(1))) T *)p;
+}
+
+template <typename V>
+__device__ __forceinline__ void out_store(const V &v, __attribute__((address_space(1))) V *p)
+{
+    __builtin_nontemporal_store(v, p);
+}
+
 // Everything one run of the Q2 cell routine reads and writes.
 struct Q2Job {
     int64_t n_cells, n_nodes;
@@ -274,19 +291,25 @@ __device__ __forceinline__ void q2_run(const Q2Job &A, int64_t e, int64_t e_end,
     if (e >= e_end) return;  // uniform over the workgroup
 
     if (tid < 9) {
-        B1[tid] = A.tab.B1[tid];
-        D1[tid] = A.tab.D1[tid];
+        B1[tid] = gmem(A.tab.B1)[tid];
+        D1[tid] = gmem(A.tab.D1)[tid];
     } else if (tid >= 32 && tid < 32 + NQ) {
-        wq[tid - 32] = A.tab.w[tid - 32];
+        wq[tid - 32] = gmem(A.tab.w)[tid - 32];
     }
-    const T *mat = static_cast<const T *>(A.mat);
+    const auto mat = gmem(static_cast<const T *>(A.mat));
+    const auto conn = gmem(A.conn);
+    const auto coords = gmem(A.coords);
     // this thread's node coordinate (threads < 81: node a = tid/3, axis tid%3)
     const int ga = tid / 3, gc = tid - 3 * (tid / 3);
     // the first cell's coordinates and coefficients go to the parking slots
     // the loop reads every cell's data from (see the park step below)
     if (tid < NB * 3) {
-        const int64_t n = checked_node(A.conn, e * NB + ga, A.n_nodes, A.flags);
-        xn[tid] = A.coords[3 * n + gc];
+        int64_t n = conn[e * NB + ga];
+        if (n < 0 || n >= A.n_nodes) {
+            raise_fault(A.flags, FAULT_INDEX);
+            n = 0;
+        }
+        xn[tid] = coords[3 * n + gc];
     }
     if (tid == 0) {
         lmn[0] = mat[2 * e];
@@ -355,7 +378,7 @@ __device__ __forceinline__ void q2_run(const Q2Job &A, int64_t e, int64_t e_end,
         int32_t nn = 0;
         T lamn = T(0), mun = T(0);
         if (has_next) {
-            if (tid < NB * 3) nn = A.conn[en * NB + ga];
+            if (tid < NB * 3) nn = conn[en * NB + ga];
             lamn = mat[2 * en];
             mun = mat[2 * en + 1];
         }
@@ -412,7 +435,7 @@ __device__ __forceinline__ void q2_run(const Q2Job &A, int64_t e, int64_t e_end,
             // wave w takes tile (w/2, w%2) of the 2x2 tiles over 27x27
             if (A.out_mass) {
                 ACC am = mass_tile<MM>(B1, wd, wave >> 1, wave & 1, lane);
-                T *om = static_cast<T *>(A.out_mass) + e * (NB * NB);
+                const auto om = gmem(static_cast<T *>(A.out_mass)) + e * (NB * NB);
                 const int b = (wave & 1) * 16 + (lane & 15);
 #pragma unroll
                 for (int v = 0; v < 4; v++) {
@@ -434,7 +457,7 @@ __device__ __forceinline__ void q2_run(const Q2Job &A, int64_t e, int64_t e_end,
                 raise_fault(A.flags, FAULT_INDEX);
                 n = 0;
             }
-            xnext = A.coords[3 * n + gc];
+            xnext = coords[3 * n + gc];
         }
 
         // 5. the blocks r <= s of P go straight to their places in the
@@ -490,7 +513,7 @@ __device__ __forceinline__ void q2_run(const Q2Job &A, int64_t e, int64_t e_end,
                 const T k0 = lm * d0 + tr, k1 = lm * d1 + tr, k2 = lm * d2 + tr;
                 if constexpr (MULTI) {
                     if (A.out_lap) {
-                        T *ol = static_cast<T *>(A.out_lap) + e * (NB * NB);
+                        const auto ol = gmem(static_cast<T *>(A.out_lap)) + e * (NB * NB);
                         const T lv = d0 + d1 + d2;
                         ol[a * NB + b] = lv;
                         ol[b * NB + a] = lv;
@@ -532,8 +555,8 @@ __device__ __forceinline__ void q2_run(const Q2Job &A, int64_t e, int64_t e_end,
         //    stores); the few entries before the first and after the last
         //    whole vector go one by one
         {
-            T *out = static_cast<T *>(A.out);
-            TV *aligned = reinterpret_cast<TV *>(out + (base - h));
+            const auto out = gmem(static_cast<T *>(A.out));
+            const auto aligned = (__attribute__((address_space(1))) TV *)(out + (base - h));
             const TV *k16 = reinterpret_cast<const TV *>(Ks);
             const int vf = h ? 1 : 0, vl = (NK + h) / L::VEC;  // whole vectors [vf, vl)
             constexpr int BATCH = 4;
