@@ -294,6 +294,7 @@ __device__ void small_pass(const GroupDev &g, int64_t e0, int n, int buf, int64_
             const int col = tid % ND, s = col / NB, b = col - s * NB;
             int row = (tid / ND) % ND, c = tid / (ND * ND);
             auto out = gmem(static_cast<T *>(g.out_el)) + e0 * (ND * ND) + tid;
+#pragma unroll 2
             for (int rr = tid / ND; rr < n * ND; rr += RPS) {
                 const int r = row / NB, a = row - r * NB;
                 const T *Pc = Ps + c * L::CR;
@@ -318,6 +319,7 @@ __device__ void small_pass(const GroupDev &g, int64_t e0, int n, int buf, int64_
         int a = (tid / NB) % NB, c = tid / (NB * NB);
         auto ol = gmem(lap ? static_cast<T *>(g.out_lap) + e0 * (NB * NB) + tid : nullptr);
         auto om = gmem(mass ? static_cast<T *>(g.out_mass) + e0 * (NB * NB) + tid : nullptr);
+#pragma unroll 2
         for (int rr = tid / NB; rr < n * NB; rr += RPB) {
             if (lap) {
                 const T *Pc = Ps + c * L::CR;
