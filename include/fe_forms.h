@@ -307,7 +307,8 @@ int fe_energy_grad(fe_plan plan, fe_incidence inc, int64_t n_cells, int64_t n_no
  *          FP64 Q1 hexahedra, 1 for Q2); the default is four passes;
  *   material: [n_cells][2] (lambda, mu) when ELASTICITY is requested;
  *   out_mass, out_laplace: [n_cells][n_basis][n_basis];
- *   out_elasticity: [n_cells][3 n_basis][3 n_basis] (16-byte aligned). */
+ *   out_elasticity: [n_cells][3 n_basis][3 n_basis] (16-byte aligned);
+ *   a group with n_cells == 0 takes no work item and its arrays may be NULL. */
 typedef struct {
     int cell, order;
     int forms;

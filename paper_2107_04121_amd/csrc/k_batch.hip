@@ -651,9 +651,11 @@ int batch_create(int n_groups, const fe_group *groups, int precision, int autotu
             return FE_ERR_UNSUPPORTED;
         }
         const int bad_forms = g.forms & ~((1 << FE_FORM_MASS) | (1 << FE_FORM_LAPLACE) | (1 << FE_FORM_ELASTICITY));
-        if (!g.forms || bad_forms || g.n_cells < 0 || g.n_nodes < 0 || (g.n_cells > 0 && (!g.coords || !g.conn)) ||
-            ((g.forms & (1 << FE_FORM_MASS)) && !g.out_mass) || ((g.forms & (1 << FE_FORM_LAPLACE)) && !g.out_laplace) ||
-            ((g.forms & (1 << FE_FORM_ELASTICITY)) && (!g.out_elasticity || !g.material)) || g.tile < 0) {
+        // an empty group needs no arrays at all
+        const bool missing = g.n_cells > 0 && (!g.coords || !g.conn || ((g.forms & (1 << FE_FORM_MASS)) && !g.out_mass) ||
+                                               ((g.forms & (1 << FE_FORM_LAPLACE)) && !g.out_laplace) ||
+                                               ((g.forms & (1 << FE_FORM_ELASTICITY)) && (!g.out_elasticity || !g.material)));
+        if (!g.forms || bad_forms || g.n_cells < 0 || g.n_nodes < 0 || missing || g.tile < 0) {
             set_error("bad group description");
             return FE_ERR_INVALID_ARG;
         }

@@ -152,3 +152,37 @@ def test_batch_p1_tet_faults():
     with pytest.raises(fe.FeError) as ei:
         b.check()
     assert ei.value.status == 4
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_empty_and_single_cell_groups(orc, prec):
+    """An empty group next to single-cell groups of every routine: the empty
+    group takes no work item, the others match the oracle."""
+    import torch
+    import paper_2107_04121_amd as fe
+    dt = {"fp64": torch.float64, "fp32": torch.float32}[prec]
+    specs = [("tet", 1, meshgen.tet_mesh((2, 2, 1), 1, alpha=0.1, seed=31), 0),
+             ("hex", 2, meshgen.hex_mesh((2, 1, 1), 2, alpha=0.1, seed=32), 1),
+             ("tet", 2, meshgen.tet_mesh((1, 1, 1), 2, alpha=0.1, seed=33), 1),
+             ("hex", 1, meshgen.hex_mesh((2, 2, 1), 1, alpha=0.1, seed=34), 3),
+             ("tet", 1, meshgen.tet_mesh((1, 1, 1), 1, alpha=0.1, seed=35), 1)]
+    groups, refs = [], []
+    for k, (cell, p, m, n) in enumerate(specs):
+        lm = meshgen.lame_cell(max(n, 1), seed=40 + k)[:n]
+        groups.append(dict(cell=cell, order=p, coords=_t(m.coords),
+                           conn=_t(m.conn[:n]), material=_t(lm, dt),
+                           forms=("mass", "laplace", "elasticity")))
+        refs.append((meshgen.Mesh(coords=m.coords, conn=m.conn[:n], cell=cell,
+                                  order=p, h=m.h), lm))
+    b = fe.Batch(groups, precision=prec, autotune=True)
+    print(f"[batch-edge] {prec} tiles={b.tiles}", flush=True)
+    o = b.run()
+    b.check()
+    for (m, lm), out in zip(refs, o):
+        for form in ("mass", "laplace", "elasticity"):
+            assert out[form].shape[0] == m.conn.shape[0]
+            if m.conn.shape[0] == 0:
+                continue
+            mat, kind = (lm, "iso_cell") if form == "elasticity" else (None, None)
+            err = _err(out[form].cpu().numpy(), orc.matrix(m, form, mat, kind))
+            assert err < TOL[prec], (m.cell, m.order, form, err)
