@@ -270,6 +270,178 @@ __device__ __forceinline__ void acc_scalar(const X &x, const ctab_t *w, const ct
     }
 }
 
+// Q1 hexahedron Laplace matrix through the tensor-product structure of the
+// trilinear basis, all in FP64.  With a = (a0, a1, a2) (a = a0 + 2 a1 + 4 a2),
+// the 1-D values l_q[a] = B1[q][a] and d[a] = D1[.][a] (the derivative of a
+// linear function, the same at both points),
+//   dphi_a/dxi_j (q) = d[a_j] l_{q_k}[a_k] l_{q_m}[a_m]       ({j,k,m} = {0,1,2}),
+// and with C(q) = (w_q / det J) adj J adj J^T (so that w det J G_a.G_b =
+// dphi_a^T C dphi_b)
+//   K_ab = sum_j d[a_j] d[b_j] T_j(a_k b_k, a_m b_m)
+//        + sum_{j<k} (d[a_j] d[b_k] V_jk(b_j, a_k, a_m b_m) + d[a_k] d[b_j] V_jk(a_j, b_k, a_m b_m)),
+//   T_j(kk, mm) = sum_{q_k, q_m} (sum_{q_j} C_jj(q)) L_kk(q_k) L_mm(q_m),
+//   V_jk(x, y, mm) = sum_q C_jk(q) l_{q_j}[x] l_{q_k}[y] L_mm(q_m),
+// where L_{ab}(q) = l_q[a] l_q[b].  The Jacobian column j depends only on the
+// other two point coordinates, so the three columns are formed once for their
+// four distinct values.  The same sums, reordered (about half the FP64
+// operations of the per-point pair loop).
+template <typename X>
+__device__ __forceinline__ void acc_laplace_q1(const X &x, const ctab_t *B1, const ctab_t *D1, const ctab_t *w,
+                                               bool valid, unsigned &fault, double (&acc)[36])
+{
+    double l[2][2], d[2];
+#pragma unroll
+    for (int q = 0; q < 2; q++)
+#pragma unroll
+        for (int a = 0; a < 2; a++) l[q][a] = B1[q * 2 + a];
+    d[0] = D1[0];
+    d[1] = D1[1];
+    // node a with its index on axis j set to u, on the other two axes to v, t
+    // (k < m the other axes)
+    auto node = [](int j, int u, int v, int t) {
+        const int k = j == 0 ? 1 : 0, m = j == 2 ? 1 : 2;
+        int c[3];
+        c[j] = u;
+        c[k] = v;
+        c[m] = t;
+        return c[0] + 2 * c[1] + 4 * c[2];
+    };
+    // Jacobian columns: Jc[j][qk][qm][i] = sum_a x_a,i dphi_a/dxi_j
+    double Jc[3][2][2][3];
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+        double E[2][2][3];  // E[ak][am][i] = sum_{aj} d[aj] x_{a,i}
+#pragma unroll
+        for (int ak = 0; ak < 2; ak++)
+#pragma unroll
+            for (int am = 0; am < 2; am++)
+#pragma unroll
+                for (int i = 0; i < 3; i++)
+                    E[ak][am][i] = fma(d[1], x(node(j, 1, ak, am), i), d[0] * x(node(j, 0, ak, am), i));
+#pragma unroll
+        for (int qk = 0; qk < 2; qk++) {
+            double F[2][3];  // F[am][i] = sum_ak l_qk[ak] E[ak][am][i]
+#pragma unroll
+            for (int am = 0; am < 2; am++)
+#pragma unroll
+                for (int i = 0; i < 3; i++) F[am][i] = fma(l[qk][1], E[1][am][i], l[qk][0] * E[0][am][i]);
+#pragma unroll
+            for (int qm = 0; qm < 2; qm++)
+#pragma unroll
+                for (int i = 0; i < 3; i++) Jc[j][qk][qm][i] = fma(l[qm][1], F[1][i], l[qm][0] * F[0][i]);
+        }
+    }
+    // per point: C(q); accumulate Cbar[j][qk][qm] = sum_{qj} C_jj and
+    // Y[p][x][y][qm] = sum_{qj, qk} C_jk l_{qj}[x] l_{qk}[y] for the pairs
+    // p = (0,1), (0,2), (1,2)
+    double Cbar[3][2][2], Y[3][2][2][2];
+#pragma unroll
+    for (int j = 0; j < 3; j++)
+#pragma unroll
+        for (int u = 0; u < 4; u++) Cbar[j][u >> 1][u & 1] = 0.0;
+#pragma unroll
+    for (int p = 0; p < 3; p++)
+#pragma unroll
+        for (int u = 0; u < 8; u++) Y[p][u >> 2][(u >> 1) & 1][u & 1] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+        const int qc[3] = {q & 1, (q >> 1) & 1, q >> 2};
+        double J[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            J[i][0] = Jc[0][qc[1]][qc[2]][i];
+            J[i][1] = Jc[1][qc[0]][qc[2]][i];
+            J[i][2] = Jc[2][qc[0]][qc[1]][i];
+        }
+        double adj[3][3];
+        adj[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+        adj[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+        adj[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+        adj[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+        adj[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+        adj[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+        adj[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+        adj[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+        adj[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        const double det = J[0][0] * adj[0][0] + J[0][1] * adj[1][0] + J[0][2] * adj[2][0];
+        if (valid && !(det > 0.0)) fault |= FAULT_DET;
+        const double sq = w[q] / det;
+        double C[3][3];
+#pragma unroll
+        for (int j = 0; j < 3; j++)
+#pragma unroll
+            for (int k = j; k < 3; k++)
+                C[j][k] = sq * (adj[j][0] * adj[k][0] + adj[j][1] * adj[k][1] + adj[j][2] * adj[k][2]);
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            const int k = j == 0 ? 1 : 0, m = j == 2 ? 1 : 2;
+            Cbar[j][qc[k]][qc[m]] += C[j][j];
+        }
+#pragma unroll
+        for (int p = 0; p < 3; p++) {
+            const int j = p == 2 ? 1 : 0, k = p == 0 ? 1 : 2, m = 3 - j - k;
+#pragma unroll
+            for (int xx = 0; xx < 2; xx++)
+#pragma unroll
+                for (int yy = 0; yy < 2; yy++)
+                    Y[p][xx][yy][qc[m]] = fma(C[j][k] * l[qc[j]][xx], l[qc[k]][yy], Y[p][xx][yy][qc[m]]);
+        }
+    }
+    // pair products L[al][q], al = (0,0), (0,1), (1,1)
+    double L[3][2];
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+        L[0][q] = l[q][0] * l[q][0];
+        L[1][q] = l[q][0] * l[q][1];
+        L[2][q] = l[q][1] * l[q][1];
+    }
+    double T3[3][3][3], V[3][2][2][3];
+#pragma unroll
+    for (int j = 0; j < 3; j++)
+#pragma unroll
+        for (int ak = 0; ak < 3; ak++) {
+            const double U0 = fma(L[ak][1], Cbar[j][1][0], L[ak][0] * Cbar[j][0][0]);
+            const double U1 = fma(L[ak][1], Cbar[j][1][1], L[ak][0] * Cbar[j][0][1]);
+#pragma unroll
+            for (int am = 0; am < 3; am++) T3[j][ak][am] = fma(L[am][1], U1, L[am][0] * U0);
+        }
+#pragma unroll
+    for (int p = 0; p < 3; p++)
+#pragma unroll
+        for (int xx = 0; xx < 2; xx++)
+#pragma unroll
+            for (int yy = 0; yy < 2; yy++)
+#pragma unroll
+                for (int am = 0; am < 3; am++)
+                    V[p][xx][yy][am] = fma(L[am][1], Y[p][xx][yy][1], L[am][0] * Y[p][xx][yy][0]);
+    // d[0] = -d[1] (the two linear functions have opposite slopes), so
+    // d[x] d[y] = dd for x == y and -dd otherwise: signs instead of products
+    const double dd = d[1] * d[1];
+#pragma unroll
+    for (int a = 0; a < 8; a++)
+#pragma unroll
+        for (int b = a; b < 8; b++) {
+            const int ac[3] = {a & 1, (a >> 1) & 1, a >> 2}, bc[3] = {b & 1, (b >> 1) & 1, b >> 2};
+            auto al = [](int u, int v) { return u + v; };  // (0,0) -> 0, (0,1)/(1,0) -> 1, (1,1) -> 2
+            double v = 0.0;
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+                const int k = j == 0 ? 1 : 0, m = j == 2 ? 1 : 2;
+                const double t = T3[j][al(ac[k], bc[k])][al(ac[m], bc[m])];
+                v = ac[j] == bc[j] ? v + t : v - t;
+            }
+#pragma unroll
+            for (int p = 0; p < 3; p++) {
+                const int j = p == 2 ? 1 : 0, k = p == 0 ? 1 : 2, m = 3 - j - k;
+                const int mm = al(ac[m], bc[m]);
+                const double t1 = V[p][bc[j]][ac[k]][mm], t2 = V[p][ac[j]][bc[k]][mm];
+                v = ac[j] == bc[k] ? v + t1 : v - t1;
+                v = ac[k] == bc[j] ? v + t2 : v - t2;
+            }
+            acc[tri(a, b, 8)] = dd * v;
+        }
+}
+
 // Accumulators of block (R,S), R <= S, of the isotropic elasticity matrix:
 // packed upper triangle for R == S, row-major NB x NB otherwise.
 template <int NB, int R, int S>

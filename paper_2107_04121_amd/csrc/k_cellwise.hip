@@ -53,7 +53,7 @@ struct CwScalar {
 };
 
 template <int CELL, int P, int FORM, typename T>
-__global__ __launch_bounds__(64, CELL == FE_CELL_HEX && sizeof(T) == 4 ? 4 : 1) void k_cw_scalar(ExecArgs A)
+__global__ __launch_bounds__(64, CELL == FE_CELL_HEX && sizeof(T) == 4 && FORM != FE_FORM_LAPLACE ? 4 : 1) void k_cw_scalar(ExecArgs A)
 {
     using C = CwScalar<CELL, P, FORM, T>;
     constexpr int NB = C::NB, NQ = C::NQ, NP = C::NP, ND = C::ND, RC = C::RC, SS = C::SS;
@@ -80,7 +80,15 @@ __global__ __launch_bounds__(64, CELL == FE_CELL_HEX && sizeof(T) == 4 ? 4 : 1) 
     }
 
     T acc[NP];
-    acc_scalar<CELL, P, FORM == FE_FORM_VMASS ? FE_FORM_MASS : FORM, T>(x, w, bf, bfgT, valid, fault, acc);
+    if constexpr (CELL == FE_CELL_HEX && P == 1 && FORM == FE_FORM_LAPLACE) {
+        // tensor-product sums in FP64, rounded once to the output type
+        double accd[NP];
+        acc_laplace_q1(x, ctab(A.tab.B1), ctab(A.tab.D1), w, valid, fault, accd);
+#pragma unroll
+        for (int p = 0; p < NP; p++) acc[p] = static_cast<T>(accd[p]);
+    } else {
+        acc_scalar<CELL, P, FORM == FE_FORM_VMASS ? FE_FORM_MASS : FORM, T>(x, w, bf, bfgT, valid, fault, acc);
+    }
 
     if (fault) raise_fault(A.flags, fault);
 
