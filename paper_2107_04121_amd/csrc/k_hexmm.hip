@@ -542,14 +542,21 @@ __global__ __launch_bounds__(THREADS, MM == MM_F64 ? 1 : 2) void k_hexmm(ExecArg
 #pragma unroll
                 for (int a0 = 0; a0 < N1; a0++) g[0][a0] = f * B1[q0 * N1 + a0];
             } else {
+                // g_c = d0 m_c + d1 m_3+c + d2 m_6+c with d = (dx by bz, bx dy bz,
+                // bx by dz), factored: dx (by bz m_c) + bx (dy bz m_3+c + by dz m_6+c)
                 const double dy = D1[q1 * N1 + a1], dz = D1[q2 * N1 + a2];
-                const double m[9] = {M[0], M[1], M[2], M[3], M[4], M[5], M[6], M[7], M[8]};
+                const double byz = by * bz, dyz = dy * bz, bdz = by * dz;
+                double f[3], h[3];
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    f[c] = byz * M[c];
+                    h[c] = fma(dyz, M[3 + c], bdz * M[6 + c]);
+                }
 #pragma unroll
                 for (int a0 = 0; a0 < N1; a0++) {
                     const double bx = B1[q0 * N1 + a0], dx = D1[q0 * N1 + a0];
-                    const double d0 = dx * by * bz, d1 = bx * dy * bz, d2 = bx * by * dz;
 #pragma unroll
-                    for (int c = 0; c < 3; c++) g[c][a0] = d0 * m[c] + d1 * m[3 + c] + d2 * m[6 + c];
+                    for (int c = 0; c < 3; c++) g[c][a0] = fma(dx, f[c], bx * h[c]);
                 }
             }
 #pragma unroll
@@ -1107,14 +1114,20 @@ __device__ __forceinline__ void mc_build(typename H::OPT *op, const double *Mq, 
 #pragma unroll
                 for (int a0 = 0; a0 < N1; a0++) put(0, a0, a12, ql, f * B1[q0 * N1 + a0]);
             } else {
+                // factored as in the one-pass build above
                 const double dy = D1[q1 * N1 + a1], dz = D1[q2 * N1 + a2];
-                const double m[9] = {M[0], M[1], M[2], M[3], M[4], M[5], M[6], M[7], M[8]};
+                const double byz = by * bz, dyz = dy * bz, bdz = by * dz;
+                double f[3], h[3];
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    f[c] = byz * M[c];
+                    h[c] = fma(dyz, M[3 + c], bdz * M[6 + c]);
+                }
 #pragma unroll
                 for (int a0 = 0; a0 < N1; a0++) {
                     const double bx = B1[q0 * N1 + a0], dx = D1[q0 * N1 + a0];
-                    const double d0 = dx * by * bz, d1 = bx * dy * bz, d2 = bx * by * dz;
 #pragma unroll
-                    for (int c = 0; c < 3; c++) put(c, a0, a12, ql, d0 * m[c] + d1 * m[3 + c] + d2 * m[6 + c]);
+                    for (int c = 0; c < 3; c++) put(c, a0, a12, ql, fma(dx, f[c], bx * h[c]));
                 }
             }
         } else {

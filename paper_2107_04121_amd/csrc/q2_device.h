@@ -413,15 +413,18 @@ __device__ __forceinline__ void q2_run(const Q2Job &A, int64_t e, int64_t e_end,
             }
             const double c0 = adjc[0] * rd, c1 = adjc[1] * rd, c2 = adjc[2] * rd;
             const double bz = B1[q2 * 3 + a2], dz = D1[q2 * 3 + a2];
+            // G = c0 dx by bz + c1 bx dy bz + c2 bx by dz, factored over the
+            // tensor indices: dx (c0 bz by) + bx (c1 bz dy + c2 dz by)
             T *dst = Gs + ci * 33 * L::KS + q;
+            const double c0z = c0 * bz, c1z = c1 * bz, c2z = c2 * dz;
 #pragma unroll
             for (int a1 = 0; a1 < 3; a1++) {
                 const double by = B1[q1 * 3 + a1], dy = D1[q1 * 3 + a1];
+                const double p0 = c0z * by, p12 = fma(c1z, dy, c2z * by);
 #pragma unroll
                 for (int a0 = 0; a0 < 3; a0++) {
                     const double bx = B1[q0 * 3 + a0], dx = D1[q0 * 3 + a0];
-                    const double v = c0 * (dx * by * bz) + c1 * (bx * dy * bz) + c2 * (bx * by * dz);
-                    dst[(a0 + 3 * (a1 + 3 * a2)) * L::KS] = static_cast<T>(v);
+                    dst[(a0 + 3 * (a1 + 3 * a2)) * L::KS] = static_cast<T>(fma(p0, dx, p12 * bx));
                 }
             }
         }
