@@ -123,6 +123,63 @@ __global__ __launch_bounds__(64, CELL == FE_CELL_HEX && sizeof(T) == 4 && FORM !
     }
 }
 
+// Vector mass I3 (x) M of 64 cells per workgroup of 256 threads.  Wave 0
+// evaluates the scalar mass matrix M (one lane per cell, upper triangle in
+// LDS); then all four waves write the 3nb x 3nb matrices in sweeps of whole
+// rows, a thread keeping its column: entry ((r,a),(s,b)) is M[a][b] when
+// r == s and zero otherwise.  Two thirds of the output are zeros, so the
+// kernel is a store stream; the sweeps make each one a contiguous run.
+template <int CELL, int P, typename T>
+__global__ __launch_bounds__(256) void k_cw_vmass(ExecArgs A)
+{
+    using S = Shape<CELL, P>;
+    constexpr int NB = S::NB, NP = NB * (NB + 1) / 2, ND = 3 * NB, MSTR = NP + 1, RPS = 256 / ND;
+    constexpr bool X_LDS = NB > 8;
+    __shared__ T Mst[64 * MSTR];
+    __shared__ double xs[X_LDS ? 64 * XLds<NB>::STRIDE : 1];
+    const int tid = threadIdx.x;
+    const int64_t e0 = logical_block(A.xcd_remap) * 64;
+    const int ncell = A.n_cells - e0 < 64 ? static_cast<int>(A.n_cells - e0) : 64;
+    unsigned fault = 0;
+    if constexpr (X_LDS) {
+        fault = gather_lds<NB>(A.conn, A.coords, e0, A.n_cells, A.n_nodes, xs, tid, 256);
+        __syncthreads();
+    }
+    if (tid < 64) {
+        const int64_t e = e0 + tid;
+        const bool valid = e < A.n_cells;
+        using XT = typename std::conditional<X_LDS, XLds<NB>, XReg<NB>>::type;
+        XT x;
+        if constexpr (X_LDS)
+            x.row = xs + tid * XLds<NB>::STRIDE;
+        else
+            fault |= gather<NB>(A.conn, A.coords, e, A.n_nodes, valid, x);
+        T acc[NP];
+        acc_scalar<CELL, P, FE_FORM_MASS, T>(x, ctab(A.tab.w), ctab(A.tab.bf), ctab(A.tab.bfgT), valid, fault, acc);
+#pragma unroll
+        for (int p = 0; p < NP; p++) Mst[tid * MSTR + p] = acc[p];
+    }
+    if (fault) raise_fault(A.flags, fault);
+    __syncthreads();
+    if (tid < RPS * ND) {
+        const int col = tid % ND, s = col / NB, b = col - s * NB;
+        int row = (tid / ND) % ND, c = tid / (ND * ND);
+        T *out = static_cast<T *>(A.out) + e0 * (ND * ND) + tid;
+        for (int rr = tid / ND; rr < ncell * ND; rr += RPS) {
+            const int r = row / NB, a = row - r * NB;
+            const T v = r == s ? Mst[c * MSTR + (a <= b ? tri(a, b, NB) : tri(b, a, NB))] : T(0);
+            st_nt(out, v);
+            out += RPS * ND;
+            row += RPS % ND;
+            c += RPS / ND;
+            if (row >= ND) {
+                row -= ND;
+                c++;
+            }
+        }
+    }
+}
+
 template <int CELL, int P, typename T>
 struct CwElast {
     using S = Shape<CELL, P>;
@@ -218,6 +275,12 @@ int launch_scalar(const Plan &, const ExecArgs &A, hipStream_t st)
 }
 
 template <int CELL, int P, typename T>
+int launch_vmass(const Plan &, const ExecArgs &A, hipStream_t st)
+{
+    return launch_cw(k_cw_vmass<CELL, P, T>, 256, A, st);
+}
+
+template <int CELL, int P, typename T>
 int launch_elast(const Plan &, const ExecArgs &A, hipStream_t st)
 {
     return launch_cw(k_cw_elast<CELL, P, T>, ELAST_THREADS, A, st);
@@ -228,7 +291,7 @@ LaunchFn pick(const Plan &p)
 {
     switch (p.form) {
     case FE_FORM_MASS: return launch_scalar<CELL, P, FE_FORM_MASS, T>;
-    case FE_FORM_VMASS: return launch_scalar<CELL, P, FE_FORM_VMASS, T>;
+    case FE_FORM_VMASS: return launch_vmass<CELL, P, T>;
     case FE_FORM_LAPLACE: return launch_scalar<CELL, P, FE_FORM_LAPLACE, T>;
     case FE_FORM_ELASTICITY:
         if (p.mat_kind == FE_MAT_ISO_CELL || p.mat_kind == FE_MAT_ISO_QP) return launch_elast<CELL, P, T>;
