@@ -65,7 +65,7 @@ MEASURED_TRAFFIC = {
                            sources=["k_hexmm.hip", "mm_device.h",
                                     "q2_device.h", "fe_device.h"]),
     "k_cw_scalar<hex,1,laplace,double>@128^3": dict(
-        bytes=1195573734, sha256="fc9c08e422a68796",
+        bytes=1195572737, sha256="ea6c4a1e084eaae9",
         sources=["k_cellwise.hip", "cw_device.h", "fe_device.h"]),
 }
 
