@@ -240,7 +240,8 @@ int fe_assemble(fe_incidence inc, int n_comp, int precision, const void *cell_ve
  * numbers, built on the current device from the cells' (n, m) node pairs by
  * a radix sort.
  *   conn [n_cells][n_basis] int32, device, entries in [0, n_nodes)
- *   (FE_ERR_INDEX_OUT_OF_RANGE otherwise); n_cells * n_basis^2 pairs and the
+ *   (FE_ERR_INDEX_OUT_OF_RANGE otherwise), no node listed twice by one cell
+ *   (FE_ERR_INVALID_ARG otherwise); n_cells * n_basis^2 pairs and the
  *   number of distinct pairs must stay below 2^31 (FE_ERR_INVALID_ARG).
  * Synchronises `stream`; the handle owns its device arrays. */
 typedef struct fe_pattern_s *fe_pattern;
@@ -308,7 +309,8 @@ int fe_energy_grad(fe_plan plan, fe_incidence inc, int64_t n_cells, int64_t n_no
  *   material: [n_cells][2] (lambda, mu) when ELASTICITY is requested;
  *   out_mass, out_laplace: [n_cells][n_basis][n_basis];
  *   out_elasticity: [n_cells][3 n_basis][3 n_basis] (16-byte aligned);
- *   a group with n_cells == 0 takes no work item and its arrays may be NULL. */
+ *   a group with n_cells == 0 takes no work item and its arrays may be NULL;
+ *   a group with cells needs n_nodes > 0 (FE_ERR_INVALID_ARG otherwise). */
 typedef struct {
     int cell, order;
     int forms;

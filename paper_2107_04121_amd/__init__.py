@@ -53,6 +53,48 @@ def reference_tables(cell: str, order: int):
     return w, pts, bf, bfg
 
 
+def material_entries(kind, n_qp: int) -> int:
+    """Material entries per cell of a material kind (the layouts of
+    fe_material_kind): iso_cell 2, iso_qp 2 n_qp, voigt_qp 36 n_qp,
+    tensor_qp 9 n_qp, none 0."""
+    return {"iso_cell": 2, "iso_qp": 2 * n_qp, "voigt_qp": 36 * n_qp,
+            "tensor_qp": 9 * n_qp}.get(kind, 0)
+
+
+def validate_inputs(n_basis, n_qp, n_comp_, material_kind, dtype, coords,
+                    conn, material=None, dofs=None):
+    """Host-side checks of the arrays passed to a plan (shapes, dtypes,
+    entry counts per material kind, then device and contiguity); raises
+    ValueError before anything reaches the library."""
+    import torch
+    if conn.dim() != 2 or conn.shape[1] != n_basis:
+        raise ValueError(f"conn must have {n_basis} columns")
+    n_cells = conn.shape[0]
+    if coords.dtype != torch.float64 or coords.dim() != 2 or \
+            coords.shape[1] != 3:
+        raise ValueError("coords must be (n_nodes, 3) float64")
+    if conn.dtype != torch.int32:
+        raise ValueError("conn must be int32")
+    if material is not None and material.dtype != dtype:
+        raise ValueError(f"material must be {dtype}")
+    if dofs is not None and dofs.dtype != dtype:
+        raise ValueError(f"dofs must be {dtype}")
+    per_cell = material_entries(material_kind, n_qp)
+    if per_cell and material is not None and \
+            material.numel() != n_cells * per_cell:
+        raise ValueError(f"material has {material.numel()} entries, a "
+                         f"{material_kind} material of {n_cells} cells "
+                         f"needs {n_cells * per_cell}")
+    if dofs is not None and dofs.numel() != coords.shape[0] * n_comp_:
+        raise ValueError(f"dofs has {dofs.numel()} entries, "
+                         f"{coords.shape[0]} nodes x {n_comp_} components "
+                         "expected")
+    for name, t in (("coords", coords), ("conn", conn),
+                    ("material", material), ("dofs", dofs)):
+        if t is not None and (not t.is_cuda or not t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous cuda tensor")
+
+
 def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
@@ -137,24 +179,10 @@ class Plan:
     def __call__(self, coords, conn, material=None, dofs=None, out=None,
                  workspace=None, stream=None):
         import torch
-        n_cells, nb = conn.shape
-        if nb != self.n_basis:
-            raise ValueError(f"conn has {nb} columns, plan needs "
-                             f"{self.n_basis}")
-        if coords.dtype != torch.float64 or coords.dim() != 2 or \
-                coords.shape[1] != 3:
-            raise ValueError("coords must be (n_nodes, 3) float64")
-        if conn.dtype != torch.int32:
-            raise ValueError("conn must be int32")
-        for name, t in (("coords", coords), ("conn", conn),
-                        ("material", material), ("dofs", dofs)):
-            if t is not None and (not t.is_cuda or not t.is_contiguous()):
-                raise ValueError(f"{name} must be a contiguous cuda tensor")
+        validate_inputs(self.n_basis, self.n_qp, self.n_comp, self.material,
+                        self.dtype, coords, conn, material, dofs)
+        n_cells = conn.shape[0]
         dt = self.dtype
-        if material is not None and material.dtype != dt:
-            raise ValueError(f"material must be {dt}")
-        if dofs is not None and dofs.dtype != dt:
-            raise ValueError(f"dofs must be {dt}")
         if out is None:
             out = torch.empty(self.out_shape(n_cells), dtype=dt,
                               device=coords.device)
@@ -393,8 +421,21 @@ class Batch:
             cell, order = g["cell"], int(g["order"])
             nb, _ = reference_sizes(cell, order)
             X, C = g["coords"], g["conn"]
+            if X.dtype != torch.float64 or X.dim() != 2 or X.shape[1] != 3:
+                raise ValueError(f"group {i}: coords must be (n_nodes, 3) "
+                                 "float64")
+            if C.dtype != torch.int32 or C.dim() != 2 or C.shape[1] != nb:
+                raise ValueError(f"group {i}: conn must be (n_cells, {nb}) "
+                                 "int32")
             n = C.shape[0]
             forms = set(g["forms"])
+            unknown = forms - {"mass", "laplace", "elasticity"}
+            if unknown:
+                raise ValueError(f"group {i}: unknown forms {sorted(unknown)}")
+            for name, t in (("coords", X), ("conn", C)):
+                if not t.is_cuda or not t.is_contiguous():
+                    raise ValueError(f"group {i}: {name} must be a "
+                                     "contiguous cuda tensor")
             outs = {}
             mask = 0
             for f in forms:
@@ -404,6 +445,11 @@ class Batch:
             mat = g.get("material")
             if mat is not None and mat.dtype != dt:
                 raise ValueError(f"material must be {dt}")
+            if "elasticity" in forms:
+                if mat is None or mat.numel() != 2 * n or not mat.is_cuda \
+                        or not mat.is_contiguous():
+                    raise ValueError(f"group {i}: elasticity needs a "
+                                     f"contiguous cuda (n_cells, 2) material")
             arr[i] = _lib.fe_group(
                 _lib.CELLS[cell], order, mask, int(g.get("tile", 0)), n,
                 X.shape[0], X.data_ptr(), C.data_ptr(),

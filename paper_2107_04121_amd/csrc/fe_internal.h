@@ -38,7 +38,8 @@ struct DevTables {
 };
 
 // Fault bits written by kernels into the first word of the workspace.
-enum : unsigned { FAULT_DET = 1u, FAULT_INDEX = 2u };
+// FAULT_REPEAT: a cell lists one node twice (refused by the pattern build).
+enum : unsigned { FAULT_DET = 1u, FAULT_INDEX = 2u, FAULT_REPEAT = 4u };
 
 // Everything a launcher needs for one fe_execute call.
 struct ExecArgs {
@@ -129,6 +130,20 @@ LaunchFn select_hexgm(const Plan &p);
 int adjoint_sumfact(const Plan &p, const ExecArgs &A, double scale, void *gmat, void *part, hipStream_t st);
 
 int n_comp_of(int form);
+
+// Material entries per cell of each material kind (the layouts of
+// fe_material_kind): ISO_CELL 2, ISO_QP 2 n_qp, VOIGT_QP 36 n_qp,
+// TENSOR_QP 9 n_qp, NONE 0.
+inline int64_t material_entries_per_cell(int mat_kind, int nq)
+{
+    switch (mat_kind) {
+    case FE_MAT_ISO_CELL: return 2;
+    case FE_MAT_ISO_QP: return 2 * (int64_t)nq;
+    case FE_MAT_VOIGT_QP: return 36 * (int64_t)nq;
+    case FE_MAT_TENSOR_QP: return 9 * (int64_t)nq;
+    default: return 0;
+    }
+}
 size_t matrix_first_bytes(const Plan &p, int64_t n_cells);
 int launch_matrix_first(const Plan &p, const ExecArgs &A, hipStream_t st);
 

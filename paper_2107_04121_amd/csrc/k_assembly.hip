@@ -11,7 +11,8 @@
 // local numbers (e, a), sorted); at each step lane b adds the n_comp x n_comp
 // block K_e[(., a), (., b)] into the row's LDS accumulator at the slot of
 // conn[e][b] (binary search in the row's columns, staged in LDS).  Within a
-// step the lanes hit distinct slots, the steps run in incidence order, and
+// step the lanes hit distinct slots (the pattern build refuses a cell that
+// lists one node twice), the steps run in incidence order, and
 // lanes b read consecutive entries of the element matrix rows; the row is
 // written once at the end.  No atomics: bitwise repeatable.
 #include <hipcub/hipcub.hpp>
@@ -40,6 +41,10 @@ __global__ void k_pair_keys(const int32_t *conn, int64_t n_cells, int nb, int64_
     if (n < 0 || n >= n_nodes || m < 0 || m >= n_nodes) {
         raise_fault(flags, FAULT_INDEX);
         n = m = 0;
+    } else if (a != b && n == m) {
+        // a cell listing one node twice would make two lanes of one
+        // assembly step add into the same slot
+        raise_fault(flags, FAULT_REPEAT);
     }
     keys[i] = static_cast<uint64_t>(n) * static_cast<uint64_t>(n_nodes) + static_cast<uint64_t>(m);
 }
@@ -216,6 +221,12 @@ int fe_pattern_create(int64_t n_cells, int64_t n_nodes, int n_basis, const int32
         fe_pattern_destroy(p);
         set_error("a connectivity entry is out of range");
         return FE_ERR_INDEX_OUT_OF_RANGE;
+    }
+    if (h_flags & FAULT_REPEAT) {
+        cleanup();
+        fe_pattern_destroy(p);
+        set_error("a cell lists the same node twice");
+        return FE_ERR_INVALID_ARG;
     }
     p->nnz = h_nsel;
     if (hipMalloc(&p->cols, (p->nnz > 0 ? p->nnz : 1) * sizeof(int32_t)) != hipSuccess) {

@@ -655,7 +655,8 @@ int batch_create(int n_groups, const fe_group *groups, int precision, int autotu
         const bool missing = g.n_cells > 0 && (!g.coords || !g.conn || ((g.forms & (1 << FE_FORM_MASS)) && !g.out_mass) ||
                                                ((g.forms & (1 << FE_FORM_LAPLACE)) && !g.out_laplace) ||
                                                ((g.forms & (1 << FE_FORM_ELASTICITY)) && (!g.out_elasticity || !g.material)));
-        if (!g.forms || bad_forms || g.n_cells < 0 || g.n_nodes < 0 || missing || g.tile < 0) {
+        if (!g.forms || bad_forms || g.n_cells < 0 || g.n_nodes < 0 || (g.n_cells > 0 && g.n_nodes == 0) || missing ||
+            g.tile < 0) {
             set_error("bad group description");
             return FE_ERR_INVALID_ARG;
         }

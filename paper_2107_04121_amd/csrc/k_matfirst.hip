@@ -45,10 +45,7 @@ int launch_matrix_first(const Plan &p, const ExecArgs &A, hipStream_t st)
     const size_t esz = p.prec == FE_PREC_FP64 ? 8 : 4;
     const int nd = p.nc * p.nb;
     void *Kbuf = reinterpret_cast<char *>(A.flags) + 256;
-    int64_t mat_stride = 0;  // material entries per cell
-    if (p.mat_kind == FE_MAT_ISO_CELL) mat_stride = 2;
-    if (p.mat_kind == FE_MAT_ISO_QP) mat_stride = 2 * p.nq;
-    if (p.mat_kind == FE_MAT_VOIGT_QP) mat_stride = 36 * p.nq;
+    const int64_t mat_stride = material_entries_per_cell(p.mat_kind, p.nq);
     for (int64_t c0 = 0; c0 < A.n_cells; c0 += chunk) {
         const int64_t nc = A.n_cells - c0 < chunk ? A.n_cells - c0 : chunk;
         ExecArgs B = A;

@@ -54,7 +54,8 @@ def test_reference_sizes(L):
 
 
 @pytest.mark.parametrize("cell,p", [("hex", 1), ("hex", 2), ("hex", 3),
-                                    ("hex", 4), ("tet", 1), ("tet", 2)])
+                                    ("hex", 4), ("hex", 5), ("tet", 1),
+                                    ("tet", 2)])
 def test_library_tables_match_oracle(orc, cell, p):
     import paper_2107_04121_amd as fe
     lib_t = fe.reference_tables(cell, p)

@@ -160,3 +160,24 @@ def test_forms_f2_residual_sumfact_vs_generic(orc, p, form, prec):
     e = ev(X, C, material=None if M is None else _t(M, ev.dtype), dofs=_t(U, ev.dtype)).cpu().numpy()
     ref_e = orc.energy(mesh, form, U, M, kind)
     assert float(np.abs(e - ref_e).max() / np.abs(ref_e).max()) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("cell,p,curved", [("hex", 2, True), ("hex", 1, False), ("tet", 2, False)])
+def test_wdot_matrix_first_chunked(orc, cell, p, curved, prec):
+    """Matrix-first weighted-dot residual in chunks of 7 cells: every chunk
+    must read its own per-point 3 x 3 matrices (9 n_qp entries per cell)."""
+    import paper_2107_04121_amd as fe
+    mesh = _mesh(cell, p, curved)
+    nb, nq = orc.sizes(cell, p)
+    M = meshgen.tensor_qp(mesh.n_cells, nq, seed=43)
+    U = meshgen.dofs(mesh.n_nodes, 3, seed=44)
+    X, C = _t(mesh.coords), _t(mesh.conn)
+    ref = orc.residual(mesh, "wdot", U, M, "tensor_qp")
+    plan = fe.Plan(cell, p, "wdot", "residual", prec, material="tensor_qp", variant="matrix_first", chunk=7)
+    print(f"[f2 matrix-first] {cell}{p} wdot {prec} cells={mesh.n_cells} chunk=7", flush=True)
+    assert mesh.n_cells > 3 * 7
+    dt = plan.dtype
+    out = plan(X, C, material=_t(M, dt), dofs=_t(U, dt), workspace=plan.workspace(mesh.n_cells, X.device))
+    plan.check()
+    assert _err(out.cpu().numpy(), ref) < TOL[prec]

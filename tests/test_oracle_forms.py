@@ -64,7 +64,7 @@ def test_q1_unit_cube_closed_form(orc):
                 assert abs(M[a, b] - mas[k] * h ** 3) < 1e-16
 
 
-@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
 def test_box_tensor_product(orc, p):
     h = (0.7, 1.3, 0.4)
     m = meshgen.hex_mesh(1, p, box=h)
@@ -87,7 +87,8 @@ def _rand_affine(seed):
 
 
 @pytest.mark.parametrize("cell,p", [("hex", 1), ("hex", 2), ("hex", 3),
-                                    ("tet", 1), ("tet", 2)])
+                                    ("hex", 4), ("hex", 5), ("tet", 1),
+                                    ("tet", 2)])
 def test_affine_element(orc, cell, p):
     """x = A xi + b: matrices follow from the exact reference integrals."""
     A, b = _rand_affine(7 + p)

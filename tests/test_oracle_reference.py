@@ -40,7 +40,7 @@ def test_gauss_legendre_textbook_values(orc):
     np.testing.assert_allclose(w, np.array([5, 8, 5]) / 18.0, atol=1e-15)
 
 
-@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
 def test_hex_rule_exactness(orc, p):
     w, pts, _, _ = orc.tables("hex", p)
     n = p + 1
@@ -94,7 +94,8 @@ def _tet_nodes(p):
 
 
 @pytest.mark.parametrize("cell,p", [("hex", 1), ("hex", 2), ("hex", 3),
-                                    ("hex", 4), ("tet", 1), ("tet", 2)])
+                                    ("hex", 4), ("hex", 5), ("tet", 1),
+                                    ("tet", 2)])
 def test_basis_reproduces_polynomial_space(orc, cell, p):
     w, pts, bf, bfg = orc.tables(cell, p)
     nodes = _hex_nodes(p) if cell == "hex" else _tet_nodes(p)
