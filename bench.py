@@ -1,6 +1,6 @@
 """Throughput benchmark of the per-element weak-form evaluation on one GPU.
 
-Default workload (--config c2): linear-elasticity element matrices, Q2
+Headline workload (c2): linear-elasticity element matrices, Q2
 hexahedra (27 nodes, 81 DOFs), 3x3x3 Gauss, 48^3 = 110,592 cells on the unit
 cube with vertices perturbed by +-0.15h (seed 0), per-cell Lame lambda, mu ~
 lognormal(0, 0.5).  Output 110592 x 81 x 81.  One step = one full
@@ -32,7 +32,10 @@ Other configurations of the same hot path (--config):
       elasticity) as element matrices (on the matrix cores, reported against
       their peak) and sum-factorized residuals; primary Q5 elasticity
       matrices.
-Every configuration prints one JSON line.
+With no --config (the default, "all") bench.py prints ONE JSON line: the
+c2 headline record, with the complete records of c1, c3, c4 and c5 (value,
+roofline, cpu_baseline, errors against the oracle) under its "configs" key.
+With --config it prints that configuration's line alone.
 """
 from __future__ import annotations
 
@@ -70,17 +73,23 @@ MEASURED_TRAFFIC = {
 }
 
 
-def traffic(kernel):
+def source_hash(files):
+    """First 16 hex digits of the sha256 of the named csrc files, in order
+    (the stamp carried by every measured figure and profile summary)."""
     import hashlib
-    m = MEASURED_TRAFFIC.get(kernel)
-    if m is None:
-        return None
     h = hashlib.sha256()
-    for f in m["sources"]:
+    for f in files:
         with open(os.path.join(ROOT, "paper_2107_04121_amd", "csrc", f),
                   "rb") as fh:
             h.update(fh.read())
-    return m["bytes"] if h.hexdigest()[:16] == m["sha256"] else None
+    return h.hexdigest()[:16]
+
+
+def traffic(kernel):
+    m = MEASURED_TRAFFIC.get(kernel)
+    if m is None:
+        return None
+    return m["bytes"] if source_hash(m["sources"]) == m["sha256"] else None
 
 
 METRIC = ("element matrices/s (GElem/s) + HBM GB/s; FP64 vs mixed precision "
@@ -92,8 +101,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c2",
-                    choices=["c1", "c2", "c3", "c4", "c5", "c6", "c7", "c8"])
+    ap.add_argument("--config", default="all",
+                    choices=["all", "c1", "c2", "c3", "c4", "c5", "c6", "c7",
+                             "c8"],
+                    help="all (default): the c2 line, with c1, c3, c4 and c5 "
+                    "under its 'configs' key")
     ap.add_argument("--n", type=int, default=0, help="cells per axis")
     ap.add_argument("--precision", default="fp64",
                     choices=["fp64", "fp32", "bf16x3"])
@@ -102,7 +114,9 @@ def parse():
                     help="skip the other precisions/variants")
     ap.add_argument("--no-cpu", action="store_true",
                     help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=6.0,
+                    help="seconds of each oracle timing (all threads, then "
+                    "one thread)")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="GiB copied by one torch copy before the run (a "
                     "plain copy kernel of known size, used to scale HBM "
@@ -178,6 +192,40 @@ def oracle_rate(orc_call, n_cells, budget_s):
         total += orc_call(k2)
         reps += 1
     return k2 * reps / total, k2, reps, total
+
+
+def host_cpu():
+    """Model name and usable cores of the host the oracle runs on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": len(os.sched_getaffinity(0)),
+            "cpu_count": os.cpu_count()}
+
+
+def cpu_baseline(orc, call, n_cells, budget_s, what):
+    """The oracle, as it stands, timed on the host: all OpenMP threads (the
+    reported value) and one thread (the paper's single-thread mode), each
+    for about budget_s on a prefix of the workload; cells/s in GElem/s.
+    `what(k, reps, seconds)` describes the sample."""
+    threads = orc.num_threads()
+    rate, k, reps, tot = oracle_rate(call, n_cells, budget_s)
+    orc.set_num_threads(1)
+    try:
+        rate1, k1, reps1, tot1 = oracle_rate(call, n_cells, budget_s)
+    finally:
+        orc.set_num_threads(threads)
+    return {"value": rate / 1e9, "unit": "GElem/s", "cores": threads,
+            "kind": "oracle", "sample": what(k, reps, tot),
+            "single_thread": {"value": rate1 / 1e9, "unit": "GElem/s",
+                              "cores": 1, "sample": what(k1, reps1, tot1)},
+            "host": host_cpu()}
 
 
 def copy_calibration(gib):
@@ -282,13 +330,10 @@ def run_c2(args, orc):
             orc.matrix(submesh(mesh, slice(0, k)), "elasticity", lm[:k],
                        "iso_cell")
             return time.perf_counter() - t
-        rate, k2, reps, tot = oracle_rate(call, mesh.n_cells,
-                                          args.cpu_seconds)
-        line["cpu_baseline"] = {
-            "value": rate / 1e9, "unit": "GElem/s",
-            "cores": orc.num_threads(), "kind": "oracle",
-            "sample": f"first {k2} cells of the 48^3 Q2 mesh x {reps} "
-                      f"passes, FP64 element matrices, {tot:.1f} s"}
+        line["cpu_baseline"] = cpu_baseline(
+            orc, call, mesh.n_cells, args.cpu_seconds,
+            lambda k2, reps, tot: f"first {k2} cells of the 48^3 Q2 mesh x "
+            f"{reps} passes, FP64 element matrices, {tot:.1f} s")
     return line
 
 
@@ -386,19 +431,28 @@ def run_c1(args, orc):
     line["residual"] = dict(kernel_ms=mean(per_r), variant=pr.variant,
                             gelem_s=mesh.n_cells / (mean(per_r) * 1e-3)
                             / 1e9, max_rel_err=err_r)
+    kname = ("k_cw_scalar<hex,1,laplace,double>" if pm.variant == "cellwise"
+             else "k_matrix<hex,1,laplace>")
+    # the roofline of the workload itself: at 16^3 the 2.3 MB of the matrix
+    # launch fit in the L2/MALL and the launch is latency-bound
+    line["roofline"] = {"bound": "hbm", "achieved": line["matrix"]["hbm_gbs"],
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": line["matrix"]["hbm_gbs"] / HBM_PEAK_GBS,
+                        "traffic": None, "kernel": f"{kname} at {n}^3",
+                        "kernel_ms": kms,
+                        "note": f"{n}^3 cells move {bpc * mesh.n_cells / 1e6:.1f}"
+                        " MB per launch: launch-latency bound, not an HBM "
+                        "measurement; see roofline_128cube"}
     big = sweep.get("128^3")
     if big:
-        line["roofline"] = {"bound": "hbm", "achieved": big["hbm_gbs"],
-                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                            "frac": big["hbm_gbs"] / HBM_PEAK_GBS,
-                            "traffic": (traffic(
-                                "k_cw_scalar<hex,1,laplace,double>@128^3")
-                                if pm.variant == "cellwise" else None),
-                            "kernel": ("k_cw_scalar<hex,1,laplace,double>"
-                                       if pm.variant == "cellwise" else
-                                       "k_matrix<hex,1,laplace>")
-                            + " at 128^3",
-                            "kernel_ms": big["kernel_ms"]}
+        line["roofline_128cube"] = {
+            "bound": "hbm", "achieved": big["hbm_gbs"], "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": big["hbm_gbs"] / HBM_PEAK_GBS,
+            "traffic": (traffic("k_cw_scalar<hex,1,laplace,double>@128^3")
+                        if pm.variant == "cellwise" else None),
+            "kernel": f"{kname} at 128^3 (2,097,152 cells, the same kernel "
+                      "and launch configuration as the workload)",
+            "kernel_ms": big["kernel_ms"]}
     line["sweep"] = sweep
     if not args.no_cpu:
         def call(k):
@@ -407,13 +461,10 @@ def run_c1(args, orc):
             orc.matrix(sub, "laplace")
             orc.residual(sub, "laplace", U)
             return time.perf_counter() - t
-        rate, k2, reps, tot = oracle_rate(call, mesh.n_cells,
-                                          args.cpu_seconds)
-        line["cpu_baseline"] = {
-            "value": rate / 1e9, "unit": "GElem/s",
-            "cores": orc.num_threads(), "kind": "oracle",
-            "sample": f"{k2} cells x {reps} passes of matrix + residual, "
-                      f"{tot:.1f} s"}
+        line["cpu_baseline"] = cpu_baseline(
+            orc, call, mesh.n_cells, args.cpu_seconds,
+            lambda k2, reps, tot: f"{k2} cells x {reps} passes of matrix + "
+            f"residual, {tot:.1f} s")
     return line
 
 
@@ -506,13 +557,10 @@ def run_c3(args, orc):
             orc.residual(submesh(mesh, slice(0, k)), "elasticity", U3,
                          lm[:k], "iso_cell")
             return time.perf_counter() - t
-        rate, k2, reps, tot = oracle_rate(call, mesh.n_cells,
-                                          args.cpu_seconds)
-        line["cpu_baseline"] = {
-            "value": rate / 1e9, "unit": "GElem/s",
-            "cores": orc.num_threads(), "kind": "oracle",
-            "sample": f"{k2} Q3 cells x {reps} passes, elasticity residual "
-                      f"FP64, {tot:.1f} s"}
+        line["cpu_baseline"] = cpu_baseline(
+            orc, call, mesh.n_cells, args.cpu_seconds,
+            lambda k2, reps, tot: f"{k2} Q3 cells x {reps} passes, "
+            f"elasticity residual FP64, {tot:.1f} s")
     return line
 
 
@@ -607,6 +655,22 @@ def run_c4(args, orc):
                         "traffic": None, "kernel": "k_batch<float>",
                         "kernel_ms": kms}
     line.update(extra)
+    if not args.no_cpu:
+        def call(k):
+            # the same fraction k / n_cells of every group, all three forms
+            t = time.perf_counter()
+            for m, lm in meshes:
+                kg = max(1, int(round(m.n_cells * k / n_cells)))
+                sub = submesh(m, slice(0, kg))
+                orc.matrix(sub, "mass")
+                orc.matrix(sub, "laplace")
+                orc.matrix(sub, "elasticity", lm[:kg], "iso_cell")
+            return time.perf_counter() - t
+        line["cpu_baseline"] = cpu_baseline(
+            orc, call, n_cells, args.cpu_seconds,
+            lambda k2, reps, tot: f"the first {k2 / n_cells:.2%} of every "
+            f"group ({k2} cells) x {reps} passes, mass + Laplace + elasticity"
+            f" matrices FP64, {tot:.1f} s")
     return line
 
 
@@ -646,12 +710,30 @@ def run_c5(args, orc):
         def rel(a, b):
             return float(np.abs(a - b).max() / np.abs(b).max())
 
+        # the adjoint launch chain alone (pencil adjoint kernel + CSR node
+        # sums), buffers preallocated, timed with events on its stream
+        from paper_2107_04121_amd import _energy_grad, energy_grad_workspace
+        ws = energy_grad_workspace(ep.eval, mesh.n_cells, dev)
+        gmb, gxb = torch.empty_like(ct), torch.empty_like(xt)
+        cd, ud = ct.detach(), ut.detach()
+        _, per_adj = time_calls(
+            lambda: _energy_grad(ep.eval, ep.inc, xt.detach(), C, cd, ud, 1.0,
+                                 ws=ws, gm=gmb, gx=gxb, check=False),
+            args.steps, args.warmup)
+        ep.eval.check(ws)
+        esz = cd.element_size()
+        # algorithmic bytes: coords, conn, c, u read once; dJ/dc, dJ/dx
+        # written once
+        adj_bytes = (mesh.n_nodes * 24 * 2 + mesh.n_cells * 27 * 4
+                     + cd.numel() * esz * 2 + ud.numel() * esz)
         out[prec] = dict(ms_per_step=wall * 1e3 / args.steps,
                          event_ms=mean(per),
+                         adjoint_kernel_ms=mean(per_adj),
+                         adjoint_alg_bytes=adj_bytes,
                          err_J=abs(float(J) - J_ref) / abs(J_ref),
                          err_dJdc=rel(ct.grad.cpu().numpy(), gm_ref),
                          err_dJdx=rel(xt.grad.cpu().numpy(), gx_ref))
-        del ep
+        del ep, ws, gmb, gxb
         torch.cuda.empty_cache()
     p = out["fp64"]
     line = base_line(args, mesh.n_cells / (p["ms_per_step"] * 1e-3) / 1e9,
@@ -661,6 +743,15 @@ def run_c5(args, orc):
                           "forward + dJ/dc, dJ/dx, dJ/du", cells=mesh.n_cells,
                           order=2, alpha=0.15, seed=0))
     line["precisions"] = out
+    gbs = p["adjoint_alg_bytes"] / (p["adjoint_kernel_ms"] * 1e-3) / 1e9
+    line["roofline"] = {
+        "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+        "kernel": "k_sf<2,elasticity,double,adjoint> + CSR node sums",
+        "kernel_ms": p["adjoint_kernel_ms"],
+        "note": f"{p['adjoint_alg_bytes'] / 1e6:.0f} MB per launch chain "
+                "(6.5 us at 8 TB/s): latency-bound, a chain of short "
+                "dependent launches"}
     if not args.no_cpu:
         def call(k):
             t = time.perf_counter()
@@ -668,13 +759,10 @@ def run_c5(args, orc):
             orc.energy(sub, "elasticity", U, c[:k], "iso_qp")
             orc.energy_grad(sub, c[:k], U)
             return time.perf_counter() - t
-        rate, k2, reps, tot = oracle_rate(call, mesh.n_cells,
-                                          args.cpu_seconds)
-        line["cpu_baseline"] = {
-            "value": rate / 1e9, "unit": "GElem/s",
-            "cores": orc.num_threads(), "kind": "oracle",
-            "sample": f"{k2} cells x {reps} passes of energy + gradient, "
-                      f"{tot:.1f} s"}
+        line["cpu_baseline"] = cpu_baseline(
+            orc, call, mesh.n_cells, args.cpu_seconds,
+            lambda k2, reps, tot: f"{k2} cells x {reps} passes of energy + "
+            f"gradient, {tot:.1f} s")
     return line
 
 # ------------------------------------------------------------------- c6 ---
@@ -752,13 +840,10 @@ def run_c6(args, orc):
             orc.matrix(submesh(mesh, slice(0, k)), "elasticity", lm[:k],
                        "iso_cell")
             return time.perf_counter() - t
-        rate, k2, reps, tot = oracle_rate(call, mesh.n_cells,
-                                          args.cpu_seconds)
-        line["cpu_baseline"] = {
-            "value": rate / 1e9, "unit": "GElem/s",
-            "cores": orc.num_threads(), "kind": "oracle",
-            "sample": f"first {k2} cells of the {n}^3 Q3 mesh x {reps} "
-                      f"passes, FP64 element matrices, {tot:.1f} s"}
+        line["cpu_baseline"] = cpu_baseline(
+            orc, call, mesh.n_cells, args.cpu_seconds,
+            lambda k2, reps, tot: f"first {k2} cells of the {n}^3 Q3 mesh x "
+            f"{reps} passes, FP64 element matrices, {tot:.1f} s")
     return line
 
 
@@ -833,13 +918,10 @@ def run_c7(args, orc):
             t = time.perf_counter()
             orc.matrix(submesh(mesh, slice(0, k)), "convect", u=U)
             return time.perf_counter() - t
-        rate, k2, reps, tot = oracle_rate(call, mesh.n_cells,
-                                          args.cpu_seconds)
-        line["cpu_baseline"] = {
-            "value": rate / 1e9, "unit": "GElem/s",
-            "cores": orc.num_threads(), "kind": "oracle",
-            "sample": f"first {k2} cells of the {n}^3 Q2 mesh x {reps} "
-                      f"passes, FP64 convection matrices, {tot:.1f} s"}
+        line["cpu_baseline"] = cpu_baseline(
+            orc, call, mesh.n_cells, args.cpu_seconds,
+            lambda k2, reps, tot: f"first {k2} cells of the {n}^3 Q2 mesh x "
+            f"{reps} passes, FP64 convection matrices, {tot:.1f} s")
     return line
 
 
@@ -952,11 +1034,10 @@ def run_c8(args, orc):
             t = time.perf_counter()
             orc.matrix(submesh(mesh, slice(0, k)), "elasticity", lm[:k], "iso_cell")
             return time.perf_counter() - t
-        rate, k2, reps, tot = oracle_rate(call, mesh.n_cells, args.cpu_seconds)
-        line["cpu_baseline"] = {
-            "value": rate / 1e9, "unit": "GElem/s", "cores": orc.num_threads(), "kind": "oracle",
-            "sample": f"first {k2} cells of the 1,024-cell Q5 mesh x {reps} passes, FP64 "
-                      f"elasticity matrices, {tot:.1f} s"}
+        line["cpu_baseline"] = cpu_baseline(
+            orc, call, mesh.n_cells, args.cpu_seconds,
+            lambda k2, reps, tot: f"first {k2} cells of the 1,024-cell Q5 mesh x {reps} "
+            f"passes, FP64 elasticity matrices, {tot:.1f} s")
     return line
 
 
@@ -970,12 +1051,33 @@ def main():
     import oracle  # test infrastructure: error vs FP64 oracle, CPU baseline
     oracle.build()
     copy_calibration(args.copy_calibration)
-    fn = {"c1": run_c1, "c2": run_c2, "c3": run_c3, "c4": run_c4,
-          "c5": run_c5, "c6": run_c6, "c7": run_c7, "c8": run_c8}[args.config]
-    line = fn(args, oracle)
-    print(json.dumps(line))
+    runs = {"c1": run_c1, "c2": run_c2, "c3": run_c3, "c4": run_c4,
+            "c5": run_c5, "c6": run_c6, "c7": run_c7, "c8": run_c8}
+    if args.config != "all":
+        line = runs[args.config](args, oracle)
+        print(json.dumps(line))
+        sys.exit(1 if "error" in line else 0)
+    # the headline workload (c2), then the other four configurations, each a
+    # complete record of its own (value, roofline, cpu_baseline, errors)
+    line = run_c2(args, oracle)
     if "error" in line:
+        print(json.dumps(line))
         sys.exit(1)
+    print(f"c2 done: {line['ms_per_step']:.3f} ms/step", file=sys.stderr,
+          flush=True)
+    line["configs"] = {}
+    for name in ("c1", "c3", "c4", "c5"):
+        t0 = time.perf_counter()
+        try:
+            sub = runs[name](args, oracle)
+        except Exception as e:  # recorded, the headline stands
+            sub = {"error": f"{type(e).__name__}: {e}"}
+        line["configs"][name] = sub
+        import torch
+        torch.cuda.empty_cache()
+        print(f"{name} done in {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
+    print(json.dumps(line))
 
 
 if __name__ == "__main__":

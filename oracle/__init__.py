@@ -75,6 +75,7 @@ def lib():
         L.orc_energy_grad.argtypes = [i32, i32, i64, i64, dp, ip, dp, dp, dp,
                                       dp]
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_num_threads.argtypes = [i32]
         _lib = L
     return _lib
 
@@ -197,6 +198,12 @@ def energy_grad(mesh, lam_mu_qp, u, want_mat=True, want_coords=True):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads of the following calls (1 = the paper's single-thread
+    mode); the results do not depend on it."""
+    lib().orc_set_num_threads(int(n))
 
 
 def assemble_matrix(mesh, cell_mats, n_comp: int):

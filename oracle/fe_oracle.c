@@ -855,3 +855,15 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads of the later parallel loops (the arithmetic does not depend on
+ * it: every cell is computed by one thread, in the same order). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -318,24 +318,37 @@ def assemble_matrix(pattern: Pattern, inc: Incidence, conn, cell_mats,
     return out
 
 
-def _energy_grad(plan, inc, coords, conn, material, dofs, scale,
-                 want_mat=True, want_coords=True, stream=None):
-    """dJ/dc and dJ/dx of the elasticity eval value (see fe_energy_grad)."""
+def energy_grad_workspace(plan, n_cells: int, device):
+    """A zero-filled workspace for _energy_grad on n_cells cells."""
     import torch
-    n_cells = conn.shape[0]
     b = ctypes.c_size_t()
     _lib.check(_lib.lib().fe_energy_grad_workspace_size(plan._h, n_cells,
                                                         ctypes.byref(b)),
                "fe_energy_grad_workspace_size")
-    ws = torch.zeros(b.value, dtype=torch.uint8, device=coords.device)
-    gm = torch.empty_like(material) if want_mat else None
-    gx = (torch.empty_like(coords) if want_coords else None)
+    return torch.zeros(b.value, dtype=torch.uint8, device=device)
+
+
+def _energy_grad(plan, inc, coords, conn, material, dofs, scale,
+                 want_mat=True, want_coords=True, stream=None, ws=None,
+                 gm=None, gx=None, check=True):
+    """dJ/dc and dJ/dx of the elasticity eval value (see fe_energy_grad).
+    ws, gm, gx may be passed preallocated; check=False skips the
+    synchronising fault check."""
+    import torch
+    n_cells = conn.shape[0]
+    if ws is None:
+        ws = energy_grad_workspace(plan, n_cells, coords.device)
+    if gm is None and want_mat:
+        gm = torch.empty_like(material)
+    if gx is None and want_coords:
+        gx = torch.empty_like(coords)
     _lib.check(_lib.lib().fe_energy_grad(
         plan._h, inc._h if inc is not None else None, n_cells,
         coords.shape[0], _ptr(coords), _ptr(conn), _ptr(material),
         _ptr(dofs), float(scale), _ptr(gm), _ptr(gx), _ptr(ws), ws.numel(),
         _stream_handle(stream)), "fe_energy_grad")
-    plan.check(ws, stream)
+    if check:
+        plan.check(ws, stream)
     return gm, gx
 
 

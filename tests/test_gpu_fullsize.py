@@ -166,3 +166,44 @@ def test_batch_uneven_full_groups(orc):
             err = _err(o[form][it].cpu().numpy(), ref)
             print(f"[fullsize] batch {m.cell}{m.order} {form} err {err:.2e}", flush=True)
             assert err < TOL["fp32"], (m.cell, m.order, form, err)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_c5_adjoint_32cube_full(orc, prec):
+    """The adjoint workload at its full size: Q2 elasticity energy
+    J = sum_e u_e^T K_e u_e on 32^3 cells (vertices +-0.15h, seed 0) with
+    per-point (lambda, mu) lognormal(0, 0.5) and u ~ N(0, 1), through the
+    autograd wrapper the benchmark times.  J against the oracle's energy, and
+    EVERY entry of dJ/dc, dJ/dx and dJ/du against the oracle's gradient and
+    twice its assembled residual."""
+    import torch
+    import paper_2107_04121_amd as fe
+    mesh = meshgen.hex_mesh(32, 2, alpha=0.15, seed=0)
+    c = meshgen.lame_qp(mesh.n_cells, 27, seed=0)
+    U = meshgen.dofs(mesh.n_nodes, 3, seed=0)
+    ep = fe.ElasticEnergyPlan("hex", 2, _t(mesh.conn), mesh.n_nodes, prec)
+    dt = ep.eval.dtype
+    ct = _t(c, dt).requires_grad_(True)
+    xt = _t(mesh.coords).requires_grad_(True)
+    ut = _t(U, dt).requires_grad_(True)
+    print(f"[fullsize] c5 32^3 adjoint {prec} eval={ep.eval.variant}", flush=True)
+    J = fe.ElasticEnergy(ct, xt, ut, ep)
+    J.backward()
+    torch.cuda.synchronize()
+    J_ref = orc.energy(mesh, "elasticity", U, c, "iso_qp").sum()
+    gm_ref, gx_ref = orc.energy_grad(mesh, c, U)
+    r = orc.residual(mesh, "elasticity", U, c, "iso_qp")
+    gu_ref = np.zeros_like(U)
+    for k in range(3):
+        np.add.at(gu_ref[:, k], mesh.conn.ravel(), r[:, k, :].ravel())
+    gu_ref *= 2.0
+
+    def rel(a, b):
+        return float(np.abs(a - b).max() / np.abs(b).max())
+
+    errs = dict(J=abs(float(J.detach()) - J_ref) / abs(J_ref),
+                dJdc=rel(ct.grad.cpu().numpy(), gm_ref),
+                dJdx=rel(xt.grad.cpu().numpy(), gx_ref),
+                dJdu=rel(ut.grad.cpu().numpy(), gu_ref))
+    print(f"[fullsize] c5 {prec} errors {errs}", flush=True)
+    assert max(errs.values()) < TOL[prec], errs
