@@ -74,14 +74,17 @@ typedef enum { FE_CELL_HEX = 0, FE_CELL_TET = 1 } fe_cell;
  * eq. fe2), non-linear: its residual is the action on the DOFs and its
  * matrix the derivative with respect to u at the DOFs passed (eq. fe4),
  *   K[(i,a),(c,m)] = int phi_a (delta_ic u . grad phi_m + du_i/dx_c phi_m),
- * so K(u) u = 2 r(u). */
+ * so K(u) u = 2 r(u).
+ * BILINEAR: any other bilinear form of the generalized notation, described
+ * by its operators and coupling (fe_bilinear, fe_plan_create_bilinear). */
 typedef enum {
     FE_FORM_MASS = 0,
     FE_FORM_VMASS = 1,
     FE_FORM_LAPLACE = 2,
     FE_FORM_ELASTICITY = 3,
     FE_FORM_WDOT = 4,
-    FE_FORM_CONVECT = 5
+    FE_FORM_CONVECT = 5,
+    FE_FORM_BILINEAR = 6
 } fe_form;
 
 /* MATRIX: element matrices (Algorithm "feloopm").  RESIDUAL: per-element
@@ -119,7 +122,11 @@ typedef enum {
     FE_VARIANT_MFMA = 2,      /* matrix mode: per-element GEMM on matrix cores */
     FE_VARIANT_SUMFACT = 3,   /* hex residual/eval: sum-factorized, gradient-first */
     FE_VARIANT_MATRIX_FIRST = 4, /* residual: form K_e then K_e u_e */
-    FE_VARIANT_CELLWISE = 5      /* matrix mode, Q1/P1/P2: one cell per lane, registers */
+    FE_VARIANT_CELLWISE = 5,     /* matrix mode, Q1/P1/P2: one cell per lane, registers */
+    FE_VARIANT_MFMA_JOBS = 6,    /* matrix mode, hex Q2-Q5: matrix-core tile jobs stored straight from the
+                                    accumulators (no staging of the cell's matrix) */
+    FE_VARIANT_MFMA_WS = 7       /* matrix mode, Q2 elasticity (ISO_CELL): tile jobs on consumer waves while
+                                    producer waves build the next cell's operand */
 } fe_variant;
 
 /* Residual output layout: CELL_MAJOR [n_cells][n_comp][n_basis] (the
@@ -130,8 +137,6 @@ typedef enum { FE_LAYOUT_CELL_MAJOR = 0, FE_LAYOUT_CELL_MINOR = 1 } fe_layout;
 
 typedef struct {
     int variant;      /* fe_variant */
-    int block;        /* threads per workgroup hint, 0 = default */
-    int elems;        /* elements per workgroup hint, 0 = default */
     int xcd_remap;    /* 1 = map contiguous element ranges to one XCD (default), 0 = off, -1 = default */
     int layout;       /* fe_layout of residual outputs */
     int chunk;        /* MATRIX_FIRST: cells per element-matrix chunk, 0 = default (16384) */
@@ -173,6 +178,72 @@ int fe_reference_tables(int cell, int order, double *weights, double *points,
 int fe_plan_create(int cell, int order, int form, int mode, int precision,
                    int material_kind, const fe_options *opts, fe_plan *out);
 
+/* Caller-supplied reference element (the paper's element loops take the
+ * reference mappings as part of their data, Algorithms "feloopv" and
+ * "feloopm"; the transpiler's evaluation function takes them with the FE
+ * data, Algorithm "wfef").  HOST arrays, copied into the plan at creation:
+ *   weights [n_qp]              quadrature weights on the reference cell;
+ *   bf      [n_qp][n_basis]     phi_a at the points;
+ *   bfg     [n_qp][3][n_basis]  d phi_a / d xi_j at the points.
+ * n_basis and n_qp must equal the library's counts for the cell and order
+ * (fe_reference_sizes: the kernels are compiled for them).  The basis must
+ * be a partition of unity (sum_a phi_a = 1, sum_a d phi_a = 0, which the
+ * isoparametric map needs to reproduce rigid translations) and the weights
+ * positive.  Hexahedral tables must be tensor products of one 1-D rule and
+ * one 1-D basis in the lexicographic order (point and node index
+ * i + n(j + n k), x fastest): the sum-factorized and matrix-core kernels
+ * work on the 1-D factors, which the library extracts and checks against
+ * the given tables (relative 1e-12).  P1 tetrahedra need constant
+ * gradients.  The reference cell itself is free: e.g. [-1,1]^3 tables
+ * (weights x 8, gradients x 1/2) give the same element matrices. */
+typedef struct {
+    int cell, order, n_basis, n_qp;
+    const double *weights;
+    const double *bf;
+    const double *bfg;
+} fe_reference;
+
+/* fe_plan_create with the caller's reference tables in place of the
+ * library's (validated as above before any device query: FE_ERR_UNSUPPORTED
+ * for sizes the kernels are not compiled for or hexahedral tables that do
+ * not factor, FE_ERR_INVALID_ARG for non-finite values, weights <= 0 or a
+ * basis that is not a partition of unity). */
+int fe_plan_create_ref(const fe_reference *ref, int form, int mode, int precision, int material_kind,
+                       const fe_options *opts, fe_plan *out);
+
+/* A bilinear form  int (test operator) . W . (unknown operator)  for the
+ * generic kernel (the shape every bilinear term of the generalized notation
+ * takes once its identity and symmetric-gradient extractor operands are
+ * contracted; the notation front-end derives these tables).
+ *   test_grad / trial_grad: 0 = basis values, 1 = physical gradients;
+ *   test_comp / trial_comp: 1 (scalar) or 3 (vector) components.
+ * Operator rows are (component r, derivative j), component-major, j absent
+ * for values: K_t = test_comp * (test_grad ? 3 : 1) rows, K_u likewise.
+ * The coupling at every quadrature point is
+ *   W0                                   [K_t][K_u]   (material NONE), or
+ *   P_test M(c, q) P_trial^T             (material TENSOR_QP),
+ * with P_test [K_t][n_a], P_trial [K_u][n_b] and the per-point material
+ * matrix M read as material[cell][point][n_a][n_b] (mat_transpose = 0) or
+ * [n_b][n_a] (1), 1 <= n_a, n_b <= 9.  HOST arrays, copied at creation.
+ * Outputs: MATRIX [n_cells][test_comp n_basis][trial_comp n_basis];
+ * RESIDUAL [n_cells][test_comp][n_basis] with DOFs [n_nodes][trial_comp];
+ * EVAL [n_cells], the test bound to the same DOFs (test_comp == trial_comp
+ * and test_grad == trial_grad). */
+typedef struct {
+    int test_grad, test_comp, trial_grad, trial_comp;
+    const double *W0;
+    const double *P_test;
+    const double *P_trial;
+    int n_a, n_b;
+    int mat_transpose;
+} fe_bilinear;
+
+/* Plan of the generic bilinear kernel: hex orders 1-3 and tets 1-2, FP64 or
+ * FP32, material_kind NONE (W0) or TENSOR_QP (P_test, P_trial).  Evaluated
+ * by fe_execute like any plan (workspace: fe_plan_workspace_size). */
+int fe_plan_create_bilinear(int cell, int order, int mode, int precision, int material_kind,
+                            const fe_bilinear *desc, const fe_options *opts, fe_plan *out);
+
 /* Plan facts: n_basis, n_qp, n_comp (1 or 3), the chosen variant and the
  * element matrix/vector row count n_comp*n_basis.  Any pointer may be NULL. */
 int fe_plan_info(fe_plan plan, int *n_basis, int *n_qp, int *n_comp,
@@ -200,6 +271,16 @@ int fe_execute(fe_plan plan, int64_t n_cells, int64_t n_nodes,
                const double *coords, const int32_t *conn, const void *material,
                const void *dofs, void *out, void *workspace,
                size_t workspace_bytes, void *stream);
+
+/* The eval mode summed over the cells: the library evaluates the per-cell
+ * values u_e^T K_e u_e into cell_values [n_cells] (device, plan precision)
+ * and adds them in a fixed order, in FP64, into total [1] (device, FP64) --
+ * the integral value of the eval mode over the whole mesh (section
+ * "Overview" of the transpiler: 'eval' returns the integral).  The plan
+ * must be an EVAL plan; other arguments as fe_execute.  Asynchronous. */
+int fe_eval_sum(fe_plan plan, int64_t n_cells, int64_t n_nodes, const double *coords, const int32_t *conn,
+                const void *material, const void *dofs, void *cell_values, double *total, void *workspace,
+                size_t workspace_bytes, void *stream);
 
 /* Synchronise `stream`, read and clear the workspace fault bits.  Returns
  * FE_ERR_INDEX_OUT_OF_RANGE or FE_ERR_NONPOSITIVE_JACOBIAN if a kernel saw
@@ -334,7 +415,10 @@ typedef struct fe_batch_s *fe_batch;
  * each group and keeps the fastest (this runs the batch, writing the
  * outputs).  Synchronous.  Errors: FE_ERR_INVALID_ARG, FE_ERR_UNSUPPORTED. */
 int fe_batch_create(int n_groups, const fe_group *groups, int precision, int autotune, fe_batch *out);
-/* Launch the captured graph on `stream` (asynchronous, allocates nothing). */
+/* Launch the captured graph on `stream` (asynchronous, allocates nothing).
+ * The batch owns one work counter: executions of the same batch must not
+ * overlap (enqueue them on one stream, or synchronise between streams);
+ * different batches are independent. */
 int fe_batch_execute(fe_batch b, void *stream);
 /* Synchronise and report det J <= 0 / out-of-range node faults (then clear). */
 int fe_batch_check(fe_batch b, void *stream);

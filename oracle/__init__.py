@@ -196,6 +196,41 @@ def energy_grad(mesh, lam_mu_qp, u, want_mat=True, want_coords=True):
     return gm, gx
 
 
+def einsum_operands(mesh):
+    """The materialised operands of the paper's expression examples (the
+    symbols table of section "Expression Examples") for every cell of a
+    mesh, from this oracle's own reference tables: det (c, q) = w_q det J,
+    bf (q, d), physical gradients bfg (c, q, j, d), the identity I and the
+    symmetric-gradient extractor Psg (3, 3, 6) in the Voigt order
+    11, 22, 33, 12, 13, 23 with ones for both shear entries."""
+    w, _, bf, bfg_ref = tables(mesh.cell, mesh.order)
+    X = np.asarray(mesh.coords)[np.asarray(mesh.conn)]   # (c, d, 3)
+    J = np.einsum("cdi,qjd->cqij", X, bfg_ref)           # dx_i / dxi_j
+    det = np.linalg.det(J)
+    if np.any(det <= 0):
+        raise OracleError(-2)
+    Ji = np.linalg.inv(J)                                # (c, q, j, i) = dxi_j / dx_i
+    bfg = np.einsum("qjd,cqji->cqid", bfg_ref, Ji)
+    Psg = np.zeros((3, 3, 6))
+    for K, (i, j) in enumerate([(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]):
+        Psg[i, j, K] = Psg[j, i, K] = 1.0
+    return dict(det=det * w[None, :], bf=bf, bfg=bfg, I=np.eye(3), Psg=Psg)
+
+
+def einsum_form(mesh, expressions, arrays):
+    """Sum over (expression, operand names) pairs of numpy.einsum of the
+    expression -- the plain definition of a transpiled weak form, evaluated
+    the way the paper's numpy backend evaluates it.  arrays supplies the
+    materials and 'dofs' (cell DOFs, (c, d) or (c, component, d)); the
+    geometric operands come from einsum_operands."""
+    ops = einsum_operands(mesh)
+    ops.update(arrays)
+    total = 0.0
+    for expr, names in expressions:
+        total = total + np.einsum(expr, *[ops[n] for n in names], optimize=True)
+    return np.asarray(total)
+
+
 def num_threads() -> int:
     return int(lib().orc_num_threads())
 

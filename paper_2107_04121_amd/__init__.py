@@ -19,8 +19,9 @@ from . import _lib
 from ._lib import FeError
 
 __all__ = ["Plan", "FeError", "Incidence", "assemble", "Pattern",
-           "assemble_matrix", "reference_sizes",
-           "reference_tables", "n_comp", "ElasticEnergy", "Batch"]
+           "assemble_matrix", "reference_sizes", "reference_tables",
+           "n_comp", "ElasticEnergy", "Batch", "BilinearPlan", "eval_sum",
+           "make_reference"]
 
 _TORCH_DT = {"fp64": "float64", "fp32": "float32", "bf16x3": "float32"}
 
@@ -51,6 +52,23 @@ def reference_tables(cell: str, order: int):
         pts.ctypes.data_as(dp), bf.ctypes.data_as(dp),
         bfg.ctypes.data_as(dp)), "fe_reference_tables")
     return w, pts, bf, bfg
+
+
+def make_reference(cell: str, order: int, weights, bf, bfg):
+    """An fe_reference over host FP64 copies of the caller's tables; returns
+    (struct, arrays kept alive for it)."""
+    w = np.ascontiguousarray(weights, dtype=np.float64)
+    b = np.ascontiguousarray(bf, dtype=np.float64)
+    g = np.ascontiguousarray(bfg, dtype=np.float64)
+    nq = w.shape[0]
+    if b.ndim != 2 or b.shape[0] != nq or g.shape != (nq, 3, b.shape[1]):
+        raise ValueError("reference tables must be weights[nq], bf[nq, nb], "
+                         "bfg[nq, 3, nb]")
+    dp = ctypes.POINTER(ctypes.c_double)
+    ref = _lib.fe_reference(_lib.CELLS[cell], int(order), b.shape[1], nq,
+                            w.ctypes.data_as(dp), b.ctypes.data_as(dp),
+                            g.ctypes.data_as(dp))
+    return ref, (w, b, g)
 
 
 def material_entries(kind, n_qp: int) -> int:
@@ -112,20 +130,34 @@ class Plan:
     def __init__(self, cell: str, order: int, form: str, mode: str = "matrix",
                  precision: str = "fp64", material: str | None = None,
                  variant: str = "auto", xcd_remap: bool = True,
-                 layout: str = "cell_major", chunk: int = 0):
+                 layout: str = "cell_major", chunk: int = 0,
+                 reference=None):
+        """reference: optional (weights[nq], bf[nq, nb], bfg[nq, 3, nb])
+        host arrays of the caller's reference element (fe_plan_create_ref);
+        by default the library builds its own."""
         self.cell, self.order, self.form = cell, int(order), form
         self.mode, self.precision, self.material = mode, precision, material
         self.layout = layout
-        opts = _lib.fe_options(_lib.VARIANTS[variant], 0, 0,
-                               1 if xcd_remap else 0, _lib.LAYOUTS[layout],
-                               int(chunk))
+        opts = _lib.fe_options(_lib.VARIANTS[variant], 1 if xcd_remap else 0,
+                               _lib.LAYOUTS[layout], int(chunk))
         h = ctypes.c_void_p()
         L = _lib.lib()
-        _lib.check(L.fe_plan_create(_lib.CELLS[cell], self.order,
-                                    _lib.FORMS[form], _lib.MODES[mode],
-                                    _lib.PRECS[precision],
-                                    _lib.MATS[material], ctypes.byref(opts),
-                                    ctypes.byref(h)), "fe_plan_create")
+        if reference is None:
+            _lib.check(L.fe_plan_create(_lib.CELLS[cell], self.order,
+                                        _lib.FORMS[form], _lib.MODES[mode],
+                                        _lib.PRECS[precision],
+                                        _lib.MATS[material],
+                                        ctypes.byref(opts), ctypes.byref(h)),
+                       "fe_plan_create")
+        else:
+            ref, self._ref_keep = make_reference(cell, self.order, *reference)
+            _lib.check(L.fe_plan_create_ref(ctypes.byref(ref),
+                                            _lib.FORMS[form], _lib.MODES[mode],
+                                            _lib.PRECS[precision],
+                                            _lib.MATS[material],
+                                            ctypes.byref(opts),
+                                            ctypes.byref(h)),
+                       "fe_plan_create_ref")
         self._h = h
         ints = [ctypes.c_int() for _ in range(5)]
         _lib.check(L.fe_plan_info(h, *[ctypes.byref(i) for i in ints]),
@@ -352,6 +384,29 @@ def _energy_grad(plan, inc, coords, conn, material, dofs, scale,
     return gm, gx
 
 
+def eval_sum(plan, coords, conn, material=None, dofs=None, cell_values=None,
+             stream=None):
+    """fe_eval_sum: the eval-mode integral over the whole mesh, summed by the
+    library in a fixed order in FP64; a 0-d float64 cuda tensor (the
+    per-cell values go to cell_values, allocated if None)."""
+    import torch
+    if plan.mode != "eval":
+        raise ValueError("eval_sum needs an eval plan")
+    validate_inputs(plan.n_basis, plan.n_qp, plan.n_comp, plan.material,
+                    plan.dtype, coords, conn, material, dofs)
+    n_cells = conn.shape[0]
+    if cell_values is None:
+        cell_values = torch.empty(n_cells, dtype=plan.dtype,
+                                  device=coords.device)
+    total = torch.empty((), dtype=torch.float64, device=coords.device)
+    ws = plan.workspace(n_cells, coords.device)
+    _lib.check(_lib.lib().fe_eval_sum(
+        plan._h, n_cells, coords.shape[0], _ptr(coords), _ptr(conn),
+        _ptr(material), _ptr(dofs), _ptr(cell_values), _ptr(total),
+        _ptr(ws), ws.numel(), _stream_handle(stream)), "fe_eval_sum")
+    return total
+
+
 class ElasticEnergyPlan:
     """Everything the elasticity energy J(c, x, u) = sum_e u_e^T K_e u_e
     needs for one mesh topology: eval and residual plans and the incidence."""
@@ -377,11 +432,11 @@ def _make_energy_function():
 
         @staticmethod
         def forward(ctx, c, x, u, ep):
-            e = ep.eval(x, ep.conn, material=c, dofs=u)
+            J = eval_sum(ep.eval, x, ep.conn, material=c, dofs=u)
             ep.eval.check()
             ctx.ep = ep
             ctx.save_for_backward(c, x, u)
-            return e.sum()
+            return J
 
         @staticmethod
         def backward(ctx, gJ):
@@ -423,8 +478,21 @@ class Batch:
     cell, for elasticity) and optionally tile.  Outputs are allocated here:
     batch.outputs[i][form] -> (n_cells, nd, nd) tensor."""
 
-    def __init__(self, groups, precision: str = "fp32", autotune: bool = True):
+    def __init__(self, groups, precision: str = "fp32", autotune: bool = True,
+                 cache: bool = True):
+        """autotune: time tile candidates per group (fe_batch_create); with
+        cache, tiles tuned before for the same groups on the same GPU
+        architecture, ROCm and library version are taken from the autotune
+        cache (FE_CACHE) instead, and new ones are stored there."""
         import torch
+        from . import autotune as _at
+        self.from_cache = False
+        if autotune and cache:
+            hit = _at.cached_batch_tiles(groups, precision)
+            if hit is not None and len(hit) == len(groups):
+                groups = [dict(g, tile=t) for g, t in zip(groups, hit)]
+                autotune = False
+                self.from_cache = True
         dt = {"fp64": torch.float64, "fp32": torch.float32}[precision]
         self.precision = precision
         self.outputs = []
@@ -489,6 +557,8 @@ class Batch:
         self.tiles = list(tiles)
         self.tuned_ms = ms.value
         self.grid = grid.value
+        if autotune and cache:
+            _at.store_batch_tiles(groups, precision, self.tiles, self.tuned_ms)
 
     def run(self, stream=None):
         _lib.check(_lib.lib().fe_batch_execute(self._h,
@@ -508,3 +578,6 @@ class Batch:
         if h is not None and h.value and lib is not None:
             lib.fe_batch_destroy(h)
             self._h = None
+
+
+from .bilinear import BilinearPlan  # noqa: E402  (uses the helpers above)

@@ -17,8 +17,9 @@ MODES = {"matrix": 0, "residual": 1, "eval": 2}
 PRECS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 MATS = {None: 0, "none": 0, "iso_cell": 1, "iso_qp": 2, "voigt_qp": 3,
         "tensor_qp": 4}
+FE_FORM_BILINEAR = 6
 VARIANTS = {"auto": 0, "generic": 1, "mfma": 2, "sumfact": 3,
-            "matrix_first": 4, "cellwise": 5}
+            "matrix_first": 4, "cellwise": 5, "mfma_jobs": 6, "mfma_ws": 7}
 VARIANT_NAMES = {v: k for k, v in VARIANTS.items()}
 
 FE_OK = 0
@@ -29,6 +30,7 @@ STATUS = {0: "FE_OK", 1: "FE_ERR_INVALID_ARG", 2: "FE_ERR_UNSUPPORTED",
 # every symbol the header declares, checked at load time
 EXPORTS = ["fe_status_string", "fe_last_error", "fe_version",
            "fe_reference_sizes", "fe_reference_tables", "fe_plan_create",
+           "fe_plan_create_ref", "fe_plan_create_bilinear", "fe_eval_sum",
            "fe_plan_info", "fe_plan_workspace_size", "fe_execute",
            "fe_plan_check", "fe_plan_destroy", "fe_incidence_create",
            "fe_incidence_destroy", "fe_assemble", "fe_pattern_create",
@@ -48,9 +50,26 @@ class FeError(RuntimeError):
 
 
 class fe_options(ctypes.Structure):
-    _fields_ = [("variant", ctypes.c_int), ("block", ctypes.c_int),
-                ("elems", ctypes.c_int), ("xcd_remap", ctypes.c_int),
+    _fields_ = [("variant", ctypes.c_int), ("xcd_remap", ctypes.c_int),
                 ("layout", ctypes.c_int), ("chunk", ctypes.c_int)]
+
+
+class fe_reference(ctypes.Structure):
+    _fields_ = [("cell", ctypes.c_int), ("order", ctypes.c_int),
+                ("n_basis", ctypes.c_int), ("n_qp", ctypes.c_int),
+                ("weights", ctypes.POINTER(ctypes.c_double)),
+                ("bf", ctypes.POINTER(ctypes.c_double)),
+                ("bfg", ctypes.POINTER(ctypes.c_double))]
+
+
+class fe_bilinear(ctypes.Structure):
+    _fields_ = [("test_grad", ctypes.c_int), ("test_comp", ctypes.c_int),
+                ("trial_grad", ctypes.c_int), ("trial_comp", ctypes.c_int),
+                ("W0", ctypes.POINTER(ctypes.c_double)),
+                ("P_test", ctypes.POINTER(ctypes.c_double)),
+                ("P_trial", ctypes.POINTER(ctypes.c_double)),
+                ("n_a", ctypes.c_int), ("n_b", ctypes.c_int),
+                ("mat_transpose", ctypes.c_int)]
 
 
 LAYOUTS = {"cell_major": 0, "cell_minor": 1}
@@ -98,6 +117,15 @@ def lib():
     L.fe_plan_create.argtypes = [i32, i32, i32, i32, i32, i32,
                                  ctypes.POINTER(fe_options),
                                  ctypes.POINTER(vp)]
+    L.fe_plan_create_ref.argtypes = [ctypes.POINTER(fe_reference), i32, i32,
+                                     i32, i32, ctypes.POINTER(fe_options),
+                                     ctypes.POINTER(vp)]
+    L.fe_plan_create_bilinear.argtypes = [i32, i32, i32, i32, i32,
+                                          ctypes.POINTER(fe_bilinear),
+                                          ctypes.POINTER(fe_options),
+                                          ctypes.POINTER(vp)]
+    L.fe_eval_sum.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, sz,
+                              vp]
     L.fe_plan_info.argtypes = [vp, ip, ip, ip, ip, ip]
     L.fe_plan_workspace_size.argtypes = [vp, i64, ctypes.POINTER(sz)]
     L.fe_execute.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, sz, vp]

@@ -32,9 +32,22 @@ int reference_sizes(int cell, int order, int *nb, int *nq);
 int reference_tables(int cell, int order, RefTables &T);
 
 // Device copy of the tables, laid out for the kernels:
-//   w[nq] | bf[nq][nb] | bfgT[nb][3][nq] | B1[n][n] | D1[n][n]   (FP64)
+//   w[nq] | bf[nq][nb] | bfgT[nb][3][nq] | B1[n][n] | D1[n][n] | coup  (FP64)
+// coup: the coupling tables of a generic bilinear plan (else empty).
 struct DevTables {
-    const double *w, *bf, *bfgT, *B1, *D1;
+    const double *w, *bf, *bfgT, *B1, *D1, *coup;
+};
+
+// Hexahedral 1-D factors of tensor-product tables (w = w1 x w1 x w1,
+// bf = B1 x B1 x B1, bfg_j with D1 in factor j), extracted from 3-D tables
+// and checked against them; FE_ERR_UNSUPPORTED if they do not factor.
+int hex_factor_tables(int order, RefTables &T, std::string &why);
+
+// Operators and coupling of a generic bilinear plan (fe_bilinear).
+struct BilinearDesc {
+    int test_grad = 0, test_comp = 1, trial_grad = 0, trial_comp = 1;
+    int Kt = 1, Ku = 1, n_a = 0, n_b = 0, mat_transpose = 0;
+    std::vector<double> coup;  // W0 [Kt][Ku] or P_test [Kt][n_a] + P_trial [Ku][n_b]
 };
 
 // Fault bits written by kernels into the first word of the workspace.
@@ -69,10 +82,18 @@ struct Plan {
     LaunchFn launch = nullptr;
     LaunchFn launch_mat = nullptr;  // MATRIX_FIRST: the matrix-mode kernel it uses
     fe_options opts{};
+    BilinearDesc bl;                // FE_FORM_BILINEAR only
 };
 
 // thread-local error message
 void set_error(const std::string &msg);
+
+}  // namespace fe
+
+// The ABI's opaque plan handle is the internal plan.
+struct fe_plan_s : fe::Plan {};
+
+namespace fe {
 
 #define FE_HIP_CHECK(call)                                                     \
     do {                                                                       \
@@ -124,6 +145,10 @@ LaunchFn select_sumfact(const Plan &p);
 LaunchFn select_cellwise(const Plan &p);
 LaunchFn select_hexmm(const Plan &p);
 LaunchFn select_hexgm(const Plan &p);
+LaunchFn select_q2ws(const Plan &p);
+LaunchFn select_bilinear(const Plan &p);
+// deterministic sum of per-cell values (FP64 or FP32) into one FP64 value
+int sum_cells(const void *vals, int prec, int64_t n, double *total, hipStream_t st);
 
 // Gradient of the elasticity eval value on hexahedra by sum factorization
 // (FE_ERR_UNSUPPORTED when the plan is not covered).
@@ -145,6 +170,13 @@ inline int64_t material_entries_per_cell(int mat_kind, int nq)
     }
 }
 size_t matrix_first_bytes(const Plan &p, int64_t n_cells);
+// Workspace bytes of fe_execute: 256 bytes of fault bits, then the
+// matrix-first chunk of element matrices when the plan uses it.
+size_t workspace_bytes_of(const Plan &p, int64_t n_cells);
+int execute_impl(const Plan *p, int64_t n_cells, int64_t n_nodes, const double *coords, const int32_t *conn,
+                 const void *material, const void *dofs, void *out, void *workspace, size_t workspace_bytes,
+                 hipStream_t stream);
+int fail(int status, const std::string &msg);
 int launch_matrix_first(const Plan &p, const ExecArgs &A, hipStream_t st);
 
 }  // namespace fe

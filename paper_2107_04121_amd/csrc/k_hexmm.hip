@@ -962,6 +962,247 @@ int launch_q3ws(const Plan &, const ExecArgs &A, hipStream_t st)
     return launch_persistent(k_elast_q3ws<MM>, Q3WS<MM>::THREADS, A, st, resident);
 }
 
+// ---------------------------------------------------------------------------
+// Q2 elasticity (per-cell coefficients) with producer and consumer waves.
+//
+// The Q2 operand (3 x 32 rows x 28 points) is small enough to keep two of
+// them in LDS, so the producers build the WHOLE operand of the next cell
+// while the consumers run this cell's jobs, and one workgroup barrier per
+// cell hands it over:
+//   consumers (8 waves): the k_hexmm jobs of the cell (21 tiles of the
+//     blocks r <= s, longest first), each stored straight from the
+//     accumulators with its mirrored tiles;
+//   producers (4 waves): the geometry and operand columns of the next cell,
+//     7 points per wave (J by sum factorization, J^-1, sqrt(w det J)), so
+//     each wave synchronises only with itself; then the coordinates of the
+//     cell after that are loaded into the other coordinate slot.
+// Consumers issue no global loads, so their stores drain while they run the
+// next cell (vector-memory counters complete in order: a load after stores
+// would wait for them); producers issue no stores.  The operand padding is
+// zeroed once, since nothing else is written there.
+template <int MM>
+struct Q2WS {
+    using H = HexMM<2, FE_FORM_ELASTICITY, MM>;
+    using T = typename H::T;
+    using OPT = typename H::OPT;
+    static constexpr int NB = 27, NQ = 27, N1 = 3;
+    static constexpr int CONS = WAVES, PROD = 4, THREADS = 64 * (CONS + PROD), PPW = 7;
+    static constexpr int OFF_TB = 0;                                  // double B1[9], D1[9], w[27]
+    static constexpr int OFF_X = q2::align16(OFF_TB + 45 * 8);        // double xs[2][3][27]
+    static constexpr int OFF_LM = q2::align16(OFF_X + 2 * 81 * 8);    // T lm[3][2]
+    static constexpr int OFF_GEO = q2::align16(OFF_LM + 6 * 8);       // double geo[PROD][PPW][19]
+    static constexpr int OFF_OP = q2::align16(OFF_GEO + PROD * PPW * 19 * 8);  // OPT op[2][NOP][ROWS][KS]
+    static constexpr int OFF_TR = OFF_OP + 2 * H::NOP * H::OP_BYTES;  // T tbuf[CONS][16][TS]
+    static constexpr int BYTES = q2::align16(OFF_TR + CONS * 16 * H::TS * (int)sizeof(T));
+};
+
+// Producer wave pw: geometry and operand columns of points 7 pw .. 7 pw + 6
+// (6 for the last wave) of the cell with coordinates x[3][27].  geo holds
+// this wave's J[7][9] then M[7][10] = sqrt(w det J) J^-1, sqrt(w det J).
+template <int MM>
+__device__ __forceinline__ void ws2_produce(int pw, const double *x, const double *B1, const double *D1,
+                                            const double *wq, double *geo, typename Q2WS<MM>::OPT *opd, int lane,
+                                            unsigned *flags)
+{
+    using W = Q2WS<MM>;
+    using H = typename W::H;
+    using OPT = typename W::OPT;
+    constexpr int N1 = 3, NB = 27, NBP = H::NBP, KS = H::KS;
+    const int np = pw < W::PROD - 1 ? W::PPW : W::NQ - W::PPW * (W::PROD - 1);
+    const int qb = W::PPW * pw;
+    double *geoJ = geo, *geoM = geo + W::PPW * 9;
+    // 1. J[i][j] at point qb + ql: lane = ql + np (3 i + j)
+    if (lane < 9 * np) {
+        const int ql = lane % np, ij = lane / np, i = ij / 3, jj = ij - 3 * (ij / 3);
+        const int q = qb + ql, q0 = q % N1, q1 = (q / N1) % N1, q2 = q / (N1 * N1);
+        const double *T0 = (jj == 0 ? D1 : B1) + q0 * N1;
+        const double *T1 = (jj == 1 ? D1 : B1) + q1 * N1;
+        const double *T2 = (jj == 2 ? D1 : B1) + q2 * N1;
+        const double *xi = x + i * NB;
+        double s2 = 0.0;
+#pragma unroll
+        for (int a2 = 0; a2 < N1; a2++) {
+            double s1 = 0.0;
+#pragma unroll
+            for (int a1 = 0; a1 < N1; a1++) {
+                const double *xr = xi + N1 * (a1 + N1 * a2);
+                s1 = fma(T1[a1], fma(T0[0], xr[0], fma(T0[1], xr[1], T0[2] * xr[2])), s1);
+            }
+            s2 = fma(T2[a2], s1, s2);
+        }
+        geoJ[ql * 9 + ij] = s2;
+    }
+    wave_sync();
+    // 2. det J, J^-1, sqrt(w det J) per point (lane = point)
+    if (lane < np) {
+        double J[3][3], Ji[3][3];
+#pragma unroll
+        for (int r = 0; r < 3; r++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) J[r][c] = geoJ[lane * 9 + r * 3 + c];
+        const double det = inverse3(J, Ji);
+        if (!(det > 0.0)) raise_fault(flags, FAULT_DET);
+        const double sw = sqrt(wq[qb + lane] * (det > 0.0 ? det : 0.0));
+#pragma unroll
+        for (int jj = 0; jj < 3; jj++)
+#pragma unroll
+            for (int i = 0; i < 3; i++) geoM[lane * 10 + jj * 3 + i] = sw * Ji[jj][i];
+        geoM[lane * 10 + 9] = sw;
+    }
+    wave_sync();
+    // 3. operand columns: item (point, a1, a2) writes a0 = 0..2 of the three
+    //    components, g_c = dx (by bz m_c) + bx (dy bz m_3+c + by dz m_6+c)
+    if (lane < 9 * np) {
+        const int ql = lane % np, a12 = lane / np, a1 = a12 % N1, a2 = a12 / N1;
+        const int q = qb + ql, q0 = q % N1, q1 = (q / N1) % N1, q2 = q / (N1 * N1);
+        const double *M = geoM + ql * 10;
+        const double by = B1[q1 * N1 + a1], bz = B1[q2 * N1 + a2];
+        const double dy = D1[q1 * N1 + a1], dz = D1[q2 * N1 + a2];
+        const double byz = by * bz, dyz = dy * bz, bdz = by * dz;
+        double f[3], h[3];
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            f[c] = byz * M[c];
+            h[c] = fma(dyz, M[3 + c], bdz * M[6 + c]);
+        }
+#pragma unroll
+        for (int a0 = 0; a0 < N1; a0++) {
+            const double bx = B1[q0 * N1 + a0], dx = D1[q0 * N1 + a0];
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                const double g = fma(dx, f[c], bx * h[c]);
+                const int o = (c * NBP + a0 + N1 * a12) * KS + q;
+                if constexpr (H::NOP == 1) {
+                    opd[o] = static_cast<OPT>(g);
+                } else {
+                    const float xf = static_cast<float>(g);
+                    const __bf16 hb = static_cast<__bf16>(xf);
+                    opd[o] = hb;
+                    opd[H::OP_BYTES / sizeof(OPT) + o] = static_cast<__bf16>(xf - static_cast<float>(hb));
+                }
+            }
+        }
+    }
+}
+
+template <int MM>
+__global__ __launch_bounds__(Q2WS<MM>::THREADS, 2) void k_elast_q2ws(ExecArgs A)
+{
+    using W = Q2WS<MM>;
+    using H = typename W::H;
+    using T = typename W::T;
+    using OPT = typename W::OPT;
+    constexpr int NB = W::NB;
+    constexpr int64_t NK = 81 * 81;
+    __shared__ __align__(16) unsigned char smem[W::BYTES];
+    double *B1 = reinterpret_cast<double *>(smem + W::OFF_TB);
+    double *D1 = B1 + 9;
+    double *wq = D1 + 9;
+    double *xs = reinterpret_cast<double *>(smem + W::OFF_X);  // [2][3][27]
+    T *lms = reinterpret_cast<T *>(smem + W::OFF_LM);          // [3][2]
+    OPT *op0 = reinterpret_cast<OPT *>(smem + W::OFF_OP);
+    OPT *op1 = reinterpret_cast<OPT *>(smem + W::OFF_OP + H::NOP * H::OP_BYTES);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const bool consumer = wave < W::CONS;
+    const int pw = wave - W::CONS;
+    double *geo = reinterpret_cast<double *>(smem + W::OFF_GEO) + (consumer ? 0 : pw * W::PPW * 19);
+    T *buf = reinterpret_cast<T *>(smem + W::OFF_TR) + (consumer ? wave : 0) * 16 * H::TS;
+
+    int64_t e, e_end, stride;
+    cell_range(A.xcd_remap, A.n_cells, e, e_end, stride);
+    if (e >= e_end) return;  // uniform over the workgroup
+    const T *mat = static_cast<const T *>(A.mat);
+    T *out = static_cast<T *>(A.out);
+
+    for (int k = tid; k < 9; k += W::THREADS) {
+        B1[k] = A.tab.B1[k];
+        D1[k] = A.tab.D1[k];
+    }
+    for (int k = tid; k < W::NQ; k += W::THREADS) wq[k] = A.tab.w[k];
+    for (int k = tid; k < 2 * H::NOP * H::OP_BYTES / (int)sizeof(OPT); k += W::THREADS) op0[k] = OPT(0);
+    const int pt = tid - 64 * W::CONS;  // producer thread 0..255
+    const int a0 = pt / 3, c0 = pt - 3 * (pt / 3);  // its coordinate (pt < 81)
+    if (!consumer) {
+        // the first two cells' coordinates and coefficients
+#pragma unroll
+        for (int s = 0; s < 2; s++) {
+            const int64_t es = e + s * stride;
+            if (es < e_end) {
+                if (pt < 3 * NB) {
+                    const int64_t n = checked_node(A.conn, es * NB + a0, A.n_nodes, A.flags);
+                    xs[s * 81 + c0 * NB + a0] = A.coords[3 * n + c0];
+                }
+                if (pt < 2) lms[s * 2 + pt] = mat[2 * es + pt];
+            }
+        }
+    }
+    __syncthreads();
+    if (!consumer) ws2_produce<MM>(pw, xs, B1, D1, wq, geo, op0, lane, A.flags);
+    __syncthreads();
+
+    // The two roles run separate loops with the same barriers in the same
+    // order (the role is uniform per wave).  Cell k of this workgroup uses
+    // operand slot k % 2, coordinate slot k % 2 and coefficient slot k % 3.
+    int k = 0;
+    if (consumer) {
+        const int nj = H::SCHED.n[wave];
+        for (;;) {
+            const bool has_next = e + stride < e_end;
+            const int slot = k % 3;
+            const T lam = lms[slot * 2], mu = lms[slot * 2 + 1];
+            const OPT *op = (k & 1) ? op1 : op0;
+            T *oc = out + e * NK;
+            for (int jj = 0; jj < nj; jj++)
+                run_job<H, FE_FORM_ELASTICITY>(H::SCHED.job[wave][jj], op, oc, buf, lam, mu, lane);
+            __syncthreads();
+            if (!has_next) break;
+            e += stride;
+            k++;
+        }
+    } else {
+        __builtin_amdgcn_s_setprio(2);
+        for (;;) {
+            const int64_t en = e + stride, enn = en + stride;
+            const bool has_next = en < e_end, has_nn = enn < e_end;
+            const int par = k & 1;
+            // the connectivity and coefficients of cell k + 2 now, its
+            // coordinates after the build (the empty asm keeps the wait for
+            // the connectivity there)
+            int32_t nn = 0;
+            T l = T(0);
+            if (has_nn) {
+                if (pt < 3 * NB) nn = A.conn[enn * NB + a0];
+                if (pt < 2) l = mat[2 * enn + pt];
+            }
+            if (has_next) ws2_produce<MM>(pw, xs + (par ^ 1) * 81, B1, D1, wq, geo, par ? op0 : op1, lane, A.flags);
+            if (has_nn) {
+                if (pt < 3 * NB) {
+                    asm volatile("" : "+v"(nn));
+                    int64_t n = nn;
+                    if (n < 0 || n >= A.n_nodes) {
+                        raise_fault(A.flags, FAULT_INDEX);
+                        n = 0;
+                    }
+                    xs[par * 81 + c0 * NB + a0] = A.coords[3 * n + c0];
+                }
+                if (pt < 2) lms[((k + 2) % 3) * 2 + pt] = l;
+            }
+            __syncthreads();
+            if (!has_next) break;
+            e = en;
+            k++;
+        }
+    }
+}
+
+template <int MM>
+int launch_q2ws(const Plan &, const ExecArgs &A, hipStream_t st)
+{
+    static std::atomic<int> resident[64];
+    return launch_persistent(k_elast_q2ws<MM>, Q2WS<MM>::THREADS, A, st, resident);
+}
+
 template <int P, int FORM, int MM>
 int launch_hexmm(const Plan &, const ExecArgs &A, hipStream_t st)
 {
@@ -1477,6 +1718,17 @@ LaunchFn pick_order(const Plan &p)
 }
 
 }  // namespace
+
+LaunchFn select_q2ws(const Plan &p)
+{
+    if (p.cell != FE_CELL_HEX || p.order != 2 || p.mode != FE_MODE_MATRIX || p.form != FE_FORM_ELASTICITY ||
+        p.mat_kind != FE_MAT_ISO_CELL)
+        return nullptr;
+    if (p.prec == FE_PREC_FP64) return launch_q2ws<MM_F64>;
+    if (p.prec == FE_PREC_FP32) return launch_q2ws<MM_F32>;
+    if (p.prec == FE_PREC_BF16X3) return launch_q2ws<MM_BF16X3>;
+    return nullptr;
+}
 
 LaunchFn select_hexmm(const Plan &p)
 {

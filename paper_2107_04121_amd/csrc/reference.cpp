@@ -19,6 +19,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <string>
 #include <vector>
 
 namespace fe {
@@ -180,6 +181,64 @@ int hex_tables_1d(int p, double *s, double *w, double *B, double *D)
     lagrange_newton(p, c);
     for (int q = 0; q < n; q++)
         for (int k = 0; k < n; k++) newton_eval(p, &c[k * n], s[q], B[q * n + k], D[q * n + k]);
+    return FE_OK;
+}
+
+int hex_factor_tables(int order, RefTables &T, std::string &why)
+{
+    // With tensor-product tables, summing bf over the second and third axes
+    // of both the point and the node index leaves B1[q0][i] s^2, where s is
+    // the sum of all entries of B1; summing that once more gives s^3.  The
+    // same sums of bfg_0 give D1 s^2, and w[(q0,0,0)] = w1[q0] w1[0]^2 with
+    // w1[0] = cbrt(w[0]).  The factors are then checked entry by entry.
+    const int n = order + 1, nb = n * n * n, nq = nb;
+    std::vector<double> Mb(n * n, 0.0), Md(n * n, 0.0);
+    for (int q = 0; q < nq; q++)
+        for (int a = 0; a < nb; a++) {
+            const int q0 = q % n, a0 = a % n;
+            Mb[q0 * n + a0] += T.bf[(size_t)q * nb + a];
+            Md[q0 * n + a0] += T.bfg[((size_t)q * 3 + 0) * nb + a];
+        }
+    double s3 = 0.0;
+    for (double v : Mb) s3 += v;
+    const double s = std::cbrt(s3);
+    if (!(std::fabs(s) > 1e-8)) {
+        why = "hexahedral tables do not factor into 1-D tables";
+        return FE_ERR_UNSUPPORTED;
+    }
+    T.B1.assign(n * n, 0.0);
+    T.D1.assign(n * n, 0.0);
+    T.w1.assign(n, 0.0);
+    T.s1.assign(n, 0.0);
+    for (int k = 0; k < n * n; k++) {
+        T.B1[k] = Mb[k] / (s * s);
+        T.D1[k] = Md[k] / (s * s);
+    }
+    const double w0 = std::cbrt(T.w[0]);
+    for (int q0 = 0; q0 < n; q0++) T.w1[q0] = T.w[q0] / (w0 * w0);
+    double err = 0.0, big = 0.0, werr = 0.0, wbig = 0.0;
+    for (int q = 0; q < nq; q++) {
+        const int q0 = q % n, q1 = (q / n) % n, q2 = q / (n * n);
+        werr = std::fmax(werr, std::fabs(T.w[q] - T.w1[q0] * T.w1[q1] * T.w1[q2]));
+        wbig = std::fmax(wbig, std::fabs(T.w[q]));
+        for (int a = 0; a < nb; a++) {
+            const int a0 = a % n, a1 = (a / n) % n, a2 = a / (n * n);
+            const double bx = T.B1[q0 * n + a0], by = T.B1[q1 * n + a1], bz = T.B1[q2 * n + a2];
+            const double dx = T.D1[q0 * n + a0], dy = T.D1[q1 * n + a1], dz = T.D1[q2 * n + a2];
+            const double ref[4] = {bx * by * bz, dx * by * bz, bx * dy * bz, bx * by * dz};
+            const double got[4] = {T.bf[(size_t)q * nb + a], T.bfg[((size_t)q * 3 + 0) * nb + a],
+                                   T.bfg[((size_t)q * 3 + 1) * nb + a], T.bfg[((size_t)q * 3 + 2) * nb + a]};
+            for (int k = 0; k < 4; k++) {
+                err = std::fmax(err, std::fabs(got[k] - ref[k]));
+                big = std::fmax(big, std::fabs(got[k]));
+            }
+        }
+    }
+    if (err > 1e-12 * std::fmax(big, 1.0) || werr > 1e-12 * wbig) {
+        why = "hexahedral tables are not tensor products of one 1-D rule and basis in lexicographic order "
+              "(x fastest)";
+        return FE_ERR_UNSUPPORTED;
+    }
     return FE_OK;
 }
 

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import meshgen
-from paper_2107_04121_amd.transpile import STATE_EINSUM, WeakForm, transpile
+from paper_2107_04121_amd.transpile import WeakForm, apply_layout, layout_support, transpile
 
 
 @pytest.mark.parametrize("expr,args,form", [
@@ -25,21 +25,51 @@ from paper_2107_04121_amd.transpile import STATE_EINSUM, WeakForm, transpile
     ("AB,s(a:b)->A,s(c:d)->B", ("D", "v", "u"), "elasticity"),
 ])
 def test_forms_recognised(expr, args, form):
+    """The dedicated kernel is chosen from the derived structure (operators,
+    component counts, the coupling left by the identity and extractor
+    operands), whatever the index letters."""
     t = transpile(expr, *args)
     assert t.form == form
+    assert t.structure["kernel"] == form
     assert t.test == args[1 if t.material else 0]
 
 
-@pytest.mark.parametrize("expr,args", [
-    ("i.i,0", ("v", "p")),            # Stokes coupling: no kernel
-    ("i.i", ("v",)),                  # divergence operator
-    ("ji,i,j", ("M", "v", "u")),      # M transposed: v_i M_ji u_j
-    ("i,j", ("v", "u")),              # not a dot product
-    ("i,i.j,j", ("v", "u", "w")),     # advection by another field
+@pytest.mark.parametrize("expr,args,test_op,trial_op", [
+    ("i.i,0", ("v", "p"), "div", "value"),      # Stokes coupling
+    ("0,i.i", ("q", "u"), "value", "div"),      # transposed Stokes coupling
+    ("ji,i,j", ("M", "v", "u"), "value", "value"),  # M transposed: v_i M_ji u_j
+    ("i.j,i.j", ("v", "u"), "grad", "grad"),    # vector Laplacian
+    ("0.i,i", ("q", "u"), "grad", "value"),
 ])
-def test_unsupported_forms_raise(expr, args):
+def test_other_bilinear_forms_go_to_the_generic_kernel(expr, args, test_op, trial_op):
+    t = transpile(expr, *args)
+    assert t.form is None and t.structure["kernel"] == "bilinear"
+    assert (t.structure["test_op"], t.structure["trial_op"]) == (test_op, trial_op)
+
+
+def test_stokes_coupling_expressions_and_coupling():
+    t = transpile("i.i,0", "v", "p")
+    assert t.einsum["matrix"][0][0] == "cq,cqid,ir,qe->crde"
+    assert t.einsum["residual"][0][0] == "cq,cqid,ir,qe,ce->crd"
+    W0 = t.structure["W0"]                      # rows (r, j), the divergence picks r == j
+    assert W0.shape == (9, 1)
+    np.testing.assert_array_equal(W0[:, 0], np.eye(3).ravel())
+
+
+@pytest.mark.parametrize("expr,args", [
+    ("i.i", ("v",)),                  # divergence operator: a linear form, no unknown
+    ("i,j.i,j", ("v", "u", "u")),    # trilinear, but not the convection
+])
+def test_forms_without_a_kernel_give_a_reason(expr, args):
+    t = transpile(expr, *args)
+    assert t.structure.get("kernel") is None and t.reason
     with pytest.raises(NotImplementedError):
-        transpile(expr, *args)
+        WeakForm((expr,) + args, "hex", 1)
+
+
+def test_more_than_one_unknown_raises():
+    with pytest.raises(NotImplementedError):
+        transpile("i,i.j,j", "v", "u", "w")     # advection by another field
 
 
 def test_malformed_expressions_raise():
@@ -49,6 +79,8 @@ def test_malformed_expressions_raise():
         transpile("0.i,0.ii", "v", "u")
     with pytest.raises(ValueError):
         transpile("i,i", "u", "u")
+    with pytest.raises(ValueError):
+        transpile("i,j", "v", "u")              # free indices: not a scalar integrand
     with pytest.raises(ValueError):
         WeakForm(("i,i", "v", "u"), "hex", 1, layout="cqgvd")
     with pytest.raises(ValueError):
@@ -62,8 +94,50 @@ def test_emitted_strings_are_the_papers():
     assert transpile("i,i", "v", "u").einsum["matrix"][0][0] == "cq,qd,ir,qe,is->crdse"
     assert transpile("IK,s(i:j)->I,s(k:l)->K", "D", "v", "u").einsum["matrix"][0][0] == \
         "cq,cqje,rjI,cqIK,cqlf,slK->cresf"
+    # and the residual of the vector dot product
+    assert transpile("i,i", "v", "u").einsum["residual"][0][0] == "cq,qd,ir,qe,cie->crd"
     # the convection matrix is a sum of two expressions (eq. fe4)
     assert len(transpile("i,i.j,j", "v", "u", "u").einsum["matrix"]) == 2
+
+
+def test_layout_permutes_data_operands():
+    t = transpile("IK,s(i:j)->I,s(k:l)->K", "D", "v", "u")
+    (e,), where = apply_layout(t, "matrix", "qcgvd0")
+    assert e == "qc,qcje,rjI,qcIK,qclf,slK->cresf" and where == "first"
+    (e,), where = apply_layout(t, "residual", "qgvd0c")
+    assert e.endswith("->rec") and where == "last"
+    assert e.split(",")[1] == "qjec"              # bfg: q, g, d, then c
+
+
+def test_layout_support_rules():
+    t = transpile("ij,i,j", "M", "v", "u")
+    assert layout_support(t, "matrix", "cqgvd0")[0]
+    assert layout_support(t, "residual", "qgvd0c")[0] is False      # material would be read q-first
+    t = transpile("0.i,0.i", "v", "u")
+    assert layout_support(t, "residual", "qgvd0c")[0]
+    assert layout_support(t, "matrix", "qgvd0c")[0] is False
+    assert layout_support(t, "residual", "qcgvd0")[0] is False      # cells neither first nor last
+    # every one of the 720 permutations is either run or refused with a reason
+    import itertools
+    for p in itertools.permutations("cqgvd0"):
+        ok, why = layout_support(t, "residual", "".join(p))
+        assert ok or why
+
+
+def test_paths_rank_gradient_first_below_matrix_first():
+    """The cheapest path of the residual contracts the DOFs with the
+    gradients first (the gradient-first order of the sum-factorized and
+    generic kernels); forming the element matrix first costs more."""
+    from paper_2107_04121_amd.contraction import path_flops
+    t = transpile("0.i,0.i", "v", "u")
+    sizes = dict(c=1, q=27, j=3, d=27, e=27)
+    (best,) = t.paths_for("residual", sizes)
+    expr = t.einsum["residual"][0][0]
+    # matrix first: det with both gradients, then the DOFs
+    mf = path_flops(expr, sizes, [(0, 1), (0, 1), (0, 1)])
+    assert best.flops < mf.flops
+    first = best.steps[0]
+    assert "ce" in first[:2] and "cqje" in first[:2]
 
 
 def _psg():
@@ -118,9 +192,6 @@ def test_emitted_einsum_matches_oracle(orc, expr, args, kind, mode):
     ops = _operands(orc, mesh, U, mats)
     ue = U[mesh.conn]                              # (c, d, nc)
     ops["dofs"] = ue[:, :, 0] if nc == 1 else np.transpose(ue, (0, 2, 1))
-    if t.form == "convect":
-        for name, (ex, names) in STATE_EINSUM.items():
-            ops[name] = np.einsum(ex, *[ops[n] for n in names])
     mat = mats.get("M", mats.get("D"))
     got = _evaluate(t, mode, ops)
     if mode == "matrix":
@@ -137,6 +208,6 @@ def test_component_counts_agree():
     """The package's n_comp and the front-end's component count agree for
     every form (mass and Laplace scalar, the rest vector)."""
     import paper_2107_04121_amd as fe
-    from paper_2107_04121_amd.transpile import _N_COMP
-    for form, nc in _N_COMP.items():
-        assert fe.n_comp(form) == nc, form
+    for expr, args, _ in CASES:
+        t = transpile(expr, *args)
+        assert fe.n_comp(t.form) == t.n_comp, t.form
