@@ -272,6 +272,25 @@ int fe_execute(fe_plan plan, int64_t n_cells, int64_t n_nodes,
                const void *dofs, void *out, void *workspace,
                size_t workspace_bytes, void *stream);
 
+/* fe_execute for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same validation, kernels and outputs, but no workspace argument.  The fault
+ * bits and the matrix-first chunk of element matrices live in a static
+ * device array of 64 MiB that the library holds on every device it runs on
+ * until the process ends; the call allocates nothing.
+ *   fault_out: device pointer to one unsigned, or NULL; receives this call's
+ *     fault bits (1 = det J <= 0, 2 = node index out of range), cleared at
+ *     the start of the call.
+ * A call whose workspace would exceed 64 MiB (a matrix-first plan whose
+ * chunk of element matrices is larger) returns FE_ERR_INVALID_ARG and
+ * enqueues nothing.  Every call on a device shares that device's array:
+ * calls that overlap on one GPU (different streams, different host threads)
+ * race on it.  Asynchronous on `stream`. */
+int fe_execute_noalloc(fe_plan plan, int64_t n_cells, int64_t n_nodes,
+                       const double *coords, const int32_t *conn,
+                       const void *material, const void *dofs, void *out,
+                       unsigned *fault_out, void *stream);
+
 /* The eval mode summed over the cells: the library evaluates the per-cell
  * values u_e^T K_e u_e into cell_values [n_cells] (device, plan precision)
  * and adds them in a fixed order, in FP64, into total [1] (device, FP64) --

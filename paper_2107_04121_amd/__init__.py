@@ -229,6 +229,26 @@ class Plan:
             _stream_handle(stream)), "fe_execute")
         return out
 
+    def execute_noalloc(self, coords, conn, material=None, dofs=None,
+                        out=None, fault=None, stream=None):
+        """fe_execute_noalloc: the same evaluation without a workspace (the
+        library's static device scratch holds the fault bits and any
+        matrix-first chunk).  out must be given (nothing is allocated);
+        fault, a one-element int32 cuda tensor or None, receives the call's
+        fault bits."""
+        validate_inputs(self.n_basis, self.n_qp, self.n_comp, self.material,
+                        self.dtype, coords, conn, material, dofs)
+        n_cells = conn.shape[0]
+        if out is None or tuple(out.shape) != self.out_shape(n_cells) or \
+                out.dtype != self.dtype or not out.is_contiguous():
+            raise ValueError("out must be a preallocated contiguous tensor "
+                             f"of shape {self.out_shape(n_cells)}")
+        _lib.check(_lib.lib().fe_execute_noalloc(
+            self._h, n_cells, coords.shape[0], _ptr(coords), _ptr(conn),
+            _ptr(material), _ptr(dofs), _ptr(out), _ptr(fault),
+            _stream_handle(stream)), "fe_execute_noalloc")
+        return out
+
     def check(self, workspace=None, stream=None):
         """Synchronise and raise FeError if a kernel saw det J <= 0 or an
         out-of-range node number since the last check."""

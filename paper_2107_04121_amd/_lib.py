@@ -32,6 +32,7 @@ EXPORTS = ["fe_status_string", "fe_last_error", "fe_version",
            "fe_reference_sizes", "fe_reference_tables", "fe_plan_create",
            "fe_plan_create_ref", "fe_plan_create_bilinear", "fe_eval_sum",
            "fe_plan_info", "fe_plan_workspace_size", "fe_execute",
+           "fe_execute_noalloc",
            "fe_plan_check", "fe_plan_destroy", "fe_incidence_create",
            "fe_incidence_destroy", "fe_assemble", "fe_pattern_create",
            "fe_pattern_info", "fe_pattern_copy", "fe_pattern_destroy",
@@ -129,6 +130,8 @@ def lib():
     L.fe_plan_info.argtypes = [vp, ip, ip, ip, ip, ip]
     L.fe_plan_workspace_size.argtypes = [vp, i64, ctypes.POINTER(sz)]
     L.fe_execute.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.fe_execute_noalloc.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp,
+                                     vp]
     L.fe_plan_check.argtypes = [vp, vp, vp]
     L.fe_plan_destroy.argtypes = [vp]
     dbl = ctypes.c_double

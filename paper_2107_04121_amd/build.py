@@ -24,7 +24,7 @@ SOURCES = ["api.hip", "reference.cpp", "k_generic_f64.hip",
            "k_generic_f32.hip", "k_mfma.hip", "k_sumfact.hip",
            "k_adjoint.hip", "k_batch.hip", "k_matfirst.hip",
            "k_cellwise.hip", "k_hexmm.hip", "k_assembly.hip",
-           "k_hexgm.hip", "k_bilinear.hip",
+           "k_hexgm.hip", "k_noalloc.hip", "k_bilinear.hip",
            "k_reduce.hip"]
 
 
