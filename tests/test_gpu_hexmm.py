@@ -113,3 +113,39 @@ def test_hexmm_matches_generic(p, prec):
     a = fe.Plan("hex", p, "laplace", "matrix", prec)(X, C)
     b = fe.Plan("hex", p, "laplace", "matrix", prec, variant="generic")(X, C)
     assert _err(a.cpu().numpy(), b.cpu().numpy().astype(np.float64)) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("variant", ["mfma_jobs", "mfma_ws"])
+def test_q2_elasticity_variants(orc, variant, prec):
+    """The other two matrix-core kernels of Q2 elasticity (per-cell Lame
+    coefficients): tile jobs stored straight from the accumulators, and the
+    same jobs on consumer waves while producer waves build the next cell's
+    operand.  1100 cells (several per workgroup, uneven XCD ranges): sampled
+    cells against the FP64 oracle, every cell for symmetry and rigid
+    translations, and the staged kernel's output to the same gate."""
+    import torch
+    import paper_2107_04121_amd as fe
+    mesh = meshgen.hex_mesh(DIMS[2], 2, alpha=0.15, seed=22, curved=0.04)
+    lm = meshgen.lame_cell(mesh.n_cells, seed=23)
+    plan = fe.Plan("hex", 2, "elasticity", "matrix", prec, material="iso_cell", variant=variant)
+    print(f"[q2-elast] {variant} {prec} variant={plan.variant} cells={mesh.n_cells}", flush=True)
+    assert plan.variant == variant
+    X, C, M = _t(mesh.coords), _t(mesh.conn), _t(lm, plan.dtype)
+    K = plan(X, C, material=M)
+    plan.check()
+    idx = _sample(mesh.n_cells)
+    ref = orc.matrix(_sub(mesh, idx), "elasticity", lm[idx], "iso_cell")
+    err = _err(K[_t(idx)].cpu().numpy(), ref)
+    print(f"[q2-elast] sampled err {err:.2e}", flush=True)
+    assert err < TOL[prec], err
+    tol = TOL[prec]
+    Kd = K.double()
+    scale = Kd.abs().amax(dim=(1, 2))
+    assert ((Kd - Kd.transpose(1, 2)).abs().amax(dim=(1, 2)) / scale).max().item() < 4 * tol
+    for c in range(3):
+        t = torch.zeros(81, dtype=torch.float64, device=K.device)
+        t[c * 27:(c + 1) * 27] = 1
+        assert ((Kd @ t).abs().amax(dim=1) / scale).max().item() < 50 * tol
+    staged = fe.Plan("hex", 2, "elasticity", "matrix", prec, material="iso_cell")(X, C, material=M)
+    assert _err(K.cpu().numpy(), staged.double().cpu().numpy()) < tol
