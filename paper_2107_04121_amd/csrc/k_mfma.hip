@@ -19,16 +19,19 @@
 //   2. Jacobian columns from the tensor-product 1-D tables, then det J, J^-1
 //      and w det J per quadrature point, all FP64;
 //   3. G[q][(i,a)] = sum_j dphi_a/dxi_j Jinv[j][i] in FP64, stored in LDS in
-//      the contraction type as the GEMM operand (rows padded 27 -> 32 per
-//      component, K padded to the MFMA depth);
-//   4. 24 output tiles of 16x16 (6 per wave) on MFMA:
-//        FP64: v_mfma_f64_16x16x4f64, FP32: v_mfma_f32_16x16x4f32,
-//        BF16X3: v_mfma_f32_16x16x32_bf16 three times per tile on the split
-//        operands (hi*hi + hi*lo + lo*hi, FP32 accumulation);
-//   5. P blocks to LDS (aliasing the operand area);
-//   6. epilogue: every thread owns fixed (a,b) positions of the 27x27 blocks
-//      and writes all nine blocks' entries there; consecutive lanes write
-//      consecutive entries of 27-wide row segments (non-temporal stores).
+//      the contraction type as the GEMM operand (K padded to the MFMA depth);
+//   4. the products on the matrix cores, K, and a linear flush of the cell's
+//      81x81 matrix from an LDS staging area with 16-byte stores.
+// FP64 and FP32 (staged routine): the 24 output tiles of 16x16 of the blocks
+// r <= s of P (6 per wave; v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32)
+// go to the staging area, and an in-place pass turns P into K there (every
+// thread owns fixed (a,b) positions of the 27x27 blocks).  The split
+// precision BF16X3 (v_mfma_f32_16x16x32_bf16 three times per tile on the
+// hi/lo halves, FP32 accumulation) makes the products cheap, so it computes
+// P_rs for all nine (r, s) at three tile positions, forms K in registers and
+// stores K tiles (and the transposes that K's symmetry provides) to the
+// staging area directly.  Prefetch of the next cell's data overlaps each
+// cell's work.
 #include "q2_device.h"
 
 namespace fe {
@@ -37,7 +40,7 @@ namespace {
 using namespace q2;
 
 template <int MM>
-__global__ __launch_bounds__(256, MM == MM_F32 ? 4 : 3) void k_elast_q2(ExecArgs A)
+__global__ __launch_bounds__(256, MM == MM_F64 ? 3 : 4) void k_elast_q2(ExecArgs A)
 {
     __shared__ __align__(16) unsigned char smem[Q2Layout<MM>::BYTES];
     int64_t e, e_end, stride;

@@ -1,7 +1,10 @@
-// Q2 hexahedron linear-elasticity cell routine on the matrix cores (shared
+// Q2 hexahedron linear-elasticity cell routines on the matrix cores (shared
 // by the single-form kernel and the batched kernel).  See k_mfma.hip for the
 // method.
 #pragma once
+
+#include <type_traits>
+#include <utility>
 
 #include "fe_device.h"
 
@@ -32,11 +35,15 @@ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 // Q2 hexahedron
 constexpr int NB = 27, NQ = 27, ND = 81, NK = ND * ND;
 
+// ---------------------------------------------------------------------------
+// Staged routine (FP64, FP32): the 24 tiles of the blocks r <= s of P on the
+// matrix cores, P to LDS, K from P in place, a linear flush.
 template <int MM>
-struct Q2Layout {
+struct Q2Staged {
     using T = typename MMT<MM>::T;
     static constexpr int VEC = 16 / (int)sizeof(T);       // entries per 16-byte store
-    static constexpr int KP = MM == MM_BF16X3 ? 32 : 28;  // padded K (quadrature points)
+    static constexpr int KP = 28;                          // padded K (quadrature points)
+    static_assert(MM == MM_F64 || MM == MM_F32, "the staged routine runs FP64 and FP32");
     // kept for the whole launch: 1-D tables and weights
     static constexpr int OFF_TB = 0;                      // double B1[9], D1[9], w[27]
     // the next cell's coordinates and coefficients, parked before the flush
@@ -63,6 +70,7 @@ struct Q2Layout {
     // 16-byte vectors of the staged matrix per thread in the flush
     static constexpr int NV = ((NK + 2 * VEC - 1) / VEC + 255) / 256;
 };
+
 
 // Persistent schedule: every workgroup walks a strided list of cells.  With
 // XCD remapping, the 8 XCDs (hardware workgroup id modulo 8) own 8
@@ -120,7 +128,7 @@ __device__ __forceinline__ void mma_rect(const typename MMT<MM>::T *Gs, const do
     const int col = lane & 15, grp = lane >> 4;
 #pragma unroll
     for (int t = 0; t < 6; t++) acc[t] = typename MMT<MM>::acc{};
-    constexpr int KS = Q2Layout<MM>::KS;
+    constexpr int KS = Q2Staged<MM>::KS;
     // operand row of tile row TM for this lane: component TM/2, basis
     // 16*(TM%2) + lane%16
     int ra[NA], rb[NBF];
@@ -128,54 +136,22 @@ __device__ __forceinline__ void mma_rect(const typename MMT<MM>::T *Gs, const do
     for (int i = 0; i < NA; i++) ra[i] = ((ar[i] >> 1) * 33 + (ar[i] & 1) * 16 + col) * KS;
 #pragma unroll
     for (int j = 0; j < NBF; j++) rb[j] = ((bc[j] >> 1) * 33 + (bc[j] & 1) * 16 + col) * KS;
-    if constexpr (MM == MM_F64 || MM == MM_F32) {
 #pragma unroll
-        for (int kk = 0; kk < Q2Layout<MM>::KP / 4; kk++) {
-            const int k = 4 * kk + grp;
-            const T w = static_cast<T>(wd[k]);  // wd[27] == 0 (padding)
-            T a[NA], b[NBF];
+    for (int kk = 0; kk < Q2Staged<MM>::KP / 4; kk++) {
+        const int k = 4 * kk + grp;
+        const T w = static_cast<T>(wd[k]);  // wd[27] == 0 (padding)
+        T a[NA], b[NBF];
 #pragma unroll
-            for (int i = 0; i < NA; i++) a[i] = Gs[ra[i] + k] * w;
+        for (int i = 0; i < NA; i++) a[i] = Gs[ra[i] + k] * w;
 #pragma unroll
-            for (int j = 0; j < NBF; j++) b[j] = Gs[rb[j] + k];
+        for (int j = 0; j < NBF; j++) b[j] = Gs[rb[j] + k];
 #pragma unroll
-            for (int t = 0; t < 6; t++) {
-                if constexpr (MM == MM_F64)
-                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta[t]], b[tb[t]], acc[t], 0, 0, 0);
-                else
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ta[t]], b[tb[t]], acc[t], 0, 0, 0);
-            }
+        for (int t = 0; t < 6; t++) {
+            if constexpr (MM == MM_F64)
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta[t]], b[tb[t]], acc[t], 0, 0, 0);
+            else
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ta[t]], b[tb[t]], acc[t], 0, 0, 0);
         }
-    } else {
-        bf8 ahi[NA], alo[NA], bhi[NBF], blo[NBF];
-#pragma unroll
-        for (int u = 0; u < 8; u++) {
-            const int k = 8 * grp + u;
-            const float w = k < NQ ? static_cast<float>(wd[k]) : 0.0f;
-#pragma unroll
-            for (int i = 0; i < NA; i++) {
-                const float x = Gs[ra[i] + k] * w;
-                const __bf16 h = static_cast<__bf16>(x);
-                ahi[i][u] = h;
-                alo[i][u] = static_cast<__bf16>(x - static_cast<float>(h));
-            }
-#pragma unroll
-            for (int j = 0; j < NBF; j++) {
-                const float x = Gs[rb[j] + k];
-                const __bf16 h = static_cast<__bf16>(x);
-                bhi[j][u] = h;
-                blo[j][u] = static_cast<__bf16>(x - static_cast<float>(h));
-            }
-        }
-#pragma unroll
-        for (int t = 0; t < 6; t++)
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[ta[t]], bhi[tb[t]], acc[t], 0, 0, 0);
-#pragma unroll
-        for (int t = 0; t < 6; t++)
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[ta[t]], blo[tb[t]], acc[t], 0, 0, 0);
-#pragma unroll
-        for (int t = 0; t < 6; t++)
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[ta[t]], bhi[tb[t]], acc[t], 0, 0, 0);
     }
 }
 
@@ -197,8 +173,7 @@ __device__ __forceinline__ void mma_wave(const typename MMT<MM>::T *Gs, const do
 }
 
 // 16x16 tile (TM, TN) of the scalar mass matrix sum_q wd[q] phi_a(q) phi_b(q)
-// on the matrix cores, basis values built from the 1-D table B1 (FP32 MFMA
-// for the split precision as well).
+// on the matrix cores, basis values built from the 1-D table B1.
 template <int MM>
 __device__ __forceinline__ typename MMT<MM>::acc mass_tile(const double *B1, const double *wd, int TM, int TN,
                                                            int lane)
@@ -264,16 +239,12 @@ struct Q2Job {
     DevTables tab;
 };
 
-// Q2 cells e, e + stride, ... < e_end with one workgroup of 256 threads.
-// MULTI also emits the Laplace matrix P_00 + P_11 + P_22 (a by-product of
-// the elasticity contraction) and the scalar mass matrix (one more small
-// product on the matrix cores), sharing the geometry.  smem must hold
-// Q2Layout<MM>::BYTES.  Ends with the workgroup synchronised.
+// Q2 cells e, e + stride, ... < e_end, FP64 or FP32; see q2_run.
 template <int MM, bool MULTI>
-__device__ __forceinline__ void q2_run(const Q2Job &A, int64_t e, int64_t e_end, int64_t stride, unsigned char *smem,
+__device__ __forceinline__ void q2_run_staged(const Q2Job &A, int64_t e, int64_t e_end, int64_t stride, unsigned char *smem,
                                        int tid)
 {
-    using L = Q2Layout<MM>;
+    using L = Q2Staged<MM>;
     using T = typename L::T;
     using ACC = typename MMT<MM>::acc;
     typedef T TV __attribute__((ext_vector_type(L::VEC)));
@@ -379,8 +350,10 @@ __device__ __forceinline__ void q2_run(const Q2Job &A, int64_t e, int64_t e_end,
         T lamn = T(0), mun = T(0);
         if (has_next) {
             if (tid < NB * 3) nn = conn[en * NB + ga];
-            lamn = mat[2 * en];
-            mun = mat[2 * en + 1];
+            if (tid == 0) {  // only the thread that parks them: a dead load would still be waited for
+                lamn = mat[2 * en];
+                mun = mat[2 * en + 1];
+            }
         }
         if (tid < NQ * 9) {
             const int q = tid % NQ, r9 = tid / NQ, ci = r9 / 3, a2 = r9 - 3 * (r9 / 3);
@@ -587,6 +560,464 @@ __device__ __forceinline__ void q2_run(const Q2Job &A, int64_t e, int64_t e_end,
         __syncthreads();  // the staging area is reused by the next cell
         if (!has_next) break;
         e = en;
+    }
+}
+// ---------------------------------------------------------------------------
+// Split routine (BF16X3: every operand a sum hi + lo of two bf16 values, the
+// product hi*hi + hi*lo + lo*hi accumulated in FP32 on the bf16 matrix
+// cores).  The products are cheap at this precision, so K is formed in
+// registers instead of through an in-place pass over P: the operand is
+// scaled symmetrically, Gt[27 i + a][k] = sqrt(w_k det J_k) dphi_a/dx_i (x_k),
+// so that P_rs[a][b] = sum_k Gt[27 r + a][k] Gt[27 s + b][k], and with
+// lambda, mu constant over the cell
+//   K_rs = lambda P_rs + mu P_sr  (r != s),
+//   K_rr = (lambda + mu) P_rr + mu (P_00 + P_11 + P_22).
+// Each 27x27 block is covered by 2x2 tiles of 16x16 at positions (x, y).  K
+// is symmetric, so its tiles at (1, 0) are the transposes of those at (0, 1)
+// and only positions (0,0), (1,1) and (0,1) are computed: P_rs for all nine
+// (r, s) at three positions, 27 tile products, 7 + 7 + 7 + 6 over the four
+// waves.  Products are grouped so that K follows in registers: a diagonal
+// group (P_00, P_11, P_22 at one position) gives K_00, K_11 and K_22 there,
+// a pair group (P_rs, P_sr) gives K_rs and K_sr.
+struct Q2Split {
+    using T = float;
+    static constexpr int VEC = 4;  // entries per 16-byte store
+    // The staging area holds the cell's 81x81 matrix with every 27-entry
+    // segment of a row padded to 28 (entry f at f + f/27), so that block
+    // columns, and the four consecutive columns one lane holds, start on
+    // 16-byte boundaries.
+    static constexpr int SROW = 84, SBLK = 28;
+    static constexpr int STAGE_BYTES = ND * SROW * 4;
+    // operand halves hi[row][k], lo[row][k]: component i's rows start at
+    // 27 i, rows 81..85 only pad the second tile of the last component; depth
+    // padded with zeros to 32 (one bf16 step); a row stride of 40 entries
+    // (8 mod 16) keeps the 16-byte fragment reads free of bank conflicts
+    static constexpr int OROWS = 86, KP = 32, KS = 40;
+    static constexpr int OP_BYTES = 2 * OROWS * KS * 2;
+    // kept for the whole launch: 1-D tables and weights
+    static constexpr int OFF_TB = 0;                                  // double B1[9], D1[9], w[27]
+    // the next cell's coordinates and coefficients, parked before the flush
+    static constexpr int OFF_N = align16(OFF_TB + (9 + 9 + NQ) * 8);  // double xn[81], float lmn[2]
+    static constexpr int OFF_S = align16(OFF_N + 81 * 8 + 2 * 4);      // staging
+    // per cell, inside the staging area (written only after the last
+    // operand read): coordinates, J and the operand halves
+    static constexpr int OFF_X = OFF_S;                               // double xc[3][28] (component-major)
+    static constexpr int OFF_J = OFF_X + 3 * 28 * 8;                  // double J[27][9]
+    static constexpr int OFF_OP = align16(OFF_J + NQ * 9 * 8);
+    static constexpr int BYTES = align16(OFF_S + STAGE_BYTES);
+    // 16-byte vectors of the staged matrix per thread in the flush
+    static constexpr int NV = ((NK + 2 * VEC - 1) / VEC + 255) / 256;
+    static_assert(OFF_OP + OP_BYTES <= OFF_S + STAGE_BYTES, "operand outside the staging area");
+};
+
+template <typename F, int... Is>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, Is...>)
+{
+    (f(std::integral_constant<int, Is>{}), ...);
+}
+// f(integral_constant<int, 0>) ... f(integral_constant<int, N - 1>)
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// Work of wave W in the split routine.
+//   F: operand fragments the wave loads, id 3 t + i = rows 27 i + 16 t ..
+//   C: products (r, s, x, y);  G: groups (0 diagonal / 1 pair, first product)
+template <int W>
+struct WavePlan;
+template <>
+struct WavePlan<0> {  // position (0,0): everything but the pair (1,2)
+    static constexpr int NF = 3, NC = 7, NG = 3;
+    static constexpr int F[6] = {0, 1, 2};
+    static constexpr int C[7][4] = {{0, 0, 0, 0}, {1, 1, 0, 0}, {2, 2, 0, 0}, {0, 1, 0, 0},
+                                    {1, 0, 0, 0}, {0, 2, 0, 0}, {2, 0, 0, 0}};
+    static constexpr int G[3][2] = {{0, 0}, {1, 3}, {1, 5}};
+};
+template <>
+struct WavePlan<1> {  // pair (1,2) at (0,0); diagonal and pair (0,1) at (1,1)
+    static constexpr int NF = 5, NC = 7, NG = 3;
+    static constexpr int F[6] = {1, 2, 3, 4, 5};
+    static constexpr int C[7][4] = {{1, 2, 0, 0}, {2, 1, 0, 0}, {0, 0, 1, 1}, {1, 1, 1, 1},
+                                    {2, 2, 1, 1}, {0, 1, 1, 1}, {1, 0, 1, 1}};
+    static constexpr int G[3][2] = {{1, 0}, {0, 2}, {1, 5}};
+};
+template <>
+struct WavePlan<2> {  // pairs (0,2), (1,2) at (1,1); diagonal at (0,1)
+    static constexpr int NF = 6, NC = 7, NG = 3;
+    static constexpr int F[6] = {0, 1, 2, 3, 4, 5};
+    static constexpr int C[7][4] = {{0, 2, 1, 1}, {2, 0, 1, 1}, {1, 2, 1, 1}, {2, 1, 1, 1},
+                                    {0, 0, 0, 1}, {1, 1, 0, 1}, {2, 2, 0, 1}};
+    static constexpr int G[3][2] = {{1, 0}, {1, 2}, {0, 4}};
+};
+template <>
+struct WavePlan<3> {  // the three pairs at (0,1)
+    static constexpr int NF = 6, NC = 6, NG = 3;
+    static constexpr int F[6] = {0, 1, 2, 3, 4, 5};
+    static constexpr int C[7][4] = {{0, 1, 0, 1}, {1, 0, 0, 1}, {0, 2, 0, 1},
+                                    {2, 0, 0, 1}, {1, 2, 0, 1}, {2, 1, 0, 1}};
+    static constexpr int G[3][2] = {{1, 0}, {1, 2}, {1, 4}};
+};
+
+template <typename WP>
+constexpr int frag_slot(int id)
+{
+    for (int n = 0; n < WP::NF; n++)
+        if (WP::F[n] == id) return n;
+    return -1;
+}
+
+constexpr int frag_row(int id) { return (id % 3) * NB + (id / 3) * 16; }
+
+// The wave's tile products.  The fragment of rows 27 s + 16 y .. goes in as
+// the MFMA's first operand and that of rows 27 r + 16 x .. as the second, so
+// the accumulator holds P_rs transposed: lane (g, c) = (lane / 16, lane % 16)
+// owns row a = 16 x + c and columns b = 16 y + 4 g + v, v = 0..3.
+template <typename WP>
+__device__ __forceinline__ void split_gemm(const unsigned char *op, int lane, f4 (&acc)[7])
+{
+    using L = Q2Split;
+    const int c = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int m = 0; m < 7; m++) acc[m] = f4{};
+    const __bf16 *hi = reinterpret_cast<const __bf16 *>(op);
+    const __bf16 *lo = hi + L::OROWS * L::KS;
+    bf8 fh[WP::NF], fl[WP::NF];
+#pragma unroll
+    for (int n = 0; n < WP::NF; n++) {
+        const int o = (frag_row(WP::F[n]) + c) * L::KS + 8 * g;
+        fh[n] = *reinterpret_cast<const bf8 *>(hi + o);
+        fl[n] = *reinterpret_cast<const bf8 *>(lo + o);
+    }
+    // the small cross terms first, then hi * hi (FP32 accumulation)
+    static_for<WP::NC>([&](auto m) {
+        constexpr int ia = frag_slot<WP>(3 * WP::C[m][3] + WP::C[m][1]);
+        constexpr int ib = frag_slot<WP>(3 * WP::C[m][2] + WP::C[m][0]);
+        static_assert(ia >= 0 && ib >= 0, "fragment missing from the wave plan");
+        acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fl[ia], fh[ib], acc[m], 0, 0, 0);
+    });
+    static_for<WP::NC>([&](auto m) {
+        constexpr int ia = frag_slot<WP>(3 * WP::C[m][3] + WP::C[m][1]);
+        constexpr int ib = frag_slot<WP>(3 * WP::C[m][2] + WP::C[m][0]);
+        acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fh[ia], fl[ib], acc[m], 0, 0, 0);
+    });
+    static_for<WP::NC>([&](auto m) {
+        constexpr int ia = frag_slot<WP>(3 * WP::C[m][3] + WP::C[m][1]);
+        constexpr int ib = frag_slot<WP>(3 * WP::C[m][2] + WP::C[m][0]);
+        acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fh[ia], fh[ib], acc[m], 0, 0, 0);
+    });
+}
+
+// One K tile (block (R, S), position (x, y), held as described at
+// split_gemm) into the staging area; with TR also its transpose, tile (1, 0)
+// of block (S, R) (only position (0, 1) is transposed, so x = 0 there).
+template <bool TR>
+__device__ __forceinline__ void put_tile(float *Ks, const f4 &k, int R, int S, int x, int y, int lane)
+{
+    using L = Q2Split;
+    const int c = lane & 15, g = lane >> 4;
+    const int a = 16 * x + c;
+    // one 16-byte vector of columns 16 y + 4 g ..; for y = 1, g = 2 its
+    // last entry falls on the segment's pad word, g = 3 is outside
+    if (a < NB && (y == 0 || g < 3))
+        *reinterpret_cast<f4 *>(Ks + (R * NB + a) * L::SROW + S * L::SBLK + 16 * y + 4 * g) = k;
+    if constexpr (TR) {
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            const int b = 16 + 4 * g + v;
+            if (b < NB) Ks[(S * NB + b) * L::SROW + R * L::SBLK + c] = k[v];
+        }
+    }
+}
+
+// K from the wave's tile products into the staging area.
+template <typename WP>
+__device__ __forceinline__ void split_epilogue(float *Ks, const f4 (&acc)[7], float lam, float mu, int lane)
+{
+    const float lm = lam + mu;
+    static_for<WP::NG>([&](auto gi) {
+        constexpr int kind = WP::G[gi][0], c0 = WP::G[gi][1];
+        constexpr int x = WP::C[c0][2], y = WP::C[c0][3];
+        constexpr bool TR = x == 0 && y == 1;
+        if constexpr (kind == 0) {
+            const f4 mtr = mu * (acc[c0] + acc[c0 + 1] + acc[c0 + 2]);
+            put_tile<TR>(Ks, lm * acc[c0] + mtr, 0, 0, x, y, lane);
+            put_tile<TR>(Ks, lm * acc[c0 + 1] + mtr, 1, 1, x, y, lane);
+            put_tile<TR>(Ks, lm * acc[c0 + 2] + mtr, 2, 2, x, y, lane);
+        } else {
+            constexpr int r = WP::C[c0][0], s = WP::C[c0][1];
+            put_tile<TR>(Ks, lam * acc[c0] + mu * acc[c0 + 1], r, s, x, y, lane);
+            put_tile<TR>(Ks, lam * acc[c0 + 1] + mu * acc[c0], s, r, x, y, lane);
+        }
+    });
+}
+
+// Q2 cells e, e + stride, ... < e_end in the split precision; see q2_run.
+__device__ __forceinline__ void q2_run_split(const Q2Job &A, int64_t e, int64_t e_end, int64_t stride,
+                                             unsigned char *smem, int tid)
+{
+    using L = Q2Split;
+    typedef float TV __attribute__((ext_vector_type(4)));
+    double *B1 = reinterpret_cast<double *>(smem + L::OFF_TB);
+    double *D1 = B1 + 9;
+    double *wq = D1 + 9;
+    double *xn = reinterpret_cast<double *>(smem + L::OFF_N);
+    float *lmn = reinterpret_cast<float *>(xn + 81);
+    double *xc = reinterpret_cast<double *>(smem + L::OFF_X);
+    double *Jq = reinterpret_cast<double *>(smem + L::OFF_J);
+    float *Ks = reinterpret_cast<float *>(smem + L::OFF_S);
+    unsigned char *op = smem + L::OFF_OP;
+    __bf16 *ohi = reinterpret_cast<__bf16 *>(op);
+    // wave-uniform, and known to be so (scalar branches below)
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    if (e >= e_end) return;  // uniform over the workgroup
+
+    if (tid < 9) {
+        B1[tid] = gmem(A.tab.B1)[tid];
+        D1[tid] = gmem(A.tab.D1)[tid];
+    } else if (tid >= 32 && tid < 32 + NQ) {
+        wq[tid - 32] = gmem(A.tab.w)[tid - 32];
+    }
+    const auto mat = gmem(static_cast<const float *>(A.mat));
+    const auto conn = gmem(A.conn);
+    const auto coords = gmem(A.coords);
+    // this thread's node coordinate (threads < 81: node a = tid/3, axis tid%3)
+    const int ga = tid / 3, gc = tid - 3 * (tid / 3);
+    // the first cell's coordinates and coefficients go to the parking slots
+    // the loop reads every cell's data from (see the park step below)
+    if (tid < NB * 3) {
+        int64_t n = conn[e * NB + ga];
+        if (n < 0 || n >= A.n_nodes) {
+            raise_fault(A.flags, FAULT_INDEX);
+            n = 0;
+        }
+        xn[tid] = coords[3 * n + gc];
+    }
+    if (tid == 0) {
+        lmn[0] = mat[2 * e];
+        lmn[1] = mat[2 * e + 1];
+    }
+    __syncthreads();
+
+    for (;;) {
+        const int64_t en = e + stride;
+        const bool has_next = en < e_end;
+        const float lam = lmn[0], mu = lmn[1];  // read before the park step rewrites them
+
+        // 1. this cell's coordinates to LDS (component-major); the operand's
+        //    depth padding (the staging area of the last cell covered it)
+        if (tid < NB * 3) xc[gc * 28 + ga] = xn[tid];
+        if (tid < 2 * ND) {
+            __bf16 *p = ohi + (tid >= ND ? L::OROWS * L::KS : 0) + (tid >= ND ? tid - ND : tid) * L::KS;
+#pragma unroll
+            for (int k = NQ; k < L::KP; k++) p[k] = static_cast<__bf16>(0.0f);
+        }
+        __syncthreads();
+
+        // 2. J[i][j] at quadrature point q, one entry per thread (243
+        //    threads), by sum factorization over the tensor-product basis
+        if (tid < NQ * 9) {
+            const int q = tid % NQ, ij = tid / NQ, i = ij / 3, j = ij - 3 * (ij / 3);
+            const int q0 = q % 3, q1 = (q / 3) % 3, q2 = q / 9;
+            const double *T0 = (j == 0 ? D1 : B1) + q0 * 3;
+            const double *T1 = (j == 1 ? D1 : B1) + q1 * 3;
+            const double *T2 = (j == 2 ? D1 : B1) + q2 * 3;
+            const double f0[3] = {T0[0], T0[1], T0[2]}, f1[3] = {T1[0], T1[1], T1[2]},
+                         f2[3] = {T2[0], T2[1], T2[2]};
+            const double *x = xc + i * 28;
+            double s2 = 0.0;
+#pragma unroll
+            for (int a2 = 0; a2 < 3; a2++) {
+                double s1 = 0.0;
+#pragma unroll
+                for (int a1 = 0; a1 < 3; a1++) {
+                    const double *xr = x + 3 * (a1 + 3 * a2);
+                    s1 = fma(f1[a1], f0[0] * xr[0] + f0[1] * xr[1] + f0[2] * xr[2], s1);
+                }
+                s2 = fma(f2[a2], s1, s2);
+            }
+            Jq[q * 9 + i * 3 + j] = s2;
+        }
+        __syncthreads();
+
+        // 3. det J and J^-1 per quadrature point (FP64, recomputed by each
+        //    of the 9 threads of a point); then the operand halves of
+        //    Gt[27 i + a][q] = sqrt(w_q / det J) sum_j dphi_a/dxi_j adj(J)[j][i]
+        //    (= sqrt(w_q det J) G[q][i][a]), one (q, i, a2) triple per
+        //    thread, 9 basis functions each.  The next cell's connectivity
+        //    and coefficients are prefetched here, its coordinates after the
+        //    GEMM; both are parked in LDS before the flush.
+        int32_t nn = 0;
+        float lamn = 0.0f, mun = 0.0f;
+        if (has_next) {
+            if (tid < NB * 3) nn = conn[en * NB + ga];
+            if (tid == 0) {  // only the thread that parks them: a dead load would still be waited for
+                lamn = mat[2 * en];
+                mun = mat[2 * en + 1];
+            }
+        }
+        if (tid < NQ * 9) {
+            const int q = tid % NQ, r9 = tid / NQ, ci = r9 / 3, a2 = r9 - 3 * (r9 / 3);
+            const int q0 = q % 3, q1 = (q / 3) % 3, q2 = q / 9;
+            double J[3][3];
+#pragma unroll
+            for (int r = 0; r < 3; r++)
+#pragma unroll
+                for (int c = 0; c < 3; c++) J[r][c] = Jq[q * 9 + r * 3 + c];
+            // column ci of the adjugate; 1/det by the hardware reciprocal
+            // refined with two Newton steps (r <- r + r (1 - det r))
+            double adj0[3], adjc[3];
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+                adj0[j] = J[1][(j + 1) % 3] * J[2][(j + 2) % 3] - J[1][(j + 2) % 3] * J[2][(j + 1) % 3];
+                const double k1 = sel3(ci, J[1][(j + 1) % 3], J[2][(j + 1) % 3], J[0][(j + 1) % 3]);
+                const double k2 = sel3(ci, J[2][(j + 2) % 3], J[0][(j + 2) % 3], J[1][(j + 2) % 3]);
+                const double k3 = sel3(ci, J[1][(j + 2) % 3], J[2][(j + 2) % 3], J[0][(j + 2) % 3]);
+                const double k4 = sel3(ci, J[2][(j + 1) % 3], J[0][(j + 1) % 3], J[1][(j + 1) % 3]);
+                adjc[j] = k1 * k2 - k3 * k4;
+            }
+            const double det = J[0][0] * adj0[0] + J[0][1] * adj0[1] + J[0][2] * adj0[2];
+            double rd = __builtin_amdgcn_rcp(det);
+            rd = fma(rd, fma(-det, rd, 1.0), rd);
+            rd = fma(rd, fma(-det, rd, 1.0), rd);
+            if (r9 == 0 && !(det > 0.0)) raise_fault(A.flags, FAULT_DET);
+            const double sc = sqrt(wq[q] * rd);
+            const double bz = B1[q2 * 3 + a2], dz = D1[q2 * 3 + a2];
+            // G = c0 dx by bz + c1 bx dy bz + c2 bx by dz, factored over the
+            // tensor indices: dx (c0 bz by) + bx (c1 bz dy + c2 dz by)
+            const double c0z = adjc[0] * sc * bz, c1z = adjc[1] * sc * bz, c2z = adjc[2] * sc * dz;
+            const int o = (ci * NB + 9 * a2) * L::KS + q;
+#pragma unroll
+            for (int a1 = 0; a1 < 3; a1++) {
+                const double by = B1[q1 * 3 + a1], dy = D1[q1 * 3 + a1];
+                const double p0 = c0z * by, p12 = fma(c1z, dy, c2z * by);
+#pragma unroll
+                for (int a0 = 0; a0 < 3; a0++) {
+                    const double bx = B1[q0 * 3 + a0], dx = D1[q0 * 3 + a0];
+                    const double val = fma(p0, dx, p12 * bx);
+                    const int oo = o + (a0 + 3 * a1) * L::KS;
+                    const __bf16 hb = static_cast<__bf16>(static_cast<float>(val));
+                    ohi[oo] = hb;
+                    ohi[L::OROWS * L::KS + oo] =
+                        static_cast<__bf16>(static_cast<float>(val - static_cast<double>(static_cast<float>(hb))));
+                }
+            }
+        }
+        __syncthreads();
+
+        // 4. the cell's tile products on the matrix cores
+        f4 acc[7];
+        if (wave == 0)
+            split_gemm<WavePlan<0>>(op, lane, acc);
+        else if (wave == 1)
+            split_gemm<WavePlan<1>>(op, lane, acc);
+        else if (wave == 2)
+            split_gemm<WavePlan<2>>(op, lane, acc);
+        else
+            split_gemm<WavePlan<3>>(op, lane, acc);
+        __syncthreads();  // every wave is done reading the operand
+
+        // second prefetch hop: the next cell's coordinates.  The empty asm
+        // keeps the first use of the connectivity value (and so the wait for
+        // its load) here instead of next to the load.
+        double xnext = 0.0;
+        if (has_next && tid < NB * 3) {
+            asm volatile("" : "+v"(nn));
+            int64_t n = nn;
+            if (n < 0 || n >= A.n_nodes) {
+                raise_fault(A.flags, FAULT_INDEX);
+                n = 0;
+            }
+            xnext = coords[3 * n + gc];
+        }
+
+        // 5. K tiles to the staging area
+        if (wave == 0)
+            split_epilogue<WavePlan<0>>(Ks, acc, lam, mu, lane);
+        else if (wave == 1)
+            split_epilogue<WavePlan<1>>(Ks, acc, lam, mu, lane);
+        else if (wave == 2)
+            split_epilogue<WavePlan<2>>(Ks, acc, lam, mu, lane);
+        else
+            split_epilogue<WavePlan<3>>(Ks, acc, lam, mu, lane);
+        // park the prefetched next-cell data in LDS: no loaded register stays
+        // live across the flush, so nothing after the flush waits for its
+        // stores to drain (vector memory counters complete in order)
+        if (has_next) {
+            if (tid < NB * 3) xn[tid] = xnext;
+            if (tid == 0) {
+                lmn[0] = lamn;
+                lmn[1] = mun;
+            }
+        }
+        __syncthreads();
+
+        // 6. flush: consecutive lanes store consecutive 16-byte vectors of
+        //    the cell's contiguous output, gathered from the padded staging
+        //    rows (LDS reads batched ahead of the stores); the few entries
+        //    before the first and after the last whole vector go one by one
+        {
+            const int64_t base = e * NK;
+            const auto out = gmem(static_cast<float *>(A.out));
+            const int ho = static_cast<int>(base & (L::VEC - 1));  // misalignment of the cell's output
+            const auto aligned = (__attribute__((address_space(1))) TV *)(out + (base - ho));
+            const int vf = ho ? 1 : 0, vl = (NK + ho) / L::VEC;  // whole vectors [vf, vl)
+            constexpr int BATCH = 4;
+#pragma unroll
+            for (int j0 = 0; j0 < L::NV; j0 += BATCH) {
+                TV buf[BATCH];
+#pragma unroll
+                for (int j = 0; j < BATCH; j++) {
+                    const int v = vf + tid + 256 * (j0 + j);
+                    if (v < vl) {
+                        // entries f0..f0+3 sit at f + f/27: five words from
+                        // f0 + f0/27 cover them, the one after a segment end
+                        // skipped
+                        const int f0 = L::VEC * v - ho;
+                        const int d = static_cast<int>(fmaf(static_cast<float>(f0), 1.0f / 27.0f, 0.5f / 27.0f));
+                        const int m = f0 - 27 * d;
+                        const float *p = Ks + f0 + d;
+                        const float w0 = p[0], w1 = p[1], w2 = p[2], w3 = p[3], w4 = p[4];
+                        buf[j] = TV{w0, m >= 26 ? w2 : w1, m >= 25 ? w3 : w2, m >= 24 ? w4 : w3};
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < BATCH; j++) {
+                    const int v = vf + tid + 256 * (j0 + j);
+                    if (v < vl) out_store(buf[j], aligned + v);
+                }
+            }
+            if (tid < 2 * L::VEC) {
+                const int f = tid < L::VEC ? tid : vl * L::VEC - ho + (tid - L::VEC);
+                const bool head = tid < L::VEC && f < vf * L::VEC - ho;
+                const bool tail = tid >= L::VEC && f < NK;
+                if (head || tail) out[base + f] = Ks[f + f / 27];
+            }
+        }
+        __syncthreads();  // the staging area is reused by the next cell
+        if (!has_next) break;
+        e = en;
+    }
+}
+
+template <int MM>
+using Q2Layout = typename std::conditional<MM == MM_BF16X3, Q2Split, Q2Staged<MM>>::type;
+
+// Q2 cells e, e + stride, ... < e_end with one workgroup of 256 threads.
+// MULTI also emits the Laplace matrix P_00 + P_11 + P_22 (a by-product of
+// the elasticity contraction) and the scalar mass matrix (one more small
+// product on the matrix cores), sharing the geometry (FP64 and FP32 only).
+// smem must hold Q2Layout<MM>::BYTES.  Ends with the workgroup synchronised.
+template <int MM, bool MULTI>
+__device__ __forceinline__ void q2_run(const Q2Job &A, int64_t e, int64_t e_end, int64_t stride, unsigned char *smem,
+                                       int tid)
+{
+    if constexpr (MM == MM_BF16X3) {
+        static_assert(!MULTI, "the split precision has no multi-form routine");
+        q2_run_split(A, e, e_end, stride, smem, tid);
+    } else {
+        q2_run_staged<MM, MULTI>(A, e, e_end, stride, smem, tid);
     }
 }
 
