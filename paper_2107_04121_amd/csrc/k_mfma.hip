@@ -22,10 +22,11 @@
 //      the contraction type as the GEMM operand (K padded to the MFMA depth);
 //   4. the products on the matrix cores, K, and a linear flush of the cell's
 //      81x81 matrix from an LDS staging area with 16-byte stores.
-// FP64 and FP32 (staged routine): the 24 output tiles of 16x16 of the blocks
-// r <= s of P (6 per wave; v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32)
-// go to the staging area, and an in-place pass turns P into K there (every
-// thread owns fixed (a,b) positions of the 27x27 blocks).  The split
+// FP64 and FP32 (staged routine): the output tiles of 16x16 of the blocks
+// r <= s of P (21: the diagonal blocks' tiles below the diagonal are left
+// out; v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32) go to the staging
+// area, and an in-place pass turns P into K there (every thread owns fixed
+// (a,b) positions of the 27x27 blocks).  The split
 // precision BF16X3 (v_mfma_f32_16x16x32_bf16 three times per tile on the
 // hi/lo halves, FP32 accumulation) makes the products cheap, so it computes
 // P_rs for all nine (r, s) at three tile positions, forms K in registers and

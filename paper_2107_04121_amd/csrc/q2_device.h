@@ -36,7 +36,7 @@ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int NB = 27, NQ = 27, ND = 81, NK = ND * ND;
 
 // ---------------------------------------------------------------------------
-// Staged routine (FP64, FP32): the 24 tiles of the blocks r <= s of P on the
+// Staged routine (FP64, FP32): the tiles of the blocks r <= s of P on the
 // matrix cores, P to LDS, K from P in place, a linear flush.
 template <int MM>
 struct Q2Staged {
@@ -94,7 +94,8 @@ __device__ __forceinline__ void cell_range(int remap, int64_t n, int64_t &first,
 
 // 6x6 grid of 16x16 output tiles; block (r,s) = tiles 2r..2r+1 x 2s..2s+1.
 // The 24 tiles of blocks r <= s are split in 2-D rectangles, 6 per wave, so
-// each wave loads few distinct operand fragments per k step:
+// each wave loads few distinct operand fragments per k step (three of them
+// are then left out, see skipped_tile):
 //   wave 0: rows {0,1} x cols {0,1,2}   wave 1: rows {0,1} x cols {3,4,5}
 //   wave 2: rows {2,3} x cols {2,3,4}   wave 3: rows {2,3} x {5}, {4,5} x {4,5}
 // Wave w < 3 uses A rows AR[w][0..1], B cols BC[w][0..2], tile t = (t/3, t%3).
@@ -114,12 +115,19 @@ __device__ __forceinline__ void tile_of(int wave, int t, int &TM, int &TN)
     }
 }
 
+// The tile (1,0) of a diagonal block lies below its diagonal, where the
+// in-place pass reads nothing (it writes both triangles from the upper
+// one): waves 0, 2 and 3 leave theirs out (tile index 3, 3, 4), 21 tiles in
+// all.
+__host__ __device__ constexpr int skipped_tile(int wave) { return wave == 1 ? -1 : (wave == 3 ? 4 : 3); }
+
 __device__ __forceinline__ int blk_id(int r, int s)  // r <= s
 {
     return r == 0 ? s : (r == 1 ? 2 + s : 5);
 }
 
-template <int MM, int NA, int NBF>
+// SKIP: a tile the wave leaves out (-1: none)
+template <int MM, int NA, int NBF, int SKIP>
 __device__ __forceinline__ void mma_rect(const typename MMT<MM>::T *Gs, const double *wd, const int (&ar)[NA],
                                          const int (&bc)[NBF], const int (&ta)[6], const int (&tb)[6], int lane,
                                          typename MMT<MM>::acc (&acc)[6])
@@ -147,6 +155,7 @@ __device__ __forceinline__ void mma_rect(const typename MMT<MM>::T *Gs, const do
         for (int j = 0; j < NBF; j++) b[j] = Gs[rb[j] + k];
 #pragma unroll
         for (int t = 0; t < 6; t++) {
+            if (t == SKIP) continue;
             if constexpr (MM == MM_F64)
                 acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta[t]], b[tb[t]], acc[t], 0, 0, 0);
             else
@@ -159,16 +168,18 @@ template <int MM>
 __device__ __forceinline__ void mma_wave(const typename MMT<MM>::T *Gs, const double *wd, int wave, int lane,
                                          typename MMT<MM>::acc (&acc)[6])
 {
-    if (wave < 3) {
+    const int ta[6] = {0, 0, 0, 1, 1, 1}, tb[6] = {0, 1, 2, 0, 1, 2};
+    if (wave == 1) {
+        const int ar[2] = {0, 1}, bc[3] = {3, 4, 5};
+        mma_rect<MM, 2, 3, -1>(Gs, wd, ar, bc, ta, tb, lane, acc);
+    } else if (wave != 3) {
         const int r0 = wave == 2 ? 2 : 0;
-        const int c0 = wave == 0 ? 0 : (wave == 1 ? 3 : 2);
-        const int ar[2] = {r0, r0 + 1}, bc[3] = {c0, c0 + 1, c0 + 2};
-        const int ta[6] = {0, 0, 0, 1, 1, 1}, tb[6] = {0, 1, 2, 0, 1, 2};
-        mma_rect<MM, 2, 3>(Gs, wd, ar, bc, ta, tb, lane, acc);
+        const int ar[2] = {r0, r0 + 1}, bc[3] = {r0, r0 + 1, r0 + 2};
+        mma_rect<MM, 2, 3, skipped_tile(0)>(Gs, wd, ar, bc, ta, tb, lane, acc);
     } else {
         const int ar[4] = {2, 3, 4, 5}, bc[2] = {4, 5};
-        const int ta[6] = {0, 1, 2, 2, 3, 3}, tb[6] = {1, 1, 0, 1, 0, 1};
-        mma_rect<MM, 4, 2>(Gs, wd, ar, bc, ta, tb, lane, acc);
+        const int ta3[6] = {0, 1, 2, 2, 3, 3}, tb3[6] = {1, 1, 0, 1, 0, 1};
+        mma_rect<MM, 4, 2, skipped_tile(3)>(Gs, wd, ar, bc, ta3, tb3, lane, acc);
     }
 }
 
@@ -258,7 +269,8 @@ __device__ __forceinline__ void q2_run_staged(const Q2Job &A, int64_t e, int64_t
     double *wd = reinterpret_cast<double *>(smem + L::OFF_WD);
     T *Gs = reinterpret_cast<T *>(smem + L::OFF_G);
     T *Ks = reinterpret_cast<T *>(smem + L::OFF_K);
-    const int wave = tid >> 6, lane = tid & 63;
+    // wave-uniform, and known to be so (scalar branches below)
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     if (e >= e_end) return;  // uniform over the workgroup
 
     if (tid < 9) {
@@ -443,6 +455,7 @@ __device__ __forceinline__ void q2_run_staged(const Q2Job &A, int64_t e, int64_t
         const int h = static_cast<int>(base & (L::VEC - 1));
 #pragma unroll
         for (int t = 0; t < 6; t++) {
+            if (t == skipped_tile(wave)) continue;
             int TM, TN;
             tile_of(wave, t, TM, TN);
             const int r = TM >> 1, s = TN >> 1;
