@@ -54,11 +54,11 @@ struct Q2Staged {
     static constexpr int OFF_J = OFF_X + 3 * 28 * 8;      // double J[27][9]
     static constexpr int OFF_WD = OFF_J + NQ * 9 * 8;     // double wd[28]
     // GEMM operand, transposed: row = i*33 + a (component i, basis a; rows
-    // a = 27..32 are zero padding), column = quadrature point k, odd row
-    // stride KS.  Lanes of one MFMA fragment read 16 consecutive rows at
-    // fixed k and the geometry threads write one row entry per quadrature
-    // point, so both spread over the LDS banks.
-    static constexpr int KS = KP + 1;
+    // a = 27..32 are padding), column = quadrature point k, row stride KS.
+    // Lanes of one MFMA fragment read 16 consecutive rows at four
+    // consecutive k: with 32 four-byte LDS banks that is conflict-free for
+    // an odd stride in FP64 and a stride of 2 mod 4 in FP32.
+    static constexpr int KS = MM == MM_F64 ? KP + 1 : KP + 2;
     static constexpr int GROWS = 3 * 33;
     static constexpr int OFF_G = align16(OFF_WD + 28 * 8);  // T Gs[GROWS][KS]
     static constexpr int END_A = OFF_G + GROWS * KS * (int)sizeof(T);
@@ -306,20 +306,15 @@ __device__ __forceinline__ void q2_run_staged(const Q2Job &A, int64_t e, int64_t
         const T lam = lmn[0], mu = lmn[1];  // read before the park step rewrites them
 
         // 1. this cell's coordinates to LDS (component-major); zero the
-        //    GEMM operand; prefetch the next cell's connectivity
-        if (tid < NB * 3) xc[gc * 28 + ga] = xn[tid];
-        if (tid == 255) wd[NQ] = 0.0;
-        // zero the operand padding: rows a = 27..32 of each component, and
-        // columns k = 27..KP-1 of the real rows
-        for (int i = tid; i < 3 * 6 * L::KS + 3 * NB * (L::KP - NQ); i += 256) {
-            if (i < 3 * 6 * L::KS) {
-                const int c = i / (6 * L::KS), rem = i - c * 6 * L::KS;
-                Gs[(c * 33 + NB) * L::KS + rem] = T(0);
-            } else {
-                const int j = i - 3 * 6 * L::KS, row = j / (L::KP - NQ), k = NQ + j % (L::KP - NQ);
-                Gs[((row / NB) * 33 + row % NB) * L::KS + k] = T(0);
-            }
+        //    operand's depth padding (k = 27) in the real rows.  The padding
+        //    rows a = 27..32 keep what the staging area left there: they
+        //    only reach output rows and columns that are never stored.
+        static_assert(L::KP == NQ + 1, "one padding column");
+        if (tid < NB * 3) {
+            xc[gc * 28 + ga] = xn[tid];
+            Gs[((tid / NB) * 33 + tid % NB) * L::KS + NQ] = T(0);
         }
+        if (tid == 255) wd[NQ] = 0.0;
         __syncthreads();
 
         // 2. J[i][j] at quadrature point q, one entry per thread (243
