@@ -905,10 +905,12 @@ __device__ __forceinline__ void q2_run_split(const Q2Job &A, int64_t e, int64_t 
                     const double bx = B1[q0 * 3 + a0], dx = D1[q0 * 3 + a0];
                     const double val = fma(p0, dx, p12 * bx);
                     const int oo = o + (a0 + 3 * a1) * L::KS;
-                    const __bf16 hb = static_cast<__bf16>(static_cast<float>(val));
+                    // hi = bf16(x), lo = bf16(x - hi) of x = fl32(val): the
+                    // residual is exact in FP32, and hi + lo carries 16 bits
+                    const float x = static_cast<float>(val);
+                    const __bf16 hb = static_cast<__bf16>(x);
                     ohi[oo] = hb;
-                    ohi[L::OROWS * L::KS + oo] =
-                        static_cast<__bf16>(static_cast<float>(val - static_cast<double>(static_cast<float>(hb))));
+                    ohi[L::OROWS * L::KS + oo] = static_cast<__bf16>(x - static_cast<float>(hb));
                 }
             }
         }
