@@ -81,7 +81,13 @@ struct SmallMM {
     static constexpr int OFF_G = align16(OFF_WD + CPP * NQP * 8);                // T G[CPP][CR]
     static constexpr int OFF_P = OFF_G;                                          // T P[CPP][CR]
     static constexpr int OFF_M = align16(OFF_P + CPP * CR * (int)sizeof(T));     // T M[CPP][NB][MS]
-    static constexpr int BYTES = align16(OFF_M + CPP * NB * MS * (int)sizeof(T));
+    // the group's reference tables, copied once per work item: without them
+    // the geometry and the products waited on global loads, and a wave's
+    // loads complete only after its earlier stores (the previous pass's
+    // outputs)
+    static constexpr int TAB = NB * 3 * NQ + NQ * NB + NQ;                      // bfgT, bf, w
+    static constexpr int OFF_TAB = align16(OFF_M + CPP * NB * MS * (int)sizeof(T));  // double tab[TAB]
+    static constexpr int BYTES = align16(OFF_TAB + TAB * 8);
 };
 
 template <typename T>
@@ -142,6 +148,8 @@ __device__ void small_pass(const GroupDev &g, int64_t e0, int n, int buf, int64_
     T *Gs = reinterpret_cast<T *>(smem + L::OFF_G);
     T *Ps = reinterpret_cast<T *>(smem + L::OFF_P);
     T *Ms = reinterpret_cast<T *>(smem + L::OFF_M);
+    const double *bfgT = reinterpret_cast<const double *>(smem + L::OFF_TAB);
+    const double *bf = bfgT + NB * 3 * NQ, *wq = bf + NQ * NB;
     const bool want_el = g.forms & FORM_BIT_ELAST;
     unsigned fault = 0;
 
@@ -179,7 +187,7 @@ __device__ void small_pass(const GroupDev &g, int64_t e0, int n, int buf, int64_
             const double x0 = x[a * 3], x1 = x[a * 3 + 1], x2 = x[a * 3 + 2];
 #pragma unroll
             for (int j = 0; j < 3; j++) {
-                const double gr = gmem(g.tab.bfgT)[(a * 3 + j) * NQ + q];
+                const double gr = bfgT[(a * 3 + j) * NQ + q];
                 J[0][j] = fma(x0, gr, J[0][j]);
                 J[1][j] = fma(x1, gr, J[1][j]);
                 J[2][j] = fma(x2, gr, J[2][j]);
@@ -189,12 +197,12 @@ __device__ void small_pass(const GroupDev &g, int64_t e0, int n, int buf, int64_
         const double det = inverse3(J, Ji);
         const bool live = c < n;
         if (live && !(det > 0.0)) fault |= FAULT_DET;
-        wd[c * NQP + q] = live ? gmem(g.tab.w)[q] * det : 0.0;
+        wd[c * NQP + q] = live ? wq[q] * det : 0.0;
         T *G = Gs + c * L::CR + q;
 #pragma unroll
         for (int a = 0; a < NB; a++) {
-            const double r0 = gmem(g.tab.bfgT)[(a * 3 + 0) * NQ + q], r1 = gmem(g.tab.bfgT)[(a * 3 + 1) * NQ + q],
-                         r2 = gmem(g.tab.bfgT)[(a * 3 + 2) * NQ + q];
+            const double r0 = bfgT[(a * 3 + 0) * NQ + q], r1 = bfgT[(a * 3 + 1) * NQ + q],
+                         r2 = bfgT[(a * 3 + 2) * NQ + q];
 #pragma unroll
             for (int i = 0; i < 3; i++)
                 G[(i * NB + a) * KS] = live ? static_cast<T>(r0 * Ji[0][i] + r1 * Ji[1][i] + r2 * Ji[2][i]) : T(0);
@@ -248,7 +256,7 @@ __device__ void small_pass(const GroupDev &g, int64_t e0, int n, int buf, int64_
                 for (int i = 0; i < NT; i++)
 #pragma unroll
                     for (int j = 0; j < NT; j++) mma4<T>(a[i], b[j], acc[i][j]);
-                const T phi = (col < NB && q < NQ) ? static_cast<T>(gmem(g.tab.bf)[q * NB + col]) : T(0);
+                const T phi = (col < NB && q < NQ) ? static_cast<T>(bf[q * NB + col]) : T(0);
                 mma4<T>(phi * w, phi, am);
             }
             // accumulator layout: column = lane % 16; FP32 rows 4*(lane/16)+v,
@@ -284,58 +292,96 @@ __device__ void small_pass(const GroupDev &g, int64_t e0, int n, int buf, int64_
     __syncthreads();
 
     // 4. outputs of the pass's n contiguous cells.  The rows of all n cells
-    //    are contiguous in each output; a sweep covers RPS whole rows with
-    //    one thread per entry, so a thread keeps its column (and the block
-    //    indices derived from it) and only steps its row and cell, and the
-    //    stores of a sweep are one contiguous run.
+    //    are contiguous in each output; a sweep covers RPS whole rows, a
+    //    thread W adjacent columns (in one block: W divides nb) of one row
+    //    per step with one W-wide store, so the stores of a sweep are one
+    //    contiguous run.  A thread keeps its columns (and the block indices
+    //    derived from them) and steps its row and cell: its LDS indices move
+    //    by constant strides, corrected by selects at a block row and at a
+    //    cell boundary, and the other columns' entries sit in the next words.
+    //    Index work per entry is what bounds these loops, hence the column
+    //    groups and the strides.
+    constexpr int W = NB % 4 == 0 ? 4 : 2;
+    static_assert(NB % W == 0, "column groups stay within a block");
+    typedef T TW __attribute__((ext_vector_type(W)));
     if (want_el) {
-        constexpr int RPS = 256 / ND;
-        if (tid < RPS * ND) {
-            const int col = tid % ND, s = col / NB, b = col - s * NB;
-            int row = (tid / ND) % ND, c = tid / (ND * ND);
-            auto out = gmem(static_cast<T *>(g.out_el)) + e0 * (ND * ND) + tid;
+        constexpr int HP = ND / W;  // column groups per row
+        constexpr int RPS = 256 / HP, CS = RPS / ND, RR = RPS % ND, QS = RR / NB, MR = RR % NB;
+        if (tid < RPS * HP) {
+            const int col = W * (tid % HP), s = col / NB, b = col - s * NB;
+            const int row = (tid / HP) % ND;
+            int c = tid / (HP * ND), r = row / NB, a = row - r * NB;
+            // P[(r,a),(s,b)], P[(s,a),(r,b)] and P_00[a][b] of cell c
+            int i1 = c * L::CR + row * PS + col, i2 = c * L::CR + (s * NB + a) * PS + r * NB + b;
+            int id = c * L::CR + a * PS + b;
+            auto out = reinterpret_cast<__attribute__((address_space(1))) TW *>(
+                gmem(static_cast<T *>(g.out_el)) + e0 * (ND * ND) + (tid / HP) * ND + col);
 #pragma unroll 2
-            for (int rr = tid / ND; rr < n * ND; rr += RPS) {
-                const int r = row / NB, a = row - r * NB;
-                const T *Pc = Ps + c * L::CR;
+            for (int rr = tid / HP; rr < n * ND; rr += RPS) {
                 const T lam = lm[2 * c], mu = lm[2 * c + 1];
-                T v = lam * Pc[row * PS + col] + mu * Pc[(s * NB + a) * PS + r * NB + b];
-                if (r == s) v += mu * (Pc[a * PS + b] + Pc[(NB + a) * PS + NB + b] + Pc[(2 * NB + a) * PS + 2 * NB + b]);
+                const T md = r == s ? mu : T(0);  // diagonal blocks only
+                TW v;
+#pragma unroll
+                for (int j = 0; j < W; j++)
+                    v[j] = lam * Ps[i1 + j] + mu * Ps[i2 + j] +
+                           md * (Ps[id + j] + Ps[id + NB * PS + NB + j] + Ps[id + 2 * NB * PS + 2 * NB + j]);
                 q2::out_store(v, out);
-                out += RPS * ND;
-                row += RPS % ND;
-                c += RPS / ND;
-                if (row >= ND) {
-                    row -= ND;
-                    c++;
-                }
+                out += RPS * HP;
+                a += MR;
+                r += QS;
+                c += CS;
+                i1 += CS * L::CR + RR * PS;
+                i2 += CS * L::CR + MR * PS + QS * NB;
+                id += CS * L::CR + MR * PS;
+                const bool wa = a >= NB;  // next block row
+                a = wa ? a - NB : a;
+                r = wa ? r + 1 : r;
+                i2 = wa ? i2 + NB - NB * PS : i2;
+                id = wa ? id - NB * PS : id;
+                const bool wc = r >= 3;  // next cell
+                r = wc ? r - 3 : r;
+                c = wc ? c + 1 : c;
+                i1 = wc ? i1 + L::CR - ND * PS : i1;
+                i2 = wc ? i2 + L::CR - 3 * NB : i2;
+                id = wc ? id + L::CR : id;
             }
         }
     }
-    constexpr int RPB = 256 / NB;  // rows per sweep of the nb x nb outputs
-    if ((g.forms & (FORM_BIT_LAPLACE | FORM_BIT_MASS)) && tid < RPB * NB) {
-        const int b = tid % NB;
+    constexpr int HB = NB / W, RPB = 256 / HB;  // column groups and rows per sweep of the nb x nb outputs
+    constexpr int QB = RPB / NB, MB = RPB % NB;
+    if ((g.forms & (FORM_BIT_LAPLACE | FORM_BIT_MASS)) && tid < RPB * HB) {
+        const int b = W * (tid % HB);
         const bool lap = g.forms & FORM_BIT_LAPLACE, mass = g.forms & FORM_BIT_MASS;
-        int a = (tid / NB) % NB, c = tid / (NB * NB);
-        auto ol = gmem(lap ? static_cast<T *>(g.out_lap) + e0 * (NB * NB) + tid : nullptr);
-        auto om = gmem(mass ? static_cast<T *>(g.out_mass) + e0 * (NB * NB) + tid : nullptr);
+        int a = (tid / HB) % NB, c = tid / (HB * NB);
+        int il = c * L::CR + a * PS + b;  // P_00[a][b] of cell c
+        const T *mp = Ms + (c * NB + a) * MS + b;
+        const int o = (tid / HB) * NB + b;
+        auto ol = reinterpret_cast<__attribute__((address_space(1))) TW *>(
+            gmem(lap ? static_cast<T *>(g.out_lap) + e0 * (NB * NB) + o : nullptr));
+        auto om = reinterpret_cast<__attribute__((address_space(1))) TW *>(
+            gmem(mass ? static_cast<T *>(g.out_mass) + e0 * (NB * NB) + o : nullptr));
 #pragma unroll 2
-        for (int rr = tid / NB; rr < n * NB; rr += RPB) {
+        for (int rr = tid / HB; rr < n * NB; rr += RPB) {
             if (lap) {
-                const T *Pc = Ps + c * L::CR;
-                q2::out_store(Pc[a * PS + b] + Pc[(NB + a) * PS + NB + b] + Pc[(2 * NB + a) * PS + 2 * NB + b], ol);
-                ol += RPB * NB;
+                TW v;
+#pragma unroll
+                for (int j = 0; j < W; j++) v[j] = Ps[il + j] + Ps[il + NB * PS + NB + j] + Ps[il + 2 * NB * PS + 2 * NB + j];
+                q2::out_store(v, ol);
+                ol += RPB * HB;
             }
             if (mass) {
-                q2::out_store(Ms[(c * NB + a) * MS + b], om);
-                om += RPB * NB;
+                TW v;
+#pragma unroll
+                for (int j = 0; j < W; j++) v[j] = mp[j];
+                q2::out_store(v, om);
+                om += RPB * HB;
             }
-            a += RPB % NB;
-            c += RPB / NB;
-            if (a >= NB) {
-                a -= NB;
-                c++;
-            }
+            mp += RPB * MS;
+            a += MB;
+            il += MB * PS + QB * L::CR;
+            const bool wc = a >= NB;  // next cell
+            a = wc ? a - NB : a;
+            il = wc ? il + L::CR - NB * PS : il;
         }
     }
     if (fault) raise_fault(flags, fault);
@@ -346,9 +392,14 @@ template <int CELL, int P, typename T>
 __device__ void small_tile(const GroupDev &g, int64_t c0, int64_t c1, unsigned *flags, unsigned char *smem, int tid)
 {
     using L = SmallMM<CELL, P, T>;
-    constexpr int CPP = L::CPP;
+    constexpr int CPP = L::CPP, NB = L::NB, NQ = L::NQ;
     if (c0 >= c1) return;
     {
+        double *tab = reinterpret_cast<double *>(smem + L::OFF_TAB);
+        for (int t = tid; t < L::TAB; t += 256)
+            tab[t] = t < NB * 3 * NQ ? gmem(g.tab.bfgT)[t]
+                     : (t < NB * 3 * NQ + NQ * NB ? gmem(g.tab.bf)[t - NB * 3 * NQ]
+                                                  : gmem(g.tab.w)[t - NB * 3 * NQ - NQ * NB]);
         const int n0 = c1 - c0 < CPP ? int(c1 - c0) : CPP;
         const unsigned f = small_gather<CELL, P, T>(g, c0, n0, reinterpret_cast<double *>(smem + L::OFF_X),
                                                     reinterpret_cast<T *>(smem + L::OFF_LM), tid);
