@@ -232,11 +232,49 @@ __global__ __launch_bounds__(GM_THREADS, (2 * HexGM<P, FORM, MM>::MINB)) void k_
         Ph[k] = static_cast<T>(v);
     }
 
-    for (; e < e_end; e += stride) {
-        gm_gather<H>(A, e, xs, us, Ms, tid);
-        __syncthreads();
+    // The next cell's data is prefetched in two hops and parked in xs / us /
+    // Ms (free once gm_points is done) before this cell's stores: a wave's
+    // loads complete only after its earlier stores, so a load issued after
+    // the stores (the gather at the top of the next cell) would wait for
+    // all of them.
+    gm_gather<H>(A, e, xs, us, Ms, tid);
+    __syncthreads();
+    const T *mat = static_cast<const T *>(A.mat);
+    const T *Ug = static_cast<const T *>(A.dofs);
+    for (;;) {
+        const int64_t en = e + stride;
+        const bool has_next = en < e_end;
+        // first hop: the next cell's connectivity (thread k < 3 nb: node k/3,
+        // axis k%3) and its per-point M (weighted dot)
+        constexpr int PM = (NQ * 9 + GM_THREADS - 1) / GM_THREADS;  // M entries per thread
+        static_assert(3 * NB <= GM_THREADS, "one coordinate per thread");
+        int32_t pn = 0;
+        T pm[PM] = {};
+        if (has_next) {
+            if (tid < 3 * NB) pn = A.conn[en * NB + tid / 3];
+            if constexpr (!CONV) {
+#pragma unroll
+                for (int k = 0; k < PM; k++)
+                    if (tid + k * GM_THREADS < NQ * 9) pm[k] = mat[en * NQ * 9 + tid + k * GM_THREADS];
+            }
+        }
         gm_points<H>(A, B1, D1, wq, xs, us, Ms, F, Pq, tid);
         __syncthreads();  // F (in W's space) is read for the last time in gm_points
+        // second hop: its coordinates (and DOFs); the empty asm keeps the
+        // wait for the connectivity here
+        double px = 0.0;
+        T pu = T(0);
+        if (has_next && tid < 3 * NB) {
+            asm volatile("" : "+v"(pn));
+            int64_t n = pn;
+            if (n < 0 || n >= A.n_nodes) {
+                raise_fault(A.flags, FAULT_INDEX);
+                n = 0;
+            }
+            const int c = tid - 3 * (tid / 3);
+            px = A.coords[3 * n + c];
+            if constexpr (CONV) pu = Ug[n * 3 + c];
+        }
 
         T *oc = static_cast<T *>(A.out) + e * static_cast<int64_t>(H::ND) * H::ND;
         for (int g = 0; g < H::NGRP; g++) {
@@ -307,6 +345,18 @@ __global__ __launch_bounds__(GM_THREADS, (2 * HexGM<P, FORM, MM>::MINB)) void k_
                 mfma((k >> 2) & 1);
                 __builtin_amdgcn_sched_barrier(0);
             }
+            if (g == 0 && has_next) {  // park the prefetched cell before the first stores
+                if (tid < 3 * NB) {
+                    const int a = tid / 3, c = tid - 3 * a;
+                    xs[c * NB + a] = px;
+                    if constexpr (CONV) us[c * NB + a] = static_cast<double>(pu);
+                }
+                if constexpr (!CONV) {
+#pragma unroll
+                    for (int k = 0; k < PM; k++)
+                        if (tid + k * GM_THREADS < NQ * 9) Ms[tid + k * GM_THREADS] = static_cast<double>(pm[k]);
+                }
+            }
 #pragma unroll
             for (int u = 0; u < NJ; u++) {
                 const int t = wave + GM_WAVES * u;
@@ -318,6 +368,8 @@ __global__ __launch_bounds__(GM_THREADS, (2 * HexGM<P, FORM, MM>::MINB)) void k_
             }
             __syncthreads();  // W is rebuilt by the next group or cell
         }
+        if (!has_next) break;
+        e = en;
     }
 }
 

@@ -186,3 +186,38 @@ def test_batch_empty_and_single_cell_groups(orc, prec):
             mat, kind = (lm, "iso_cell") if form == "elasticity" else (None, None)
             err = _err(out[form].cpu().numpy(), orc.matrix(m, form, mat, kind))
             assert err < TOL[prec], (m.cell, m.order, form, err)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("tile", [None, 24])
+def test_batch_partial_passes(orc, prec, tile):
+    """The low-order passes take 8 P2 tetrahedra or 8/16 Q1 hexahedra at a
+    time, and their output loops write groups of adjacent columns while
+    stepping rows and cells by constant strides.  Cell counts that leave a
+    partial last pass (108 P2 tets, 45 Q1 hexahedra; with tile 24 also a
+    partial pass in every item) and every form, against the oracle."""
+    import torch
+    import paper_2107_04121_amd as fe
+    dt = {"fp64": torch.float64, "fp32": torch.float32}[prec]
+    meshes = [("tet", 2, meshgen.tet_mesh((3, 3, 2), 2, alpha=0.15, seed=31)),
+              ("hex", 1, meshgen.hex_mesh((5, 3, 3), 1, alpha=0.15, seed=32))]
+    groups, refs = [], []
+    for k, (cell, p, m) in enumerate(meshes):
+        lm = meshgen.lame_cell(m.n_cells, seed=40 + k)
+        g = dict(cell=cell, order=p, coords=_t(m.coords), conn=_t(m.conn), material=_t(lm, dt),
+                 forms=("mass", "laplace", "elasticity"))
+        if tile:
+            g["tile"] = tile
+        groups.append(g)
+        refs.append((m, lm))
+    assert [m.n_cells for _, _, m in meshes] == [108, 45]
+    b = fe.Batch(groups, precision=prec, autotune=False)
+    print(f"[batch-partial] {prec} tiles={b.tiles}", flush=True)
+    outs = b.run()
+    b.check()
+    for (m, lm), o in zip(refs, outs):
+        for form in ("mass", "laplace", "elasticity"):
+            mat, kind = (lm, "iso_cell") if form == "elasticity" else (None, None)
+            err = _err(o[form].cpu().numpy(), orc.matrix(m, form, mat, kind))
+            print(f"[batch-partial] {m.cell}{m.order} {form} {err:.2e}", flush=True)
+            assert err < TOL[prec], (m.cell, m.order, form, err)
