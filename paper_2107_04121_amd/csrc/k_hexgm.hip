@@ -79,6 +79,13 @@ struct HexGM {
     static constexpr int W_BYTES = G * NBP * KS * (int)sizeof(T);
     static constexpr int F_BYTES = NF * NQ * 8;
     static constexpr int BYTES = q2::align16(OFF_W + (W_BYTES > F_BYTES ? W_BYTES : F_BYTES));
+    // all nine blocks in one group (Q2): the cell's matrix is staged in W's
+    // space after the products and leaves in linear 16-byte stores (its
+    // 81-entry rows straddle 128-byte lines, so tile stores would write
+    // partial lines)
+    static constexpr int VEC = 16 / (int)sizeof(T);
+    static constexpr bool STAGE = G == 9;
+    static_assert(!STAGE || (ND * ND + VEC) * (int)sizeof(T) <= W_BYTES, "staging fits in W");
     // workgroups per CU the LDS allows (the launch bound asks for 2 MINB
     // waves per SIMD: 8 waves per workgroup over 4 SIMDs)
     static constexpr int MINB = P <= 2 ? 2 : 1;
@@ -183,6 +190,65 @@ __device__ __forceinline__ void gm_points(const ExecArgs &A, const double *B1, c
 #pragma unroll
             for (int rs = 0; rs < 9; rs++) pq[rs] = wd * Ms[q * 9 + rs];
         }
+    }
+}
+
+template <int MM>
+__device__ __forceinline__ typename MMT<MM>::acc gm_mma(typename MMT<MM>::T a, typename MMT<MM>::T b,
+                                                      const typename MMT<MM>::acc &c)
+{
+    if constexpr (MM == MM_F64)
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Q2 (nine blocks of 2x2 tiles, 36 tiles): wave w takes the four tiles of
+// block w (u = 0..3: ti = u % 2, tj = u / 2) and waves 0-3 also tile
+// (w % 2, w / 2) of block 8 (u = 4).  The Phi fragments (rows ti) are the
+// same for every block, so a wave loads two of them and two or three W
+// fragments per depth step instead of one pair per tile.
+__device__ __forceinline__ void gm_q2_tile(int wave, int u, int &bl, int &ti, int &tj)
+{
+    bl = u < 4 ? wave : 8;
+    ti = u < 4 ? (u & 1) : (wave & 1);
+    tj = u < 4 ? (u >> 1) : (wave >> 1);
+}
+
+template <class H>
+__device__ __forceinline__ void gm_q2_products(const typename H::T *Ph, const typename H::T *W, int wave, int m,
+                                               int grp, typename H::ACC (&acc)[5])
+{
+    using T = typename H::T;
+    constexpr int KS = H::KS, KP = H::KP, NBP = H::NBP, MM = sizeof(T) == 8 ? MM_F64 : MM_F32;
+    static_assert(H::NT == 2 && H::G == 9 && H::NJ == 5, "Q2 tile plan");
+    const bool extra = wave < 4, odd = wave & 1;  // wave-uniform
+    const T *pa = Ph + m * KS + grp;
+    const T *pb = W + (wave * NBP + m) * KS + grp;
+    const T *pe = W + (8 * NBP + 16 * (wave >> 1) + m) * KS + grp;
+    T a0[2], a1[2], b0[2], b1[2], be[2];
+    auto load = [&](int buf, int k) {
+        a0[buf] = pa[k];
+        a1[buf] = pa[16 * KS + k];
+        b0[buf] = pb[k];
+        b1[buf] = pb[16 * KS + k];
+        if (extra) be[buf] = pe[k];
+    };
+    auto mfma = [&](int buf) {
+        acc[0] = gm_mma<MM>(a0[buf], b0[buf], acc[0]);
+        acc[1] = gm_mma<MM>(a1[buf], b0[buf], acc[1]);
+        acc[2] = gm_mma<MM>(a0[buf], b1[buf], acc[2]);
+        acc[3] = gm_mma<MM>(a1[buf], b1[buf], acc[3]);
+        if (extra) acc[4] = gm_mma<MM>(odd ? a1[buf] : a0[buf], be[buf], acc[4]);
+    };
+    // fragments of step k + 4 are loaded while step k multiplies
+    load(0, 0);
+#pragma unroll
+    for (int k = 0; k < KP; k += 4) {
+        if (k + 4 < KP) load(((k >> 2) + 1) & 1, k + 4);
+        __builtin_amdgcn_sched_barrier(0);
+        mfma((k >> 2) & 1);
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -306,44 +372,44 @@ __global__ __launch_bounds__(GM_THREADS, (2 * HexGM<P, FORM, MM>::MINB)) void k_
 
             // 3b. this wave's tiles t = wave + 8 u of the group: block bl,
             //     tile (ti, tj); slots past the last tile multiply tile 0
-            //     and are not stored
+            //     and are not stored (Q2: see gm_q2_products)
             ACC acc[NJ];
-            int ra[NJ], rb[NJ];
 #pragma unroll
-            for (int u = 0; u < NJ; u++) {
-                acc[u] = ACC{};
-                const int t = wave + GM_WAVES * u, tt = t < H::NTILE ? t : 0;
-                const int bl = tt / (NT * NT), rem = tt - bl * (NT * NT), ti = rem / NT, tj = rem - ti * NT;
-                ra[u] = 16 * ti;
-                rb[u] = bl * NBP + 16 * tj;
-            }
-            // fragments of step k + 4 are loaded while step k multiplies
-            // (the scheduling barriers keep the compiler from hoisting the
-            // loads of every step ahead of the products)
-            T a[2][NJ], b[2][NJ];
-            auto load = [&](int buf, int k) {
+            for (int u = 0; u < NJ; u++) acc[u] = ACC{};
+            if constexpr (H::STAGE) {
+                gm_q2_products<H>(Ph, W, wave, m, grp, acc);
+            } else {
+                int ra[NJ], rb[NJ];
 #pragma unroll
                 for (int u = 0; u < NJ; u++) {
-                    a[buf][u] = Ph[(ra[u] + m) * KS + k + grp];
-                    b[buf][u] = W[(rb[u] + m) * KS + k + grp];
+                    const int t = wave + GM_WAVES * u, tt = t < H::NTILE ? t : 0;
+                    const int bl = tt / (NT * NT), rem = tt - bl * (NT * NT), ti = rem / NT, tj = rem - ti * NT;
+                    ra[u] = 16 * ti;
+                    rb[u] = bl * NBP + 16 * tj;
                 }
-            };
-            auto mfma = [&](int buf) {
+                // fragments of step k + 4 are loaded while step k multiplies
+                // (the scheduling barriers keep the compiler from hoisting the
+                // loads of every step ahead of the products)
+                T a[2][NJ], b[2][NJ];
+                auto load = [&](int buf, int k) {
 #pragma unroll
-                for (int u = 0; u < NJ; u++) {
-                    if constexpr (MM == MM_F64)
-                        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[buf][u], b[buf][u], acc[u], 0, 0, 0);
-                    else
-                        acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[buf][u], b[buf][u], acc[u], 0, 0, 0);
+                    for (int u = 0; u < NJ; u++) {
+                        a[buf][u] = Ph[(ra[u] + m) * KS + k + grp];
+                        b[buf][u] = W[(rb[u] + m) * KS + k + grp];
+                    }
+                };
+                auto mfma = [&](int buf) {
+#pragma unroll
+                    for (int u = 0; u < NJ; u++) acc[u] = gm_mma<MM>(a[buf][u], b[buf][u], acc[u]);
+                };
+                load(0, 0);
+#pragma unroll
+                for (int k = 0; k < KP; k += 4) {
+                    if (k + 4 < KP) load(((k >> 2) + 1) & 1, k + 4);
+                    __builtin_amdgcn_sched_barrier(0);
+                    mfma((k >> 2) & 1);
+                    __builtin_amdgcn_sched_barrier(0);
                 }
-            };
-            load(0, 0);
-#pragma unroll
-            for (int k = 0; k < KP; k += 4) {
-                if (k + 4 < KP) load(((k >> 2) + 1) & 1, k + 4);
-                __builtin_amdgcn_sched_barrier(0);
-                mfma((k >> 2) & 1);
-                __builtin_amdgcn_sched_barrier(0);
             }
             if (g == 0 && has_next) {  // park the prefetched cell before the first stores
                 if (tid < 3 * NB) {
@@ -357,13 +423,70 @@ __global__ __launch_bounds__(GM_THREADS, (2 * HexGM<P, FORM, MM>::MINB)) void k_
                         if (tid + k * GM_THREADS < NQ * 9) Ms[tid + k * GM_THREADS] = static_cast<double>(pm[k]);
                 }
             }
+            if constexpr (H::STAGE) {
+                // the cell's matrix row-major in W's space, shifted by h
+                // entries so that LDS vectors line up with 16-byte aligned
+                // output addresses (h from the address itself: the output
+                // need only be aligned to its element size); then linear
+                // 16-byte nontemporal stores
+                const int64_t base = e * static_cast<int64_t>(H::ND) * H::ND;
+                const int h = static_cast<int>(
+                    (reinterpret_cast<uintptr_t>(static_cast<T *>(A.out) + base) / sizeof(T)) & (H::VEC - 1));
+                T *Ks = W;
+                __syncthreads();  // every wave is done reading W
 #pragma unroll
-            for (int u = 0; u < NJ; u++) {
-                const int t = wave + GM_WAVES * u;
-                if (t < H::NTILE) {
-                    const int bl = t / (NT * NT), rem = t - bl * (NT * NT), ti = rem / NT, tj = rem - ti * NT;
-                    const int rs = g * G + bl, r = rs / 3, s = rs - 3 * r;
-                    store_tile<H>(oc, r * NB + 16 * ti, s * NB + 16 * tj, valid<H>(ti), valid<H>(tj), acc[u], lane);
+                for (int u = 0; u < NJ; u++) {
+                    if (u < 4 || wave < 4) {
+                        int bl, ti, tj;
+                        gm_q2_tile(wave, u, bl, ti, tj);
+                        const int r = bl / 3, s = bl - 3 * r;
+                        const int b = 16 * tj + m;
+#pragma unroll
+                        for (int v = 0; v < 4; v++) {
+                            const int a = 16 * ti + mm::acc_row<MM>(lane, v);
+                            if (a < NB && b < NB) Ks[h + (r * NB + a) * H::ND + s * NB + b] = acc[u][v];
+                        }
+                    }
+                }
+                __syncthreads();
+                typedef T TV __attribute__((ext_vector_type(H::VEC)));
+                constexpr int NK = H::ND * H::ND;
+                const auto out = q2::gmem(static_cast<T *>(A.out));
+                const auto aligned = (__attribute__((address_space(1))) TV *)(out + (base - h));
+                const TV *k16 = reinterpret_cast<const TV *>(Ks);
+                const int vf = h ? 1 : 0, vl = (NK + h) / H::VEC;  // whole vectors [vf, vl)
+                constexpr int NV = ((NK + 2 * H::VEC - 1) / H::VEC + GM_THREADS - 1) / GM_THREADS;
+                constexpr int BATCH = 4;
+#pragma unroll
+                for (int j0 = 0; j0 < NV; j0 += BATCH) {
+                    TV buf[BATCH];
+#pragma unroll
+                    for (int j = 0; j < BATCH; j++) {
+                        const int v = vf + tid + GM_THREADS * (j0 + j);
+                        if (j0 + j < NV && v < vl) buf[j] = k16[v];
+                    }
+#pragma unroll
+                    for (int j = 0; j < BATCH; j++) {
+                        const int v = vf + tid + GM_THREADS * (j0 + j);
+                        if (j0 + j < NV && v < vl) __builtin_nontemporal_store(buf[j], aligned + v);
+                    }
+                }
+                // the entries before the first and after the last whole vector
+                if (tid < 2 * H::VEC) {
+                    const int f = tid < H::VEC ? tid : vl * H::VEC - h + (tid - H::VEC);
+                    const bool head = tid < H::VEC && f < vf * H::VEC - h;
+                    const bool tail = tid >= H::VEC && f < NK;
+                    if (head || tail) out[base + f] = Ks[h + f];
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < NJ; u++) {
+                    const int t = wave + GM_WAVES * u;
+                    if (t < H::NTILE) {
+                        const int bl = t / (NT * NT), rem = t - bl * (NT * NT), ti = rem / NT, tj = rem - ti * NT;
+                        const int rs = g * G + bl, r = rs / 3, s = rs - 3 * r;
+                        store_tile<H>(oc, r * NB + 16 * ti, s * NB + 16 * tj, valid<H>(ti), valid<H>(tj), acc[u], lane);
+                    }
                 }
             }
             __syncthreads();  // W is rebuilt by the next group or cell

@@ -181,3 +181,36 @@ def test_wdot_matrix_first_chunked(orc, cell, p, curved, prec):
     out = plan(X, C, material=_t(M, dt), dofs=_t(U, dt), workspace=plan.workspace(mesh.n_cells, X.device))
     plan.check()
     assert _err(out.cpu().numpy(), ref) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("form", ["wdot", "convect"])
+def test_forms_f2_q2_matrix_output_offsets(orc, form, prec):
+    """Q2 matrices of the two forms written through an LDS staging area in
+    16-byte vectors: an output that starts at any element offset from a
+    16-byte boundary (and cells whose matrices start at either parity) gets
+    the same values as an aligned one, bit for bit, with nothing written
+    outside the matrices."""
+    import torch
+    import paper_2107_04121_amd as fe
+    mesh = meshgen.hex_mesh((3, 3, 3), 2, alpha=0.15, seed=48, curved=0.04)
+    nb, nq = orc.sizes("hex", 2)
+    kind = "tensor_qp" if form == "wdot" else None
+    M = meshgen.tensor_qp(mesh.n_cells, nq, seed=49) if kind else None
+    U = meshgen.dofs(mesh.n_nodes, 3, seed=50)
+    plan = fe.Plan("hex", 2, form, "matrix", prec, material=kind)
+    assert plan.variant == "mfma"
+    dt = plan.dtype
+    X, C, Ud = _t(mesh.coords), _t(mesh.conn), _t(U, dt)
+    Md = None if M is None else _t(M, dt)
+    K0 = plan(X, C, material=Md, dofs=Ud)
+    plan.check()
+    n = K0.numel()
+    for off in ((1,) if prec == "fp64" else (1, 2, 3)):
+        print(f"[f2] output offset {off} Q2 {form} {prec}", flush=True)
+        buf = torch.full((n + off + 4,), 7.0, dtype=dt, device="cuda:0")
+        out = buf[off:off + n].view(K0.shape)
+        plan(X, C, material=Md, dofs=Ud, out=out)
+        plan.check()
+        assert torch.equal(out, K0)
+        assert bool((buf[:off] == 7.0).all()) and bool((buf[off + n:] == 7.0).all())
