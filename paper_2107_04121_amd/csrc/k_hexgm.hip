@@ -67,25 +67,30 @@ struct HexGM {
     // convection also du_i/dxi_j (9) and u_i (3)
     static constexpr int NF = CONV ? 21 : 9;
     static constexpr int PS = CONV ? 12 : 9;  // per point: c_rs (9), then w det v (3)
-    // LDS layout (bytes); the sum-factorization scratch F shares the space
-    // of W, which is free between the last products of a cell and the
-    // first W block of the next
+    // Q2 (all nine blocks in one group): no W blocks.  The products take
+    // W_rs = c_rs Phi (+ V on the diagonal blocks of the convection, V[b][q]
+    // = w det v . grad_xi phi_b) straight from Phi, the point coefficients
+    // and V, and the cell's matrix is staged in LDS after them and leaves in
+    // linear 16-byte stores (its 81-entry rows straddle 128-byte lines, so
+    // tile stores would write partial lines).
+    static constexpr bool STAGE = G == 9;
+    static constexpr int VEC = 16 / (int)sizeof(T);
+    // LDS layout (bytes).  Region R holds, one after the other in a cell,
+    // the sum-factorization scratch F, then W (Q3) or V (Q2 convection),
+    // then (Q2) the staged matrix; F is free between the last products of a
+    // cell and the first W block of the next.
     static constexpr int OFF_TB = 0;  // double B1[N1][N1], D1[N1][N1], w[NQ]
     // double xs[3][NB], then us[3][NB] (convection) or the cell's M[NQ][9]
     static constexpr int OFF_X = q2::align16(OFF_TB + (2 * N1 * N1 + NQ) * 8);
-    static constexpr int OFF_P = q2::align16(OFF_X + (CONV ? 6 * NB : 3 * NB + 9 * NQ) * 8);  // double Pq[NQ][PS]
-    static constexpr int OFF_A = q2::align16(OFF_P + NQ * PS * 8);               // T Phi[NBP][KS]
-    static constexpr int OFF_W = q2::align16(OFF_A + NBP * KS * (int)sizeof(T));  // T W[G][NBP][KS]; double F[NF][NQ]
-    static constexpr int W_BYTES = G * NBP * KS * (int)sizeof(T);
+    // double Pq[KP][PS] (rows NQ.. are zero: the padding points)
+    static constexpr int OFF_P = q2::align16(OFF_X + (CONV ? 6 * NB : 3 * NB + 9 * NQ) * 8);
+    static constexpr int OFF_A = q2::align16(OFF_P + KP * PS * 8);               // T Phi[NBP][KS]
+    static constexpr int OFF_W = q2::align16(OFF_A + NBP * KS * (int)sizeof(T));  // region R
+    static constexpr int W_BYTES = STAGE ? (CONV ? NBP * KS * (int)sizeof(T) : 0) : G * NBP * KS * (int)sizeof(T);
     static constexpr int F_BYTES = NF * NQ * 8;
-    static constexpr int BYTES = q2::align16(OFF_W + (W_BYTES > F_BYTES ? W_BYTES : F_BYTES));
-    // all nine blocks in one group (Q2): the cell's matrix is staged in W's
-    // space after the products and leaves in linear 16-byte stores (its
-    // 81-entry rows straddle 128-byte lines, so tile stores would write
-    // partial lines)
-    static constexpr int VEC = 16 / (int)sizeof(T);
-    static constexpr bool STAGE = G == 9;
-    static_assert(!STAGE || (ND * ND + VEC) * (int)sizeof(T) <= W_BYTES, "staging fits in W");
+    static constexpr int K_BYTES = STAGE ? (ND * ND + VEC) * (int)sizeof(T) : 0;
+    static constexpr int R_BYTES = q2::cmax(q2::cmax(W_BYTES, F_BYTES), K_BYTES);
+    static constexpr int BYTES = q2::align16(OFF_W + R_BYTES);
     // workgroups per CU the LDS allows (the launch bound asks for 2 MINB
     // waves per SIMD: 8 waves per workgroup over 4 SIMDs)
     static constexpr int MINB = P <= 2 ? 2 : 1;
@@ -205,9 +210,7 @@ __device__ __forceinline__ typename MMT<MM>::acc gm_mma(typename MMT<MM>::T a, t
 
 // Q2 (nine blocks of 2x2 tiles, 36 tiles): wave w takes the four tiles of
 // block w (u = 0..3: ti = u % 2, tj = u / 2) and waves 0-3 also tile
-// (w % 2, w / 2) of block 8 (u = 4).  The Phi fragments (rows ti) are the
-// same for every block, so a wave loads two of them and two or three W
-// fragments per depth step instead of one pair per tile.
+// (w % 2, w / 2) of block 8 (u = 4).
 __device__ __forceinline__ void gm_q2_tile(int wave, int u, int &bl, int &ti, int &tj)
 {
     bl = u < 4 ? wave : 8;
@@ -215,31 +218,55 @@ __device__ __forceinline__ void gm_q2_tile(int wave, int u, int &bl, int &ti, in
     tj = u < 4 ? (u >> 1) : (wave >> 1);
 }
 
+// The Q2 products.  Both operands come from Phi: a fragment of W_rs (rows
+// b, depth q) is c_rs(q) times the Phi fragment of the same rows, plus the
+// V fragment on the diagonal blocks of the convection.  So a wave loads two
+// Phi fragments (rows 0-15 and 16-31, the same for every block), its
+// blocks' coefficients (one value per point: broadcast reads) and V where
+// it needs it, per depth step.
 template <class H>
-__device__ __forceinline__ void gm_q2_products(const typename H::T *Ph, const typename H::T *W, int wave, int m,
-                                               int grp, typename H::ACC (&acc)[5])
+__device__ __forceinline__ void gm_q2_products(const typename H::T *Ph, const double *Pq, const typename H::T *V,
+                                               int wave, int m, int grp, typename H::ACC (&acc)[5])
 {
     using T = typename H::T;
-    constexpr int KS = H::KS, KP = H::KP, NBP = H::NBP, MM = sizeof(T) == 8 ? MM_F64 : MM_F32;
+    constexpr int KS = H::KS, KP = H::KP, PS = H::PS, MM = sizeof(T) == 8 ? MM_F64 : MM_F32;
     static_assert(H::NT == 2 && H::G == 9 && H::NJ == 5, "Q2 tile plan");
-    const bool extra = wave < 4, odd = wave & 1;  // wave-uniform
+    // wave-uniform
+    const bool extra = wave < 4, odd = wave & 1, hi = wave >> 1;
+    const bool diag = H::CONV && (wave == 0 || wave == 4);
     const T *pa = Ph + m * KS + grp;
-    const T *pb = W + (wave * NBP + m) * KS + grp;
-    const T *pe = W + (8 * NBP + 16 * (wave >> 1) + m) * KS + grp;
-    T a0[2], a1[2], b0[2], b1[2], be[2];
+    const T *pv = V + m * KS + grp;
+    const T *pve = V + (16 * (wave >> 1) + m) * KS + grp;
+    const double *pc = Pq + grp * PS;
+    T a0[2], a1[2], c[2], ce[2], v0[2], v1[2], ve[2];
     auto load = [&](int buf, int k) {
         a0[buf] = pa[k];
         a1[buf] = pa[16 * KS + k];
-        b0[buf] = pb[k];
-        b1[buf] = pb[16 * KS + k];
-        if (extra) be[buf] = pe[k];
+        c[buf] = static_cast<T>(pc[k * PS + wave]);
+        if (extra) ce[buf] = static_cast<T>(pc[k * PS + 8]);
+        if constexpr (H::CONV) {
+            if (diag) {
+                v0[buf] = pv[k];
+                v1[buf] = pv[16 * KS + k];
+            }
+            if (extra) ve[buf] = pve[k];
+        }
     };
     auto mfma = [&](int buf) {
-        acc[0] = gm_mma<MM>(a0[buf], b0[buf], acc[0]);
-        acc[1] = gm_mma<MM>(a1[buf], b0[buf], acc[1]);
-        acc[2] = gm_mma<MM>(a0[buf], b1[buf], acc[2]);
-        acc[3] = gm_mma<MM>(a1[buf], b1[buf], acc[3]);
-        if (extra) acc[4] = gm_mma<MM>(odd ? a1[buf] : a0[buf], be[buf], acc[4]);
+        T b0 = c[buf] * a0[buf], b1 = c[buf] * a1[buf];
+        if (diag) {
+            b0 += v0[buf];
+            b1 += v1[buf];
+        }
+        acc[0] = gm_mma<MM>(a0[buf], b0, acc[0]);
+        acc[1] = gm_mma<MM>(a1[buf], b0, acc[1]);
+        acc[2] = gm_mma<MM>(a0[buf], b1, acc[2]);
+        acc[3] = gm_mma<MM>(a1[buf], b1, acc[3]);
+        if (extra) {
+            T be = ce[buf] * (hi ? a1[buf] : a0[buf]);
+            if constexpr (H::CONV) be += ve[buf];
+            acc[4] = gm_mma<MM>(odd ? a1[buf] : a0[buf], be, acc[4]);
+        }
     };
     // fragments of step k + 4 are loaded while step k multiplies
     load(0, 0);
@@ -286,6 +313,7 @@ __global__ __launch_bounds__(GM_THREADS, (2 * HexGM<P, FORM, MM>::MINB)) void k_
     }
     for (int k = tid; k < NQ; k += GM_THREADS) wq[k] = A.tab.w[k];
     __syncthreads();
+    for (int k = tid; k < (KP - NQ) * PS; k += GM_THREADS) Pq[NQ * PS + k] = 0.0;
     // Phi[b][q] = phi_b(q), zero in the padding rows and points
     for (int k = tid; k < NBP * KS; k += GM_THREADS) {
         const int b = k / KS, q = k - b * KS;
@@ -344,8 +372,27 @@ __global__ __launch_bounds__(GM_THREADS, (2 * HexGM<P, FORM, MM>::MINB)) void k_
 
         T *oc = static_cast<T *>(A.out) + e * static_cast<int64_t>(H::ND) * H::ND;
         for (int g = 0; g < H::NGRP; g++) {
-            // 3a. W blocks rs = g G + bl, bl < G: item (b, q) writes row b,
-            //     column q of each (zero at the padding rows and points)
+            // 3a. W blocks rs = g G + bl, bl < G (Q2: V only): item (b, q)
+            //     writes row b, column q of each (zero at the padding rows
+            //     and points)
+            if constexpr (H::STAGE) {
+                if constexpr (CONV) {
+                    for (int it = tid; it < NBP * KP; it += GM_THREADS) {
+                        const int q = it % KP, b = it / KP;
+                        double adv = 0.0;
+                        if (q < NQ && b < NB) {
+                            const int q0 = q % N1, q1 = (q / N1) % N1, q2 = q / (N1 * N1);
+                            const int b0 = b % N1, b1 = (b / N1) % N1, b2 = b / (N1 * N1);
+                            const double bx = B1[q0 * N1 + b0], by = B1[q1 * N1 + b1], bz = B1[q2 * N1 + b2];
+                            const double dx = D1[q0 * N1 + b0], dy = D1[q1 * N1 + b1], dz = D1[q2 * N1 + b2];
+                            const double *pq = Pq + q * PS;
+                            adv = pq[9] * (dx * by * bz) + pq[10] * (bx * dy * bz) + pq[11] * (bx * by * dz);
+                        }
+                        W[b * KS + q] = static_cast<T>(adv);
+                    }
+                    __syncthreads();
+                }
+            } else {
             for (int it = tid; it < NBP * KP; it += GM_THREADS) {
                 const int q = it % KP, b = it / KP;
                 double phi = 0.0, adv = 0.0;
@@ -369,6 +416,7 @@ __global__ __launch_bounds__(GM_THREADS, (2 * HexGM<P, FORM, MM>::MINB)) void k_
                 }
             }
             __syncthreads();
+            }
 
             // 3b. this wave's tiles t = wave + 8 u of the group: block bl,
             //     tile (ti, tj); slots past the last tile multiply tile 0
@@ -377,7 +425,7 @@ __global__ __launch_bounds__(GM_THREADS, (2 * HexGM<P, FORM, MM>::MINB)) void k_
 #pragma unroll
             for (int u = 0; u < NJ; u++) acc[u] = ACC{};
             if constexpr (H::STAGE) {
-                gm_q2_products<H>(Ph, W, wave, m, grp, acc);
+                gm_q2_products<H>(Ph, Pq, W, wave, m, grp, acc);
             } else {
                 int ra[NJ], rb[NJ];
 #pragma unroll
