@@ -208,14 +208,30 @@ __device__ __forceinline__ typename MMT<MM>::acc gm_mma(typename MMT<MM>::T a, t
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// Q2 (nine blocks of 2x2 tiles, 36 tiles): wave w takes the four tiles of
-// block w (u = 0..3: ti = u % 2, tj = u / 2) and waves 0-3 also tile
-// (w % 2, w / 2) of block 8 (u = 4).
-__device__ __forceinline__ void gm_q2_tile(int wave, int u, int &bl, int &ti, int &tj)
+// Q2 (nine blocks of 2x2 tiles).  Weighted dot: every block is
+// Phi^T diag(c_rs) Phi, symmetric, so its tiles (0,0), (0,1), (1,1) are
+// computed and (1,0) is written as the transpose of (0,1): wave w takes
+// those of block w (u = 0, 1, 2) and waves 0-2 one of block 8 (u = 3), 27
+// tiles.  Convection (whose diagonal blocks add V): wave w takes the four
+// tiles of block w (u = 0..3: ti = u % 2, tj = u / 2) and waves 0-3 tile
+// (w % 2, w / 2) of block 8 (u = 4), 36 tiles.  (The symmetric plan for the
+// convection's off-diagonal blocks, 30 tiles, measured slower.)
+struct GmSlot {
+    int bl, ti, tj;
+    bool mirror, valid;
+};
+
+template <bool CONV>
+__device__ __forceinline__ GmSlot gm_q2_slot(int wave, int u)
 {
-    bl = u < 4 ? wave : 8;
-    ti = u < 4 ? (u & 1) : (wave & 1);
-    tj = u < 4 ? (u >> 1) : (wave >> 1);
+    if constexpr (CONV) {
+        if (u < 4) return GmSlot{wave, u & 1, u >> 1, false, true};
+        return GmSlot{8, wave & 1, wave >> 1, false, wave < 4};
+    } else {
+        if (u < 3) return GmSlot{wave, u == 2, u >= 1, u == 1, true};
+        const int k = u == 3 && wave < 3 ? wave : -1;
+        return GmSlot{8, k == 2, k >= 1, k == 1, k >= 0};
+    }
 }
 
 // The Q2 products.  Both operands come from Phi: a fragment of W_rs (rows
@@ -231,25 +247,25 @@ __device__ __forceinline__ void gm_q2_products(const typename H::T *Ph, const do
     using T = typename H::T;
     constexpr int KS = H::KS, KP = H::KP, PS = H::PS, MM = sizeof(T) == 8 ? MM_F64 : MM_F32;
     static_assert(H::NT == 2 && H::G == 9 && H::NJ == 5, "Q2 tile plan");
-    // wave-uniform
-    const bool extra = wave < 4, odd = wave & 1, hi = wave >> 1;
+    // wave-uniform: the tile of block 8, if any
+    const GmSlot e = gm_q2_slot<H::CONV>(wave, H::CONV ? 4 : 3);
     const bool diag = H::CONV && (wave == 0 || wave == 4);
     const T *pa = Ph + m * KS + grp;
     const T *pv = V + m * KS + grp;
-    const T *pve = V + (16 * (wave >> 1) + m) * KS + grp;
+    const T *pve = V + (16 * e.tj + m) * KS + grp;
     const double *pc = Pq + grp * PS;
     T a0[2], a1[2], c[2], ce[2], v0[2], v1[2], ve[2];
     auto load = [&](int buf, int k) {
         a0[buf] = pa[k];
         a1[buf] = pa[16 * KS + k];
         c[buf] = static_cast<T>(pc[k * PS + wave]);
-        if (extra) ce[buf] = static_cast<T>(pc[k * PS + 8]);
+        if (e.valid) ce[buf] = static_cast<T>(pc[k * PS + 8]);
         if constexpr (H::CONV) {
             if (diag) {
                 v0[buf] = pv[k];
                 v1[buf] = pv[16 * KS + k];
             }
-            if (extra) ve[buf] = pve[k];
+            if (e.valid) ve[buf] = pve[k];
         }
     };
     auto mfma = [&](int buf) {
@@ -258,14 +274,23 @@ __device__ __forceinline__ void gm_q2_products(const typename H::T *Ph, const do
             b0 += v0[buf];
             b1 += v1[buf];
         }
-        acc[0] = gm_mma<MM>(a0[buf], b0, acc[0]);
-        acc[1] = gm_mma<MM>(a1[buf], b0, acc[1]);
-        acc[2] = gm_mma<MM>(a0[buf], b1, acc[2]);
-        acc[3] = gm_mma<MM>(a1[buf], b1, acc[3]);
-        if (extra) {
-            T be = ce[buf] * (hi ? a1[buf] : a0[buf]);
+        T ae = T(0), be = T(0);
+        if (e.valid) {
+            ae = e.ti ? a1[buf] : a0[buf];
+            be = ce[buf] * (e.tj ? a1[buf] : a0[buf]);
             if constexpr (H::CONV) be += ve[buf];
-            acc[4] = gm_mma<MM>(odd ? a1[buf] : a0[buf], be, acc[4]);
+        }
+        if constexpr (H::CONV) {
+            acc[0] = gm_mma<MM>(a0[buf], b0, acc[0]);
+            acc[1] = gm_mma<MM>(a1[buf], b0, acc[1]);
+            acc[2] = gm_mma<MM>(a0[buf], b1, acc[2]);
+            acc[3] = gm_mma<MM>(a1[buf], b1, acc[3]);
+            if (e.valid) acc[4] = gm_mma<MM>(ae, be, acc[4]);
+        } else {
+            acc[0] = gm_mma<MM>(a0[buf], b0, acc[0]);
+            acc[1] = gm_mma<MM>(a0[buf], b1, acc[1]);
+            acc[2] = gm_mma<MM>(a1[buf], b1, acc[2]);
+            if (e.valid) acc[3] = gm_mma<MM>(ae, be, acc[3]);
         }
     };
     // fragments of step k + 4 are loaded while step k multiplies
@@ -484,15 +509,17 @@ __global__ __launch_bounds__(GM_THREADS, (2 * HexGM<P, FORM, MM>::MINB)) void k_
                 __syncthreads();  // every wave is done reading W
 #pragma unroll
                 for (int u = 0; u < NJ; u++) {
-                    if (u < 4 || wave < 4) {
-                        int bl, ti, tj;
-                        gm_q2_tile(wave, u, bl, ti, tj);
-                        const int r = bl / 3, s = bl - 3 * r;
-                        const int b = 16 * tj + m;
+                    const GmSlot t = gm_q2_slot<CONV>(wave, u);
+                    if (t.valid) {
+                        const int r = t.bl / 3, s = t.bl - 3 * r;
+                        const int b = 16 * t.tj + m;
 #pragma unroll
                         for (int v = 0; v < 4; v++) {
-                            const int a = 16 * ti + mm::acc_row<MM>(lane, v);
-                            if (a < NB && b < NB) Ks[h + (r * NB + a) * H::ND + s * NB + b] = acc[u][v];
+                            const int a = 16 * t.ti + mm::acc_row<MM>(lane, v);
+                            if (a < NB && b < NB) {
+                                Ks[h + (r * NB + a) * H::ND + s * NB + b] = acc[u][v];
+                                if (t.mirror) Ks[h + (r * NB + b) * H::ND + s * NB + a] = acc[u][v];
+                            }
                         }
                     }
                 }
