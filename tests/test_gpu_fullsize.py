@@ -207,3 +207,45 @@ def test_c5_adjoint_32cube_full(orc, prec):
                 dJdu=rel(ut.grad.cpu().numpy(), gu_ref))
     print(f"[fullsize] c5 {prec} errors {errs}", flush=True)
     assert max(errs.values()) < TOL[prec], errs
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("form", ["wdot", "convect"])
+def test_q2_forms_f2_32cube(orc, form, prec):
+    """Weighted dot and convection matrices of Q2 hexahedra on 32^3 =
+    32,768 cells (the matrix-core kernel, persistent over XCD ranges):
+    sampled cells against the oracle; for every cell, the weighted dot's
+    blocks symmetric, and the convection matrix times the state twice the
+    residual of the sum-factorized kernel."""
+    import torch
+    import paper_2107_04121_amd as fe
+    mesh = meshgen.hex_mesh(32, 2, alpha=0.15, seed=0)
+    nq = 27
+    kind = "tensor_qp" if form == "wdot" else None
+    M = meshgen.tensor_qp(mesh.n_cells, nq, seed=1) if kind else None
+    U = meshgen.dofs(mesh.n_nodes, 3, seed=2)
+    plan = fe.Plan("hex", 2, form, "matrix", prec, material=kind)
+    print(f"[fullsize] q2 32^3 {form} {prec} {plan.variant}", flush=True)
+    assert plan.variant == "mfma"
+    dt = plan.dtype
+    X, C, Ud = _t(mesh.coords), _t(mesh.conn), _t(U, dt)
+    Md = None if M is None else _t(M, dt)
+    K = plan(X, C, material=Md, dofs=Ud)
+    plan.check()
+    idx = _sample(mesh.n_cells)
+    ref = orc.matrix(_sub(mesh, idx), form, None if M is None else M[idx], kind, u=U)
+    err = _err(K[_t(idx)].cpu().numpy(), ref)
+    print(f"[fullsize] q2 32^3 {form} {prec} sampled err {err:.2e}", flush=True)
+    assert err < TOL[prec]
+    scale = K.abs().amax(dim=(1, 2))
+    if form == "wdot":
+        Kb = K.reshape(-1, 3, 27, 3, 27)
+        asym = (Kb - Kb.transpose(2, 4)).abs().amax(dim=(1, 2, 3, 4)) / scale
+        assert float(asym.max()) < 4 * TOL[prec]
+    else:
+        r = fe.Plan("hex", 2, "convect", "residual", prec)(X, C, dofs=Ud)
+        ue = Ud[C.long()].transpose(1, 2).reshape(mesh.n_cells, -1).contiguous()
+        Ku = torch.bmm(K, ue.unsqueeze(2)).squeeze(2)
+        rr = r.reshape(mesh.n_cells, -1)
+        rel = (Ku - 2 * rr).abs().amax(1) / (K.abs().amax(dim=(1, 2)) * ue.abs().amax(1))
+        assert float(rel.max()) < 50 * TOL[prec], float(rel.max())
