@@ -429,7 +429,8 @@ def eval_sum(plan, coords, conn, material=None, dofs=None, cell_values=None,
 
 class ElasticEnergyPlan:
     """Everything the elasticity energy J(c, x, u) = sum_e u_e^T K_e u_e
-    needs for one mesh topology: eval and residual plans and the incidence."""
+    needs for one mesh topology: eval and residual plans, the incidence and
+    the gradient kernel's workspace."""
 
     def __init__(self, cell, order, conn, n_nodes, precision="fp64",
                  material="iso_qp"):
@@ -440,6 +441,37 @@ class ElasticEnergyPlan:
         self.resid = Plan(cell, order, "elasticity", "residual", precision,
                           material=material)
         self.inc = Incidence(conn, n_nodes)
+        self._gws = None
+
+    def grad_workspace(self, device):
+        """The gradient kernel's workspace, zero-filled once: its fault bits
+        are cleared by check() and the rest is overwritten by every call."""
+        n_cells = self.conn.shape[0]
+        b = ctypes.c_size_t()
+        _lib.check(_lib.lib().fe_energy_grad_workspace_size(
+            self.eval._h, n_cells, ctypes.byref(b)),
+            "fe_energy_grad_workspace_size")
+        if self._gws is None or self._gws.numel() < b.value or \
+                self._gws.device != device:
+            self._gws = energy_grad_workspace(self.eval, n_cells, device)
+        return self._gws
+
+    def check(self, stream=None):
+        """Synchronise and raise FeError if a kernel of the energy, of its
+        gradient or of the residual saw det J <= 0 or an out-of-range node
+        number since the last check.  Every workspace is read and cleared
+        before the first fault found is raised."""
+        first = None
+        checks = [(self.eval, None), (self.resid, None)]
+        if self._gws is not None:
+            checks.append((self.eval, self._gws))
+        for plan, ws in checks:
+            try:
+                plan.check(ws, stream)
+            except FeError as err:
+                first = first or err
+        if first is not None:
+            raise first
 
 
 def _make_energy_function():
@@ -448,12 +480,14 @@ def _make_energy_function():
     class _ElasticEnergy(torch.autograd.Function):
         """J = sum_e u_e^T K_e(c, x) u_e.  Backward: dJ/dc, dJ/dx from the
         adjoint kernel (geometry recomputed), dJ/du = 2 * assembled
-        residual."""
+        residual.  The forward does not synchronise; the backward checks
+        the fault bits of both passes once, after its launches, and keeps
+        the incoming gradient on the device (the kernels run with scale 1
+        and their results are multiplied by it)."""
 
         @staticmethod
         def forward(ctx, c, x, u, ep):
             J = eval_sum(ep.eval, x, ep.conn, material=c, dofs=u)
-            ep.eval.check()
             ctx.ep = ep
             ctx.save_for_backward(c, x, u)
             return J
@@ -462,16 +496,20 @@ def _make_energy_function():
         def backward(ctx, gJ):
             c, x, u = ctx.saved_tensors
             ep = ctx.ep
-            s = float(gJ)
             gc = gx = gu = None
             need_c, need_x, need_u = ctx.needs_input_grad[:3]
             if need_c or need_x:
-                gc, gx = _energy_grad(ep.eval, ep.inc, x, ep.conn, c, u, s,
-                                      want_mat=need_c, want_coords=need_x)
+                gc, gx = _energy_grad(ep.eval, ep.inc, x, ep.conn, c, u, 1.0,
+                                      want_mat=need_c, want_coords=need_x,
+                                      ws=ep.grad_workspace(x.device),
+                                      check=False)
             if need_u:
                 r = ep.resid(x, ep.conn, material=c, dofs=u)
-                ep.resid.check()
-                gu = assemble(ep.inc, r, scale=2.0 * s)
+                gu = assemble(ep.inc, r, scale=2.0)
+            ep.check()
+            for g in (gc, gx, gu):
+                if g is not None:
+                    g.mul_(gJ)
             return gc, gx, gu, None
 
     return _ElasticEnergy
@@ -481,7 +519,9 @@ _ELASTIC = None
 
 
 def ElasticEnergy(c, x, u, ep: ElasticEnergyPlan):
-    """Differentiable J(c, x, u) (a torch scalar) on the GPU."""
+    """Differentiable J(c, x, u) (a torch scalar) on the GPU.  Faults
+    (det J <= 0, node numbers out of range) are raised by the backward pass,
+    or by ep.check() when no backward pass runs."""
     global _ELASTIC
     if _ELASTIC is None:
         _ELASTIC = _make_energy_function()

@@ -131,6 +131,43 @@ def test_autograd_energy(orc, prec):
     assert _rel(ut.grad.cpu().numpy(), 3.0 * gu_ref) < tol
 
 
+def test_autograd_energy_faults_and_repeats(orc):
+    """The energy's forward does not synchronise: an inverted cell is
+    reported by the backward pass (FE_ERR_NONPOSITIVE_JACOBIAN), or by
+    ep.check() when only the forward ran, and the next clean step runs
+    normally.  Repeated steps with the cached gradient workspace give
+    identical gradients."""
+    import torch
+    import paper_2107_04121_amd as fe
+    mesh = meshgen.hex_mesh(1, 2, alpha=0.0, seed=74)
+    c = meshgen.lame_qp(1, 27, seed=33)
+    U = meshgen.dofs(mesh.n_nodes, 3, seed=34)
+    bad = mesh.conn.reshape(1, 3, 3, 3)[:, :, :, ::-1].reshape(1, -1).copy()  # mirror x: det < 0
+    for conn, faulty in ((bad, True), (mesh.conn, False)):
+        ep = fe.ElasticEnergyPlan("hex", 2, _t(conn), mesh.n_nodes, "fp64")
+        ct = _t(c).requires_grad_(True)
+        xt = _t(mesh.coords).requires_grad_(True)
+        ut = _t(U).requires_grad_(True)
+        J = fe.ElasticEnergy(ct, xt, ut, ep)
+        if faulty:
+            with pytest.raises(fe.FeError) as ei:
+                J.backward()
+            assert ei.value.status == 3
+            fe.ElasticEnergy(ct, xt, ut, ep)  # forward only
+            with pytest.raises(fe.FeError):
+                ep.check()
+            ep.check()  # cleared
+            continue
+        J.backward()
+        g1 = [t.grad.clone() for t in (ct, xt, ut)]
+        for t in (ct, xt, ut):
+            t.grad = None
+        fe.ElasticEnergy(ct, xt, ut, ep).backward()
+        for a, t in zip(g1, (ct, xt, ut)):
+            assert torch.equal(a, t.grad)
+        assert _rel(ct.grad.cpu().numpy(), orc.energy_grad(mesh, c, U)[0]) < TOL["fp64"]
+
+
 def test_gpu_gradient_central_differences(orc):
     """FP64 central differences (h = 1e-6) of the GPU forward along seeded
     directions agree with the GPU adjoint."""
