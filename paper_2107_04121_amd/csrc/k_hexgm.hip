@@ -751,10 +751,19 @@ __global__ __launch_bounds__(GM_THREADS, 2) void k_hexgmc(ExecArgs A)
                         W[(bk * NBP + b) * KS + dl] = static_cast<T>(x);
                     }
                 } else {
-                // Phi chunk: basis b at the chunk's points (zero past NB / NQ)
+                // Phi chunk: basis b at the chunk's points (zero past NB / NQ),
+                // from the 1-D tables in LDS: a global load here would wait
+                // for the previous pass's tile stores (a wave's memory
+                // operations complete in order)
                 for (int it = tid; it < NBP * KC; it += GM_THREADS) {
                     const int b = it % NBP, ql = it / NBP, q = k0 + ql;
-                    Ph[b * KS + ql] = static_cast<T>(b < NB && q < NQ ? A.tab.bf[q * NB + b] : 0.0);
+                    double v = 0.0;
+                    if (b < NB && q < NQ) {
+                        const int q0 = q % N1, q1 = (q / N1) % N1, q2 = q / (N1 * N1);
+                        const int b0 = b % N1, b1 = (b / N1) % N1, b2 = b / (N1 * N1);
+                        v = B1[q0 * N1 + b0] * B1[q1 * N1 + b1] * B1[q2 * N1 + b2];
+                    }
+                    Ph[b * KS + ql] = static_cast<T>(v);
                 }
                 // W chunks of the pass's blocks
                 for (int it = tid; it < nbk * NBP * KC; it += GM_THREADS) {
