@@ -638,7 +638,13 @@ struct HexGMC {
     static constexpr int DQ = ELAST ? 3 * NQ : NQ;
     static constexpr int KC = 16, NCH = (DQ + KC - 1) / KC, KS = op_stride(MM, KC);
     static constexpr int NTILES = 9 * TPB;
-    static constexpr int NPASS = (NTILES + GM_WAVES * gmc_cap(MM) - 1) / (GM_WAVES * gmc_cap(MM));
+    // FP64 weighted dot: W_rs = c_rs Phi formed in registers from the Phi
+    // chunk and the point coefficients (no W chunks), with fewer
+    // accumulator tiles per wave to make room.  For the convection and in
+    // FP32 the extra passes cost more than the W chunks save (measured).
+    static constexpr bool REGW = FORM == FE_FORM_WDOT && MM == MM_F64;
+    static constexpr int CAP = REGW ? 12 : gmc_cap(MM);
+    static constexpr int NPASS = (NTILES + GM_WAVES * CAP - 1) / (GM_WAVES * CAP);
     static constexpr int NJ = (NTILES + GM_WAVES * NPASS - 1) / (GM_WAVES * NPASS);  // tiles per wave and pass
     static constexpr int PT = GM_WAVES * NJ;                                          // tiles per pass
     static constexpr int WB = (PT + TPB - 1) / TPB + 1 < 9 ? (PT + TPB - 1) / TPB + 1 : 9;  // blocks a pass touches
@@ -650,7 +656,9 @@ struct HexGMC {
     static constexpr int OFF_TB = 0;  // double B1[N1][N1], D1[N1][N1], w[NQ]
     static constexpr int OFF_X = q2::align16(OFF_TB + (2 * N1 * N1 + NQ) * 8);
     static constexpr int OFF_P = q2::align16(OFF_X + (CONV ? 6 * NB : (ELAST ? 3 * NB : 3 * NB + 9 * NQ)) * 8);  // double Pq[NQ][PS]
-    static constexpr int OFF_A = q2::align16(OFF_P + NQ * PS * 8);  // T Phi[NBP][KS] or G; double F[NF][NQ]
+    // REGW: Pq rows NQ .. NCH KC - 1 are zero (the chunks' padding points)
+    static constexpr int QPAD = REGW ? NCH * KC : NQ;
+    static constexpr int OFF_A = q2::align16(OFF_P + QPAD * PS * 8);  // T Phi[NBP][KS] or G; double F[NF][NQ]
     static constexpr int OFF_W = q2::align16(OFF_A + NBP * KS * (int)sizeof(T));  // T W[WB][NBP][KS]
     static constexpr int CH_END = OFF_W + WB * NBP * KS * (int)sizeof(T);
     static constexpr int F_END = OFF_A + NF * NQ * 8;
@@ -691,6 +699,7 @@ __global__ __launch_bounds__(GM_THREADS, 2) void k_hexgmc(ExecArgs A)
         D1[k] = A.tab.D1[k];
     }
     for (int k = tid; k < NQ; k += GM_THREADS) wq[k] = A.tab.w[k];
+    for (int k = tid; k < (H::QPAD - NQ) * PS; k += GM_THREADS) Pq[NQ * PS + k] = 0.0;
     __syncthreads();
 
     for (; e < e_end; e += stride) {
@@ -714,8 +723,15 @@ __global__ __launch_bounds__(GM_THREADS, 2) void k_hexgmc(ExecArgs A)
                 const int t = t0 + wave + GM_WAVES * u, tt = t < t1 ? t : t0;
                 const int blk = tt / TPB, rem = tt - blk * TPB, ti = rem / NT, tj = rem - ti * NT;
                 ra[u] = 16 * ti;
-                rb[u] = (blk - blo) * NBP + 16 * tj;
+                // the row of the block's W chunk, or (REGW) the Phi row of the
+                // trial side
+                rb[u] = H::REGW ? 16 * tj : (blk - blo) * NBP + 16 * tj;
             }
+            // block of slot u (wave-uniform)
+            auto slot_blk = [&](int u) {
+                const int t = t0 + wave + GM_WAVES * u;
+                return (t < t1 ? t : t0) / TPB;
+            };
             for (int ch = 0; ch < H::NCH; ch++) {
                 const int k0 = ch * KC;
                 if constexpr (ELAST) {
@@ -765,8 +781,8 @@ __global__ __launch_bounds__(GM_THREADS, 2) void k_hexgmc(ExecArgs A)
                     }
                     Ph[b * KS + ql] = static_cast<T>(v);
                 }
-                // W chunks of the pass's blocks
-                for (int it = tid; it < nbk * NBP * KC; it += GM_THREADS) {
+                // W chunks of the pass's blocks (REGW: none)
+                for (int it = tid; it < (H::REGW ? 0 : nbk) * NBP * KC; it += GM_THREADS) {
                     const int ql = it % KC, rest = it / KC, b = rest % NBP, bk = rest / NBP;
                     const int q = k0 + ql, rs = blo + bk;
                     double x = 0.0;
@@ -788,17 +804,27 @@ __global__ __launch_bounds__(GM_THREADS, 2) void k_hexgmc(ExecArgs A)
                 // products over the chunk's points: k steps in a loop, the
                 // slots in groups whose fragments are loaded while the
                 // previous group multiplies
-                constexpr int G = sizeof(T) == 8 ? 4 : 8, NG = (NJ + G - 1) / G;
-                T a[2][G], bb[2][G];
+                constexpr int G = (sizeof(T) == 8 ? 4 : 8) / (H::REGW ? 2 : 1), NG = (NJ + G - 1) / G;
+                T a[2][G], bb[2][G], cq[2][G];
                 auto load = [&](int buf, int g, int k) {
 #pragma unroll
                     for (int v = 0; v < G; v++)
                         if (g * G + v < NJ) {
                             a[buf][v] = Ph[(ra[g * G + v] + m) * KS + k];
-                            bb[buf][v] = W[(rb[g * G + v] + m) * KS + k];
+                            if constexpr (H::REGW) {
+                                bb[buf][v] = Ph[(rb[g * G + v] + m) * KS + k];
+                                cq[buf][v] = static_cast<T>(Pq[(k0 + k) * PS + slot_blk(g * G + v)]);
+                            } else {
+                                bb[buf][v] = W[(rb[g * G + v] + m) * KS + k];
+                            }
                         }
                 };
                 auto mfma = [&](int buf, int g) {
+                    if constexpr (H::REGW) {
+#pragma unroll
+                        for (int v = 0; v < G; v++)
+                            if (g * G + v < NJ) bb[buf][v] *= cq[buf][v];
+                    }
 #pragma unroll
                     for (int v = 0; v < G; v++)
                         if (g * G + v < NJ) {
