@@ -661,8 +661,12 @@ struct HexGMC {
     static constexpr int OFF_A = q2::align16(OFF_P + QPAD * PS * 8);  // T Phi[NBP][KS] or G; double F[NF][NQ]
     static constexpr int OFF_W = q2::align16(OFF_A + NBP * KS * (int)sizeof(T));  // T W[WB][NBP][KS]
     static constexpr int CH_END = OFF_W + WB * NBP * KS * (int)sizeof(T);
+    // elasticity: the material rows C_rjsk (k = 0..2) of a chunk's depth
+    // values and the pass's blocks, double Cs[WB][KC][3]
+    static constexpr int OFF_C = q2::align16(CH_END);
+    static constexpr int C_END = OFF_C + (ELAST ? WB * KC * 3 * 8 : 0);
     static constexpr int F_END = OFF_A + NF * NQ * 8;
-    static constexpr int BYTES = q2::align16(CH_END > F_END ? CH_END : F_END);
+    static constexpr int BYTES = q2::align16(C_END > F_END ? C_END : F_END);
     static_assert(BYTES <= 160 * 1024, "LDS");
 };
 
@@ -686,6 +690,7 @@ __global__ __launch_bounds__(GM_THREADS, 2) void k_hexgmc(ExecArgs A)
     T *Ph = reinterpret_cast<T *>(smem + H::OFF_A);            // [NBP][KS]: points of the chunk
     double *F = reinterpret_cast<double *>(smem + H::OFF_A);   // [NF][NQ]
     T *W = reinterpret_cast<T *>(smem + H::OFF_W);             // [WB][NBP][KS]
+    double *Cs = reinterpret_cast<double *>(smem + H::OFF_C);  // [WB][KC][3] (elasticity)
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int m = lane & 15, grp = lane >> 4;
@@ -735,6 +740,18 @@ __global__ __launch_bounds__(GM_THREADS, 2) void k_hexgmc(ExecArgs A)
             for (int ch = 0; ch < H::NCH; ch++) {
                 const int k0 = ch * KC;
                 if constexpr (ELAST) {
+                    // the material rows of the chunk and the pass's blocks,
+                    // read from global memory once per chunk instead of by
+                    // every basis function's item
+                    if (tid < nbk * KC) {
+                        const int dl = tid % KC, bk = tid / KC, d = k0 + dl, q = d / 3, j = d - 3 * (d / 3);
+                        const int rs = blo + bk, r = rs / 3, s = rs - 3 * r;
+                        double c[3] = {0.0, 0.0, 0.0};
+                        if (q < NQ) material_row<T>(A, e * NQ + q, r, j, s, c);
+#pragma unroll
+                        for (int k = 0; k < 3; k++) Cs[(bk * KC + dl) * 3 + k] = c[k];
+                    }
+                    __syncthreads();
                     // G chunk: G_ja(q) at depth d = 3 q + j; W chunks:
                     // w det J sum_k C_rjsk(q) G_kb(q)
                     for (int it = tid; it < NBP * KC; it += GM_THREADS) {
@@ -751,14 +768,12 @@ __global__ __launch_bounds__(GM_THREADS, 2) void k_hexgmc(ExecArgs A)
                     for (int it = tid; it < nbk * NBP * KC; it += GM_THREADS) {
                         const int dl = it % KC, rest = it / KC, b = rest % NBP, bk = rest / NBP;
                         const int d = k0 + dl, q = d / 3, j = d - 3 * (d / 3);
-                        const int rs = blo + bk, r = rs / 3, s = rs - 3 * r;
                         double x = 0.0;
                         if (q < NQ && b < NB) {
                             double gx[3];
                             ref_grad<H>(B1, D1, b, q, gx);
                             const double *pq = Pq + q * PS;
-                            double c[3];
-                            material_row<T>(A, e * NQ + q, r, j, s, c);
+                            const double *c = Cs + (bk * KC + dl) * 3;
 #pragma unroll
                             for (int k = 0; k < 3; k++)
                                 x += c[k] * (gx[0] * pq[k] + gx[1] * pq[3 + k] + gx[2] * pq[6 + k]);
