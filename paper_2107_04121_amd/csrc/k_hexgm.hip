@@ -22,14 +22,19 @@
 //      dot) or w det J du_r/dx_s, with grad u = (du/dxi) J^-1 (convection),
 //      and for the convection w det J v, v = J^-1 u the reference-space
 //      velocity, so that u . grad phi_b = sum_j v_j dphi_b/dxi_j;
-//   3. the W blocks in LDS in the contraction type (all nine for Q2, three
-//      at a time for Q3), one (point, basis function) per item:
-//      W_rs = c_rs phi_b (+ w det v . dphi_b/dxi on the diagonal blocks),
-//      then every wave multiplies its 16x16 output tiles
-//      (v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32) over the points and
-//      stores them.  Rows of 81 or 192 entries: Q2 tiles go out through the
-//      L2 (their row segments straddle 128-byte lines), Q3 tiles
-//      nontemporally.
+//   3. Q3: the W blocks in LDS in the contraction type, three at a time,
+//      one (point, basis function) per item: W_rs = c_rs phi_b (+ w det
+//      v . dphi_b/dxi on the diagonal blocks); every wave multiplies its
+//      16x16 output tiles (v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32)
+//      over the points and stores them nontemporally (rows of 192 entries:
+//      whole 128-byte lines).
+//      Q2: no W blocks.  A W fragment is c_rs times the Phi fragment of the
+//      same rows (plus V = w det v . grad_xi phi, one matrix for the
+//      convection's diagonal blocks), formed in registers; the weighted
+//      dot's blocks are symmetric, so their (1,0) tiles are written as the
+//      transposes of the (0,1) tiles.  The cell's matrix is staged in LDS
+//      and leaves in linear 16-byte nontemporal stores (rows of 81 entries
+//      straddle 128-byte lines).
 #include "mm_device.h"
 
 namespace fe {
