@@ -1044,7 +1044,8 @@ def run_c8(args, orc):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; "
+        print(json.dumps({"error": "the library runs on one GPU (the "
+                          "multi-GPU sharding is designed, not built); "
                           "--gpus must be 1", "n_gpus": args.gpus}))
         sys.exit(2)
     import torch  # noqa: F401
