@@ -70,6 +70,16 @@ MEASURED_TRAFFIC = {
     "k_cw_scalar<hex,1,laplace,double>@128^3": dict(
         bytes=1195572737, sha256="ea6c4a1e084eaae9",
         sources=["k_cellwise.hip", "cw_device.h", "fe_device.h"]),
+    "k_sf<3,elasticity,float>@96^3": dict(
+        bytes=2067873756, sha256="7bfc61c550fd7cfd",
+        sources=["k_sumfact.hip", "cw_device.h", "fe_device.h"]),
+    "k_batch<float>@c4": dict(
+        bytes=2796599778, sha256="509ddc13a3475b6d",
+        sources=["k_batch.hip", "q2_device.h", "fe_device.h"]),
+    "k_hexgm<2,convect,fp64>@32^3": dict(
+        bytes=1778415335, sha256="b05bba2f3d372102",
+        sources=["k_hexgm.hip", "mm_device.h", "q2_device.h",
+                 "fe_device.h"]),
 }
 
 
@@ -543,7 +553,8 @@ def run_c3(args, orc):
     line["roofline"] = {"bound": "alu", "achieved": achieved,
                         "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                         "frac": achieved / FP64_PEAK_TFLOPS,
-                        "traffic": None,
+                        "traffic": (traffic("k_sf<3,elasticity,float>@96^3")
+                                    if n == 96 else None),
                         "kernel": "k_sf<3,elasticity,float>",
                         "flops_per_cell": flops,
                         "kernel_ms": prim["kernel_ms"],
@@ -652,7 +663,8 @@ def run_c4(args, orc):
     line["max_rel_err_vs_fp64_oracle"] = errs
     line["roofline"] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-                        "traffic": None, "kernel": "k_batch<float>",
+                        "traffic": traffic("k_batch<float>@c4"),
+                        "kernel": "k_batch<float>",
                         "kernel_ms": kms}
     line.update(extra)
     if not args.no_cpu:
@@ -909,7 +921,8 @@ def run_c7(args, orc):
     line["roofline"] = {"bound": "hbm", "achieved": prim["hbm_gbs"],
                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": prim["hbm_gbs"] / HBM_PEAK_GBS,
-                        "traffic": None,
+                        "traffic": (traffic("k_hexgm<2,convect,fp64>@32^3")
+                                    if n == 32 else None),
                         "kernel": "k_hexgm<2,convect,fp64>",
                         "kernel_ms": prim["kernel_ms"]}
     line["paths"] = paths
