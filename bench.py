@@ -68,7 +68,7 @@ MEASURED_TRAFFIC = {
                            sources=["k_hexmm.hip", "mm_device.h",
                                     "q2_device.h", "fe_device.h"]),
     "k_cw_scalar<hex,1,laplace,double>@128^3": dict(
-        bytes=1195572737, sha256="ea6c4a1e084eaae9",
+        bytes=1195579701, sha256="fb152f97c8e4eef5",
         sources=["k_cellwise.hip", "cw_device.h", "fe_device.h"]),
     "k_sf<3,elasticity,float>@96^3": dict(
         bytes=2067873756, sha256="7bfc61c550fd7cfd",
@@ -77,7 +77,7 @@ MEASURED_TRAFFIC = {
         bytes=2796599778, sha256="509ddc13a3475b6d",
         sources=["k_batch.hip", "q2_device.h", "fe_device.h"]),
     "k_hexgm<2,convect,fp64>@32^3": dict(
-        bytes=1778415335, sha256="b05bba2f3d372102",
+        bytes=1777412415, sha256="a8930954dabea877",
         sources=["k_hexgm.hip", "mm_device.h", "q2_device.h",
                  "fe_device.h"]),
 }

@@ -56,7 +56,7 @@ template <int CELL, int P, int FORM, typename T>
 __global__ __launch_bounds__(64, CELL == FE_CELL_HEX && sizeof(T) == 4 && FORM != FE_FORM_LAPLACE ? 4 : 1) void k_cw_scalar(ExecArgs A)
 {
     using C = CwScalar<CELL, P, FORM, T>;
-    constexpr int NB = C::NB, NQ = C::NQ, NP = C::NP, ND = C::ND, RC = C::RC, SS = C::SS;
+    constexpr int NB = C::NB, NP = C::NP, ND = C::ND, RC = C::RC, SS = C::SS;
     constexpr bool X_LDS = C::X_LDS;
     __shared__ T stage[64 * SS];
     __shared__ double xs[X_LDS ? 64 * XLds<NB>::STRIDE : 1];
@@ -197,7 +197,7 @@ __device__ __forceinline__ void elast_block(const ExecArgs &A, int64_t e0, const
                                             unsigned fault)
 {
     using C = CwElast<CELL, P, T>;
-    constexpr int NB = C::NB, NQ = C::NQ, ND = C::ND, RH = C::RH, SS = C::SS;
+    constexpr int NB = C::NB, ND = C::ND, RH = C::RH, SS = C::SS;
     constexpr bool DIAG = R == S;
     constexpr int NACC = ElastAcc<NB, R, S>::N;
     const int tid = threadIdx.x, lane = tid & 63;

@@ -772,7 +772,7 @@ __global__ __launch_bounds__(GM_THREADS, 2) void k_hexgmc(ExecArgs A)
                     }
                     for (int it = tid; it < nbk * NBP * KC; it += GM_THREADS) {
                         const int dl = it % KC, rest = it / KC, b = rest % NBP, bk = rest / NBP;
-                        const int d = k0 + dl, q = d / 3, j = d - 3 * (d / 3);
+                        const int q = (k0 + dl) / 3;
                         double x = 0.0;
                         if (q < NQ && b < NB) {
                             double gx[3];
