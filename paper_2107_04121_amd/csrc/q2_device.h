@@ -92,6 +92,21 @@ __device__ __forceinline__ void cell_range(int remap, int64_t n, int64_t &first,
     stride = per;
 }
 
+// Column c of adj J (J row-major at Jp) and det J: the column is the cross
+// product of rows c+1 and c+2 (mod 3), det J its dot product with row c.
+__device__ __forceinline__ void q2_adj_column(const double *Jp, int c, double (&adjc)[3], double &det)
+{
+    const int c1 = c == 2 ? 0 : c + 1, c2 = c == 0 ? 2 : c - 1;
+    const double *R0 = Jp + 3 * c, *R1 = Jp + 3 * c1, *R2 = Jp + 3 * c2;
+    const double x0 = R0[0], x1 = R0[1], x2 = R0[2];
+    const double y0 = R1[0], y1 = R1[1], y2 = R1[2];
+    const double z0 = R2[0], z1 = R2[1], z2 = R2[2];
+    adjc[0] = y1 * z2 - y2 * z1;
+    adjc[1] = y2 * z0 - y0 * z2;
+    adjc[2] = y0 * z1 - y1 * z0;
+    det = x0 * adjc[0] + x1 * adjc[1] + x2 * adjc[2];
+}
+
 // 6x6 grid of 16x16 output tiles; block (r,s) = tiles 2r..2r+1 x 2s..2s+1.
 // The 24 tiles of blocks r <= s are split in 2-D rectangles, 6 per wave, so
 // each wave loads few distinct operand fragments per k step (three of them
@@ -365,25 +380,14 @@ __device__ __forceinline__ void q2_run_staged(const Q2Job &A, int64_t e, int64_t
         if (tid < NQ * 9) {
             const int q = tid % NQ, r9 = tid / NQ, ci = r9 / 3, a2 = r9 - 3 * (r9 / 3);
             const int q0 = q % 3, q1 = (q / 3) % 3, q2 = q / 9;
-            double J[3][3];
-#pragma unroll
-            for (int r = 0; r < 3; r++)
-#pragma unroll
-                for (int c = 0; c < 3; c++) J[r][c] = Jq[q * 9 + r * 3 + c];
-            // column ci of J^-1 = adj J / det J: only that column of the
-            // adjugate, and 1/det by the hardware reciprocal refined with two
-            // Newton steps (r <- r + r (1 - det r)), accurate to ~1 ulp
-            double adj0[3], adjc[3];
-#pragma unroll
-            for (int j = 0; j < 3; j++) {
-                adj0[j] = J[1][(j + 1) % 3] * J[2][(j + 2) % 3] - J[1][(j + 2) % 3] * J[2][(j + 1) % 3];
-                const double k1 = sel3(ci, J[1][(j + 1) % 3], J[2][(j + 1) % 3], J[0][(j + 1) % 3]);
-                const double k2 = sel3(ci, J[2][(j + 2) % 3], J[0][(j + 2) % 3], J[1][(j + 2) % 3]);
-                const double k3 = sel3(ci, J[1][(j + 2) % 3], J[2][(j + 2) % 3], J[0][(j + 2) % 3]);
-                const double k4 = sel3(ci, J[2][(j + 1) % 3], J[0][(j + 1) % 3], J[1][(j + 1) % 3]);
-                adjc[j] = k1 * k2 - k3 * k4;
-            }
-            const double det = J[0][0] * adj0[0] + J[0][1] * adj0[1] + J[0][2] * adj0[2];
+            // column ci of J^-1 = adj J / det J.  That adjugate column is the
+            // cross product of rows ci+1 and ci+2 of J (indices mod 3), and
+            // det J = row ci . that column (cyclic), so the thread loads the
+            // three rows in that order from addresses computed from ci.
+            double adjc[3], det;
+            q2_adj_column(Jq + q * 9, ci, adjc, det);
+            // 1/det by the hardware reciprocal refined with two Newton steps
+            // (r <- r + r (1 - det r)), accurate to ~1 ulp
             double rd = __builtin_amdgcn_rcp(det);
             rd = fma(rd, fma(-det, rd, 1.0), rd);
             rd = fma(rd, fma(-det, rd, 1.0), rd);
@@ -868,24 +872,11 @@ __device__ __forceinline__ void q2_run_split(const Q2Job &A, int64_t e, int64_t 
         if (tid < NQ * 9) {
             const int q = tid % NQ, r9 = tid / NQ, ci = r9 / 3, a2 = r9 - 3 * (r9 / 3);
             const int q0 = q % 3, q1 = (q / 3) % 3, q2 = q / 9;
-            double J[3][3];
-#pragma unroll
-            for (int r = 0; r < 3; r++)
-#pragma unroll
-                for (int c = 0; c < 3; c++) J[r][c] = Jq[q * 9 + r * 3 + c];
-            // column ci of the adjugate; 1/det by the hardware reciprocal
-            // refined with two Newton steps (r <- r + r (1 - det r))
-            double adj0[3], adjc[3];
-#pragma unroll
-            for (int j = 0; j < 3; j++) {
-                adj0[j] = J[1][(j + 1) % 3] * J[2][(j + 2) % 3] - J[1][(j + 2) % 3] * J[2][(j + 1) % 3];
-                const double k1 = sel3(ci, J[1][(j + 1) % 3], J[2][(j + 1) % 3], J[0][(j + 1) % 3]);
-                const double k2 = sel3(ci, J[2][(j + 2) % 3], J[0][(j + 2) % 3], J[1][(j + 2) % 3]);
-                const double k3 = sel3(ci, J[1][(j + 2) % 3], J[2][(j + 2) % 3], J[0][(j + 2) % 3]);
-                const double k4 = sel3(ci, J[2][(j + 1) % 3], J[0][(j + 1) % 3], J[1][(j + 1) % 3]);
-                adjc[j] = k1 * k2 - k3 * k4;
-            }
-            const double det = J[0][0] * adj0[0] + J[0][1] * adj0[1] + J[0][2] * adj0[2];
+            // column ci of the adjugate and det J (as in the staged routine);
+            // 1/det by the hardware reciprocal refined with two Newton steps
+            // (r <- r + r (1 - det r))
+            double adjc[3], det;
+            q2_adj_column(Jq + q * 9, ci, adjc, det);
             double rd = __builtin_amdgcn_rcp(det);
             rd = fma(rd, fma(-det, rd, 1.0), rd);
             rd = fma(rd, fma(-det, rd, 1.0), rd);
