@@ -47,11 +47,15 @@ struct Q2Staged {
     // kept for the whole launch: 1-D tables and weights
     static constexpr int OFF_TB = 0;                      // double B1[9], D1[9], w[27]
     // the next cell's coordinates and coefficients, parked before the flush
-    static constexpr int OFF_N = align16(OFF_TB + (9 + 9 + NQ) * 8);  // double xn[81], T lmn[2]
-    static constexpr int OFF_U = align16(OFF_N + 81 * 8 + 2 * 8);
+    // (coordinates component-major: xn[3][28], node a of axis i at 28 i + a)
+    static constexpr int OFF_N = align16(OFF_TB + (9 + 9 + NQ) * 8);  // double xn[3][28], T lmn[2]
+    static constexpr int OFF_U = align16(OFF_N + 3 * 28 * 8 + 2 * 8);
+    // JOUT: J and w det J lie outside the staging area, so a cell's J phase
+    // may start while other waves still flush the previous cell (FP32; the
+    // FP64 layout has no room for it within three workgroups per CU)
+    static constexpr bool JOUT = MM == MM_F32;
     // phase A (per cell): geometry and GEMM operand
-    static constexpr int OFF_X = OFF_U;                   // double xc[3][28] (component-major)
-    static constexpr int OFF_J = OFF_X + 3 * 28 * 8;      // double J[27][9]
+    static constexpr int OFF_J = OFF_U;                   // double J[27][9]
     static constexpr int OFF_WD = OFF_J + NQ * 9 * 8;     // double wd[28]
     // GEMM operand, transposed: row = i*33 + a (component i, basis a; rows
     // a = 27..32 are padding), column = quadrature point k, row stride KS.
@@ -62,9 +66,10 @@ struct Q2Staged {
     static constexpr int GROWS = 3 * 33;
     static constexpr int OFF_G = align16(OFF_WD + 28 * 8);  // T Gs[GROWS][KS]
     static constexpr int END_A = OFF_G + GROWS * KS * (int)sizeof(T);
-    // phase B (aliases A): the cell's matrix row-major, shifted to the output
-    // alignment; it first holds the blocks r <= s of P in their places
-    static constexpr int OFF_K = OFF_U;
+    // phase B (aliases A, or only the operand with JOUT): the cell's matrix
+    // row-major, shifted to the output alignment; it first holds the blocks
+    // r <= s of P in their places
+    static constexpr int OFF_K = JOUT ? OFF_G : OFF_U;
     static constexpr int END_B = OFF_K + (NK + VEC) * (int)sizeof(T);
     static constexpr int BYTES = align16(cmax(END_A, END_B));
     // 16-byte vectors of the staged matrix per thread in the flush
@@ -278,8 +283,7 @@ __device__ __forceinline__ void q2_run_staged(const Q2Job &A, int64_t e, int64_t
     double *D1 = B1 + 9;
     double *wq = D1 + 9;
     double *xn = reinterpret_cast<double *>(smem + L::OFF_N);
-    T *lmn = reinterpret_cast<T *>(xn + 81);
-    double *xc = reinterpret_cast<double *>(smem + L::OFF_X);
+    T *lmn = reinterpret_cast<T *>(xn + 3 * 28);
     double *Jq = reinterpret_cast<double *>(smem + L::OFF_J);
     double *wd = reinterpret_cast<double *>(smem + L::OFF_WD);
     T *Gs = reinterpret_cast<T *>(smem + L::OFF_G);
@@ -307,7 +311,7 @@ __device__ __forceinline__ void q2_run_staged(const Q2Job &A, int64_t e, int64_t
             raise_fault(A.flags, FAULT_INDEX);
             n = 0;
         }
-        xn[tid] = coords[3 * n + gc];
+        xn[gc * 28 + ga] = coords[3 * n + gc];
     }
     if (tid == 0) {
         lmn[0] = mat[2 * e];
@@ -320,18 +324,7 @@ __device__ __forceinline__ void q2_run_staged(const Q2Job &A, int64_t e, int64_t
         const bool has_next = en < e_end;
         const T lam = lmn[0], mu = lmn[1];  // read before the park step rewrites them
 
-        // 1. this cell's coordinates to LDS (component-major); zero the
-        //    operand's depth padding (k = 27) in the real rows.  The padding
-        //    rows a = 27..32 keep what the staging area left there: they
-        //    only reach output rows and columns that are never stored.
-        static_assert(L::KP == NQ + 1, "one padding column");
-        if (tid < NB * 3) {
-            xc[gc * 28 + ga] = xn[tid];
-            Gs[((tid / NB) * 33 + tid % NB) * L::KS + NQ] = T(0);
-        }
-        if (tid == 255) wd[NQ] = 0.0;
-        __syncthreads();
-
+        // 1. (the cell's coordinates were parked component-major in LDS)
         // 2. J[i][j] at quadrature point q, one entry per thread (243
         //    threads), by sum factorization over the tensor-product basis
         if (tid < NQ * 9) {
@@ -342,7 +335,7 @@ __device__ __forceinline__ void q2_run_staged(const Q2Job &A, int64_t e, int64_t
             const double *T2 = (j == 2 ? D1 : B1) + q2 * 3;
             const double f0[3] = {T0[0], T0[1], T0[2]}, f1[3] = {T1[0], T1[1], T1[2]},
                          f2[3] = {T2[0], T2[1], T2[2]};
-            const double *x = xc + i * 28;
+            const double *x = xn + i * 28;
             double s2 = 0.0;
 #pragma unroll
             for (int a2 = 0; a2 < 3; a2++) {
@@ -368,6 +361,15 @@ __device__ __forceinline__ void q2_run_staged(const Q2Job &A, int64_t e, int64_t
         //    coefficients here, its coordinates after the GEMM, parked in LDS
         //    after the epilogue.  Every wait thus falls before this cell's
         //    flush; the previous cell's flush drains during phases 1-4.
+        //
+        //    The operand's depth padding (k = 27) of the real rows is zeroed
+        //    here, after the barrier that follows the previous cell's flush
+        //    reads.  The padding rows a = 27..32 keep what the staging area
+        //    left there: they only reach output rows and columns that are
+        //    never stored.
+        static_assert(L::KP == NQ + 1, "one padding column");
+        if (tid < NB * 3) Gs[((tid / NB) * 33 + tid % NB) * L::KS + NQ] = T(0);
+        if (tid == 255) wd[NQ] = 0.0;
         int32_t nn = 0;
         T lamn = T(0), mun = T(0);
         if (has_next) {
@@ -530,7 +532,7 @@ __device__ __forceinline__ void q2_run_staged(const Q2Job &A, int64_t e, int64_t
         // live across the flush, so nothing after the flush waits for its
         // stores to drain (vector memory counters complete in order)
         if (has_next) {
-            if (tid < NB * 3) xn[tid] = xnext;
+            if (tid < NB * 3) xn[gc * 28 + ga] = xnext;
             if (tid == 0) {
                 lmn[0] = lamn;
                 lmn[1] = mun;
@@ -569,10 +571,14 @@ __device__ __forceinline__ void q2_run_staged(const Q2Job &A, int64_t e, int64_t
                 if (head || tail) out[base + f] = Ks[h + f];
             }
         }
-        __syncthreads();  // the staging area is reused by the next cell
+        // the staging area is reused by the next cell: without JOUT its J
+        // phase writes there; with JOUT the barrier after the J phase orders
+        // the next writes after these reads
+        if constexpr (!L::JOUT) __syncthreads();
         if (!has_next) break;
         e = en;
     }
+    if constexpr (L::JOUT) __syncthreads();  // end synchronised
 }
 // ---------------------------------------------------------------------------
 // Split routine (BF16X3: every operand a sum hi + lo of two bf16 values, the
@@ -609,13 +615,15 @@ struct Q2Split {
     // kept for the whole launch: 1-D tables and weights
     static constexpr int OFF_TB = 0;                                  // double B1[9], D1[9], w[27]
     // the next cell's coordinates and coefficients, parked before the flush
-    static constexpr int OFF_N = align16(OFF_TB + (9 + 9 + NQ) * 8);  // double xn[81], float lmn[2]
-    static constexpr int OFF_S = align16(OFF_N + 81 * 8 + 2 * 4);      // staging
-    // per cell, inside the staging area (written only after the last
-    // operand read): coordinates, J and the operand halves
-    static constexpr int OFF_X = OFF_S;                               // double xc[3][28] (component-major)
-    static constexpr int OFF_J = OFF_X + 3 * 28 * 8;                  // double J[27][9]
-    static constexpr int OFF_OP = align16(OFF_J + NQ * 9 * 8);
+    // (coordinates component-major: xn[3][28], node a of axis i at 28 i + a)
+    static constexpr int OFF_N = align16(OFF_TB + (9 + 9 + NQ) * 8);  // double xn[3][28], float lmn[2]
+    // per cell, outside the staging area, so a cell's J phase may start while
+    // other waves still flush the previous cell
+    static constexpr int OFF_J = align16(OFF_N + 3 * 28 * 8 + 2 * 4);  // double J[27][9]
+    static constexpr int OFF_S = align16(OFF_J + NQ * 9 * 8);          // staging
+    // the operand halves, inside the staging area (written only after the
+    // last operand read)
+    static constexpr int OFF_OP = OFF_S;
     static constexpr int BYTES = align16(OFF_S + STAGE_BYTES);
     // 16-byte vectors of the staged matrix per thread in the flush
     static constexpr int NV = ((NK + 2 * VEC - 1) / VEC + 255) / 256;
@@ -775,8 +783,7 @@ __device__ __forceinline__ void q2_run_split(const Q2Job &A, int64_t e, int64_t 
     double *D1 = B1 + 9;
     double *wq = D1 + 9;
     double *xn = reinterpret_cast<double *>(smem + L::OFF_N);
-    float *lmn = reinterpret_cast<float *>(xn + 81);
-    double *xc = reinterpret_cast<double *>(smem + L::OFF_X);
+    float *lmn = reinterpret_cast<float *>(xn + 3 * 28);
     double *Jq = reinterpret_cast<double *>(smem + L::OFF_J);
     float *Ks = reinterpret_cast<float *>(smem + L::OFF_S);
     unsigned char *op = smem + L::OFF_OP;
@@ -804,7 +811,7 @@ __device__ __forceinline__ void q2_run_split(const Q2Job &A, int64_t e, int64_t 
             raise_fault(A.flags, FAULT_INDEX);
             n = 0;
         }
-        xn[tid] = coords[3 * n + gc];
+        xn[gc * 28 + ga] = coords[3 * n + gc];
     }
     if (tid == 0) {
         lmn[0] = mat[2 * e];
@@ -817,16 +824,7 @@ __device__ __forceinline__ void q2_run_split(const Q2Job &A, int64_t e, int64_t 
         const bool has_next = en < e_end;
         const float lam = lmn[0], mu = lmn[1];  // read before the park step rewrites them
 
-        // 1. this cell's coordinates to LDS (component-major); the operand's
-        //    depth padding (the staging area of the last cell covered it)
-        if (tid < NB * 3) xc[gc * 28 + ga] = xn[tid];
-        if (tid < 2 * ND) {
-            __bf16 *p = ohi + (tid >= ND ? L::OROWS * L::KS : 0) + (tid >= ND ? tid - ND : tid) * L::KS;
-#pragma unroll
-            for (int k = NQ; k < L::KP; k++) p[k] = static_cast<__bf16>(0.0f);
-        }
-        __syncthreads();
-
+        // 1. (the cell's coordinates were parked component-major in LDS)
         // 2. J[i][j] at quadrature point q, one entry per thread (243
         //    threads), by sum factorization over the tensor-product basis
         if (tid < NQ * 9) {
@@ -837,7 +835,7 @@ __device__ __forceinline__ void q2_run_split(const Q2Job &A, int64_t e, int64_t 
             const double *T2 = (j == 2 ? D1 : B1) + q2 * 3;
             const double f0[3] = {T0[0], T0[1], T0[2]}, f1[3] = {T1[0], T1[1], T1[2]},
                          f2[3] = {T2[0], T2[1], T2[2]};
-            const double *x = xc + i * 28;
+            const double *x = xn + i * 28;
             double s2 = 0.0;
 #pragma unroll
             for (int a2 = 0; a2 < 3; a2++) {
@@ -859,7 +857,14 @@ __device__ __forceinline__ void q2_run_split(const Q2Job &A, int64_t e, int64_t 
         //    (= sqrt(w_q det J) G[q][i][a]), one (q, i, a2) triple per
         //    thread, 9 basis functions each.  The next cell's connectivity
         //    and coefficients are prefetched here, its coordinates after the
-        //    GEMM; both are parked in LDS before the flush.
+        //    GEMM; both are parked in LDS before the flush.  The operand's
+        //    depth padding is zeroed here, after the barrier that follows the
+        //    previous cell's flush reads of the staging area.
+        if (tid < 2 * ND) {
+            __bf16 *p = ohi + (tid >= ND ? L::OROWS * L::KS : 0) + (tid >= ND ? tid - ND : tid) * L::KS;
+#pragma unroll
+            for (int k = NQ; k < L::KP; k++) p[k] = static_cast<__bf16>(0.0f);
+        }
         int32_t nn = 0;
         float lamn = 0.0f, mun = 0.0f;
         if (has_next) {
@@ -946,7 +951,7 @@ __device__ __forceinline__ void q2_run_split(const Q2Job &A, int64_t e, int64_t 
         // live across the flush, so nothing after the flush waits for its
         // stores to drain (vector memory counters complete in order)
         if (has_next) {
-            if (tid < NB * 3) xn[tid] = xnext;
+            if (tid < NB * 3) xn[gc * 28 + ga] = xnext;
             if (tid == 0) {
                 lmn[0] = lamn;
                 lmn[1] = mun;
@@ -996,10 +1001,13 @@ __device__ __forceinline__ void q2_run_split(const Q2Job &A, int64_t e, int64_t 
                 if (head || tail) out[base + f] = Ks[f + f / 27];
             }
         }
-        __syncthreads();  // the staging area is reused by the next cell
+        // no barrier: the next cell's J phase writes outside the staging
+        // area, and the barrier after it orders the next writes there after
+        // these reads
         if (!has_next) break;
         e = en;
     }
+    __syncthreads();  // end synchronised
 }
 
 template <int MM>
