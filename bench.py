@@ -61,10 +61,10 @@ MEASURED_TRAFFIC = {
     "k_elast_q2<0>": dict(bytes=5983546000, sha256="6ef548f20797550a",
                           sources=["k_mfma.hip", "q2_device.h",
                                    "fe_device.h"]),
-    "k_elast_q3ws<0>": dict(bytes=9696681998, sha256="b52fff172fb4a023",
+    "k_elast_q3ws<0>": dict(bytes=9696687281, sha256="e72b02810c95e020",
                             sources=["k_hexmm.hip", "mm_device.h",
                                      "q2_device.h", "fe_device.h"]),
-    "k_hexmc<5,3,0>": dict(bytes=3529668865, sha256="b52fff172fb4a023",
+    "k_hexmc<5,3,0>": dict(bytes=3534367966, sha256="e72b02810c95e020",
                            sources=["k_hexmm.hip", "mm_device.h",
                                     "q2_device.h", "fe_device.h"]),
     "k_cw_scalar<hex,1,laplace,double>@128^3": dict(
@@ -77,7 +77,7 @@ MEASURED_TRAFFIC = {
         bytes=2797008333, sha256="da3868d0322718fc",
         sources=["k_batch.hip", "q2_device.h", "fe_device.h"]),
     "k_hexgm<2,convect,fp64>@32^3": dict(
-        bytes=1777412415, sha256="a8930954dabea877",
+        bytes=1777911343, sha256="6f59da7c0f2b2c14",
         sources=["k_hexgm.hip", "mm_device.h", "q2_device.h",
                  "fe_device.h"]),
 }
