@@ -461,10 +461,22 @@ class ElasticEnergyPlan:
         gradient or of the residual saw det J <= 0 or an out-of-range node
         number since the last check.  Every workspace is read and cleared
         before the first fault found is raised."""
-        first = None
-        checks = [(self.eval, None), (self.resid, None)]
+        import torch
+        checks = [(self.eval, self.eval._ws), (self.resid, self.resid._ws)]
         if self._gws is not None:
             checks.append((self.eval, self._gws))
+        checks = [(plan, ws) for plan, ws in checks if ws is not None]
+        if not checks:
+            return
+        # one device-to-host read of every fault word (the first four bytes
+        # of each workspace) on the stream the kernels ran on; the library's
+        # check, which names the fault and clears the bits, runs only when
+        # one of them is set
+        with torch.cuda.stream(stream):  # a no-op for None (the current stream)
+            words = torch.cat([ws[:4] for _, ws in checks]).cpu()
+        if not bool(words.any()):
+            return
+        first = None
         for plan, ws in checks:
             try:
                 plan.check(ws, stream)
