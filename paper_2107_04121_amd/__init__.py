@@ -518,10 +518,11 @@ def _make_energy_function():
             if need_u:
                 r = ep.resid(x, ep.conn, material=c, dofs=u)
                 gu = assemble(ep.inc, r, scale=2.0)
-            ep.check()
             for g in (gc, gx, gu):
                 if g is not None:
                     g.mul_(gJ)
+            # the one synchronisation, after every launch of the pass
+            ep.check()
             return gc, gx, gu, None
 
     return _ElasticEnergy
