@@ -168,6 +168,34 @@ def test_autograd_energy_faults_and_repeats(orc):
         assert _rel(ct.grad.cpu().numpy(), orc.energy_grad(mesh, c, U)[0]) < TOL["fp64"]
 
 
+def test_energy_check_reads_every_workspace():
+    """ElasticEnergyPlan.check reads the fault words of the energy, residual
+    and gradient workspaces in one copy: a bit set (from the host) in any
+    one of them alone is reported with its status and cleared."""
+    import torch
+    import paper_2107_04121_amd as fe
+    mesh = meshgen.hex_mesh((2, 2, 1), 2, alpha=0.1, seed=75)
+    c = meshgen.lame_qp(mesh.n_cells, 27, seed=35)
+    U = meshgen.dofs(mesh.n_nodes, 3, seed=36)
+    ep = fe.ElasticEnergyPlan("hex", 2, _t(mesh.conn), mesh.n_nodes, "fp64")
+    ct = _t(c).requires_grad_(True)
+    xt = _t(mesh.coords).requires_grad_(True)
+    ut = _t(U).requires_grad_(True)
+    fe.ElasticEnergy(ct, xt, ut, ep).backward()  # every workspace exists, no fault
+    ep.check()
+    spaces = (ep.eval._ws, ep.resid._ws, ep._gws)
+    assert all(ws is not None for ws in spaces)
+    for i in range(3):
+        for bit, status in ((1, 3), (2, 4)):  # det J <= 0, node out of range
+            print(f"[check] workspace {i} bit {bit}", flush=True)
+            spaces[i][:4].copy_(torch.tensor([bit, 0, 0, 0], dtype=torch.uint8))
+            with pytest.raises(fe.FeError) as ei:
+                ep.check()
+            assert ei.value.status == status
+            ep.check()  # cleared
+            assert all(int(ws[:4].sum()) == 0 for ws in spaces)
+
+
 def test_gpu_gradient_central_differences(orc):
     """FP64 central differences (h = 1e-6) of the GPU forward along seeded
     directions agree with the GPU adjoint."""
